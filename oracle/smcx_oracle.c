@@ -1,0 +1,425 @@
+/*
+ * smcx_oracle.c -- plain sequential CPU oracle (TEST INFRASTRUCTURE ONLY).
+ *
+ * Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+ * load this code.  It shares nothing with the HIP library: no headers, no
+ * tables, no helpers.  Every function is written for readability, not speed.
+ *
+ * Paper: arXiv:2509.20949 (SMC-X).  Citations name the section and equation.
+ *
+ * ---------------------------------------------------------------------------
+ * Geometry (reading; the paper's production lattice is FCC, this path is BCC)
+ *   Cells (x, y, z), 0 <= x < Lx etc., two sites per cell: b = 0 at the cube
+ *   corner, b = 1 at the body centre.  In "doubled" coordinates (units of half
+ *   the lattice constant) a site sits at X = 2x + b, Y = 2y + b, Z = 2z + b.
+ *   Boundaries are periodic on every axis (the paper simulates supercells;
+ *   it states no boundary condition).
+ *   Site id i = ((z*Ly + y)*Lx + x)*2 + b.
+ *
+ * Neighbour shells in doubled coordinates:
+ *   shell 1 (8):  (+-1, +-1, +-1)        first neighbours, other sublattice
+ *   shell 2 (6):  (+-2, 0, 0) and perms   second neighbours, same sublattice
+ *   shell 3 (12): (+-2, +-2, 0) and perms third neighbours, same sublattice
+ *   Shell-1 vector number `dir` (0..7) has component +1 on axis a when bit a
+ *   of dir is set, -1 otherwise.
+ *
+ * Energy (reading of the EPI model, Section "Results and discussion": pair
+ * interactions only):  E = 1/2 sum_i sum_{delta in shells 1..S}
+ *   V_{shell(delta)}(sigma_i, sigma_{i+delta}),  V symmetric int32 micro-eV.
+ *   A bond whose periodic images coincide (L = 2) is counted once per
+ *   displacement vector.
+ * ---------------------------------------------------------------------------
+ */
+#include "smcx_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Philox (Salmon et al., SC'11, "Parallel random numbers: as easy as 1, 2,  */
+/* 3").  State: four counter words and two key words.  One round multiplies */
+/* words 0 and 2 by two fixed odd constants, keeping both halves of each     */
+/* double-width product; the new words are                                   */
+/*   (hi(M1*x2) ^ x1 ^ k0,  lo(M1*x2),  hi(M0*x0) ^ x3 ^ k1,  lo(M0*x0)).    */
+/* Between rounds the key is bumped by two Weyl constants.  Ten rounds.      */
+/* ------------------------------------------------------------------------ */
+/* Both widths are generated from one body, so that the 64-bit instance,
+ * which numpy.random.Philox also implements, pins the round structure shared
+ * with the 32-bit instance used for the trials. */
+static void mulhilo32(uint32_t a, uint32_t b, uint32_t* hi, uint32_t* lo)
+{
+    uint64_t p = (uint64_t)a * b;
+    *hi = (uint32_t)(p >> 32);
+    *lo = (uint32_t)p;
+}
+
+static void mulhilo64(uint64_t a, uint64_t b, uint64_t* hi, uint64_t* lo)
+{
+    /* schoolbook 64x64 -> 128 from 32-bit halves */
+    uint64_t a0 = a & 0xffffffffu, a1 = a >> 32;
+    uint64_t b0 = b & 0xffffffffu, b1 = b >> 32;
+    uint64_t p00 = a0 * b0, p01 = a0 * b1, p10 = a1 * b0, p11 = a1 * b1;
+    uint64_t mid = (p00 >> 32) + (p01 & 0xffffffffu) + (p10 & 0xffffffffu);
+    *lo = (p00 & 0xffffffffu) | (mid << 32);
+    *hi = p11 + (p01 >> 32) + (p10 >> 32) + (mid >> 32);
+}
+
+#define DEFINE_PHILOX4(NAME, WORD, MULHILO, M0, M1, W0, W1)                 \
+    void NAME(const WORD ctr[4], const WORD key[2], WORD out[4])            \
+    {                                                                       \
+        WORD x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];            \
+        WORD k0 = key[0], k1 = key[1];                                      \
+        for (int r = 0; r < 10; ++r) {                                      \
+            if (r > 0) { k0 += (W0); k1 += (W1); }                          \
+            WORD hi0, lo0, hi1, lo1;                                        \
+            MULHILO((M0), x0, &hi0, &lo0);                                  \
+            MULHILO((M1), x2, &hi1, &lo1);                                  \
+            WORD n0 = hi1 ^ x1 ^ k0;                                        \
+            WORD n1 = lo1;                                                  \
+            WORD n2 = hi0 ^ x3 ^ k1;                                        \
+            WORD n3 = lo0;                                                  \
+            x0 = n0; x1 = n1; x2 = n2; x3 = n3;                             \
+        }                                                                   \
+        out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;                 \
+    }
+
+/* constants of the SC'11 paper: multipliers, then Weyl key increments
+ * (golden ratio and sqrt(3) - 1 in fixed point) */
+DEFINE_PHILOX4(or_philox4x32_10, uint32_t, mulhilo32,
+               0xD2511F53u, 0xCD9E8D57u, 0x9E3779B9u, 0xBB67AE85u)
+DEFINE_PHILOX4(or_philox4x64_10, uint64_t, mulhilo64,
+               0xD2E7470EE14C6C93ull, 0xCA5A826395121157ull,
+               0x9E3779B97F4A7C15ull, 0xBB67AE8584CAA73Bull)
+
+/* ------------------------------------------------------------------------ */
+/* Metropolis acceptance, Eq. (3): accept with probability 1 if dE <= 0,    */
+/* exp(-beta dE) otherwise.  Reading for exact reproducibility: a uniform   */
+/* 32-bit draw u is accepted iff (double)u < 2^32 exp(-beta dE), where the  */
+/* right-hand side is assembled from three 256-entry FP64 tables indexed by */
+/* the bytes of dE, multiplied in a fixed order.  dE >= 2^24 is rejected    */
+/* (for T <= 5000 K its probability is below 2^-32).                        */
+/* ------------------------------------------------------------------------ */
+void or_thresholds(double T, double tab[768])
+{
+    const double kB_ueV_per_K = 86.17333262; /* CODATA 2018, micro-eV / K */
+    double beta = 1.0 / (kB_ueV_per_K * T);
+    for (int l = 0; l < 256; ++l) {
+        tab[l] = exp(-((double)l * beta));
+        tab[256 + l] = exp(-((double)(l * 256) * beta));
+        tab[512 + l] = ldexp(exp(-((double)(l * 65536) * beta)), 32);
+    }
+}
+
+int or_accept(int64_t dE, uint32_t u, const double tab[768])
+{
+    if (dE <= 0) return 1;
+    if (dE >= (1 << 24)) return 0;
+    double thr = (tab[512 + (dE >> 16)] * tab[256 + ((dE >> 8) & 255)]) * tab[dE & 255];
+    return (double)u < thr;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Geometry                                                                  */
+/* ------------------------------------------------------------------------ */
+static const int SHELL1[8][3] = {
+    {-1, -1, -1}, {+1, -1, -1}, {-1, +1, -1}, {+1, +1, -1},
+    {-1, -1, +1}, {+1, -1, +1}, {-1, +1, +1}, {+1, +1, +1}};
+static const int SHELL2[6][3] = {
+    {+2, 0, 0}, {-2, 0, 0}, {0, +2, 0}, {0, -2, 0}, {0, 0, +2}, {0, 0, -2}};
+static const int SHELL3[12][3] = {
+    {+2, +2, 0}, {+2, -2, 0}, {-2, +2, 0}, {-2, -2, 0},
+    {+2, 0, +2}, {+2, 0, -2}, {-2, 0, +2}, {-2, 0, -2},
+    {0, +2, +2}, {0, +2, -2}, {0, -2, +2}, {0, -2, -2}};
+
+int or_shell_size(int s) { return s == 0 ? 8 : (s == 1 ? 6 : 12); }
+
+/* displacement k of the concatenated list shell1 ++ shell2 ++ shell3 */
+static const int* displacement(int k, int* shell)
+{
+    if (k < 8) { *shell = 0; return SHELL1[k]; }
+    if (k < 14) { *shell = 1; return SHELL2[k - 8]; }
+    *shell = 2;
+    return SHELL3[k - 14];
+}
+
+static int64_t wrap(int64_t v, int64_t m) { v %= m; return v < 0 ? v + m : v; }
+
+int64_t or_neighbour(const int32_t L[3], int64_t i, int k)
+{
+    int shell;
+    const int* d = displacement(k, &shell);
+    int64_t b = i & 1, cell = i >> 1;
+    int64_t x = cell % L[0], y = (cell / L[0]) % L[1], z = cell / ((int64_t)L[0] * L[1]);
+    int64_t X = wrap(2 * x + b + d[0], 2 * (int64_t)L[0]);
+    int64_t Y = wrap(2 * y + b + d[1], 2 * (int64_t)L[1]);
+    int64_t Z = wrap(2 * z + b + d[2], 2 * (int64_t)L[2]);
+    int64_t nb = X & 1; /* equal parities on all axes */
+    return ((((Z >> 1) * L[1] + (Y >> 1)) * L[0] + (X >> 1)) << 1) | nb;
+}
+
+static int n_displacements(int S)
+{
+    int n = 0;
+    for (int s = 0; s < S; ++s) n += or_shell_size(s);
+    return n;
+}
+
+static int64_t n_sites(const int32_t L[3]) { return 2 * (int64_t)L[0] * L[1] * L[2]; }
+
+/* ------------------------------------------------------------------------ */
+/* Energy, energy change, pair counts, SRO                                   */
+/* ------------------------------------------------------------------------ */
+int64_t or_energy(const int32_t L[3], int S, int K, const int32_t* epi, const uint8_t* sigma)
+{
+    int64_t N = n_sites(L), twiceE = 0;
+    int nd = n_displacements(S);
+    for (int64_t i = 0; i < N; ++i)
+        for (int k = 0; k < nd; ++k) {
+            int s;
+            displacement(k, &s);
+            int64_t n = or_neighbour(L, i, k);
+            twiceE += epi[(s * K + sigma[i]) * K + sigma[n]];
+        }
+    return twiceE / 2;
+}
+
+/* Energy change of exchanging the species of sites i and j (j a first
+ * neighbour of i).  Only bonds touching i or j change; the bond i-j itself
+ * is unchanged because V is symmetric:
+ *   dE = sum_{delta, i+delta != j} [V(sj, s_{i+delta}) - V(si, s_{i+delta})]
+ *      + sum_{delta, j+delta != i} [V(si, s_{j+delta}) - V(sj, s_{j+delta})]  */
+int64_t or_delta_energy(const int32_t L[3], int S, int K, const int32_t* epi,
+                        const uint8_t* sigma, int64_t i, int64_t j)
+{
+    int nd = n_displacements(S);
+    int si = sigma[i], sj = sigma[j];
+    int64_t dE = 0;
+    for (int k = 0; k < nd; ++k) {
+        int s;
+        displacement(k, &s);
+        int64_t n = or_neighbour(L, i, k);
+        if (n != j) dE += epi[(s * K + sj) * K + sigma[n]] - epi[(s * K + si) * K + sigma[n]];
+        int64_t m = or_neighbour(L, j, k);
+        if (m != i) dE += epi[(s * K + si) * K + sigma[m]] - epi[(s * K + sj) * K + sigma[m]];
+    }
+    return dE;
+}
+
+/* counts[m][p'][p] = number of (centre i of species p', displacement of
+ * shell m, neighbour of species p). */
+void or_pair_counts(const int32_t L[3], int S, int K, const uint8_t* sigma, uint64_t* counts)
+{
+    int64_t N = n_sites(L);
+    int nd = n_displacements(S);
+    memset(counts, 0, sizeof(uint64_t) * S * K * K);
+    for (int64_t i = 0; i < N; ++i)
+        for (int k = 0; k < nd; ++k) {
+            int s;
+            displacement(k, &s);
+            int64_t n = or_neighbour(L, i, k);
+            counts[(s * K + sigma[i]) * K + sigma[n]] += 1;
+        }
+}
+
+/* Warren-Cowley SRO, Eq. (SRO): alpha_m^{pp'} = 1 - P_m^{p|p'} / c_p with
+ * P_m^{p|p'} = counts[m][p'][p] / (Z_m N_{p'}), c_p = N_p / N.  Stored at
+ * alpha[(m*K + p')*K + p].  NaN when N_p or N_{p'} is zero (reading). */
+void or_sro(const int32_t L[3], int S, int K, const uint8_t* sigma, double* alpha, uint64_t* counts)
+{
+    int64_t N = n_sites(L);
+    uint64_t* c = counts ? counts : (uint64_t*)malloc(sizeof(uint64_t) * S * K * K);
+    or_pair_counts(L, S, K, sigma, c);
+    int64_t Np[256] = {0};
+    for (int64_t i = 0; i < N; ++i) Np[sigma[i]] += 1;
+    for (int m = 0; m < S; ++m)
+        for (int pc = 0; pc < K; ++pc)
+            for (int p = 0; p < K; ++p) {
+                double P = (double)c[(m * K + pc) * K + p] / ((double)or_shell_size(m) * (double)Np[pc]);
+                double cp = (double)Np[p] / (double)N;
+                alpha[(m * K + pc) * K + p] = (Np[p] == 0 || Np[pc] == 0) ? NAN : 1.0 - P / cp;
+            }
+    if (!counts) free(c);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Schedule of one sweep (reading of the dynamical link cells, Section      */
+/* "Distributed SMC-X": every site is visited exactly once per step, and     */
+/* sites updated together are separated by more than the interaction range).*/
+/*                                                                           */
+/* Per axis with L cells and block-width parameter B:                        */
+/*   n = 1 if L < 4, else n = max(2, min(2*ceil(L/(2B)), 2*floor(L/4)))      */
+/*   (even, every block at least 2 and at most max(B, 4) cells wide),        */
+/*   bounds b_k = floor(k*L/n).                                              */
+/* Sweep s draws an origin shift o_a = (r_a * L_a) >> 32 from                */
+/*   Philox4x32-10(key = seed, counter = (0, 0, s, 8)).                      */
+/* Cell coordinate x_a maps to u_a = (x_a - o_a) mod L_a, block k_a with     */
+/* b_k <= u_a < b_{k+1}, local coordinate l_a = u_a - b_k.                   */
+/* Colour c = (k_x & 1) | (k_y & 1) << 1 | (k_z & 1) << 2, phases c = 0..7.  */
+/* Sub-colour q = (((l_z%3)*3 + l_y%3)*3 + l_x%3)*2 + b, rounds q = 0..53.   */
+/* Trials run colour by colour, sub-colour by sub-colour, and inside one     */
+/* (c, q) set in ascending site id (the trials of one set commute).          */
+/* ------------------------------------------------------------------------ */
+int or_axis_blocks(int L, int B)
+{
+    if (L < 4) return 1;
+    int n = 2 * ((L + 2 * B - 1) / (2 * B));
+    int cap = 2 * (L / 4);
+    if (n > cap) n = cap;
+    if (n < 2) n = 2;
+    return n;
+}
+
+void or_axis_bounds(int L, int B, int32_t* bounds)
+{
+    int n = or_axis_blocks(L, B);
+    for (int k = 0; k <= n; ++k) bounds[k] = (int32_t)(((int64_t)k * L) / n);
+}
+
+void or_sweep_shift(const int32_t L[3], uint64_t seed, uint32_t s, int32_t shift[3])
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t ctr[4] = {0u, 0u, s, 8u};
+    uint32_t r[4];
+    or_philox4x32_10(ctr, key, r);
+    for (int a = 0; a < 3; ++a) shift[a] = (int32_t)(((uint64_t)r[a] * (uint64_t)L[a]) >> 32);
+}
+
+void or_schedule(const int32_t L[3], const int32_t B[3], uint64_t seed, uint32_t s,
+                 uint8_t* colour, uint8_t* subcolour, int64_t* block)
+{
+    int32_t shift[3];
+    or_sweep_shift(L, seed, s, shift);
+    int n[3];
+    int32_t* bounds[3];
+    for (int a = 0; a < 3; ++a) {
+        n[a] = or_axis_blocks(L[a], B[a]);
+        bounds[a] = (int32_t*)malloc(sizeof(int32_t) * (n[a] + 1));
+        or_axis_bounds(L[a], B[a], bounds[a]);
+    }
+    int64_t N = n_sites(L);
+    for (int64_t i = 0; i < N; ++i) {
+        int64_t cell = i >> 1;
+        int b = (int)(i & 1);
+        int64_t xyz[3] = {cell % L[0], (cell / L[0]) % L[1], cell / ((int64_t)L[0] * L[1])};
+        int k[3], l[3];
+        for (int a = 0; a < 3; ++a) {
+            int64_t u = wrap(xyz[a] - shift[a], L[a]);
+            int kk = 0;
+            while (!(bounds[a][kk] <= u && u < bounds[a][kk + 1])) ++kk;
+            k[a] = kk;
+            l[a] = (int)(u - bounds[a][kk]);
+        }
+        colour[i] = (uint8_t)((k[0] & 1) | ((k[1] & 1) << 1) | ((k[2] & 1) << 2));
+        subcolour[i] = (uint8_t)((((l[2] % 3) * 3 + l[1] % 3) * 3 + l[0] % 3) * 2 + b);
+        if (block) block[i] = ((int64_t)k[2] * n[1] + k[1]) * n[0] + k[0];
+    }
+    for (int a = 0; a < 3; ++a) free(bounds[a]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sweeps                                                                    */
+/* ------------------------------------------------------------------------ */
+static int valid_inputs(const int32_t L[3], const int32_t B[3], int S, int K, const int32_t* epi)
+{
+    if (S < 1 || S > 3 || K < 1 || K > 255) return 0;
+    for (int a = 0; a < 3; ++a)
+        if (L[a] < 2 || B[a] < 2) return 0;
+    for (int s = 0; s < S; ++s)
+        for (int p = 0; p < K; ++p)
+            for (int q = 0; q < K; ++q)
+                if (epi[(s * K + p) * K + q] != epi[(s * K + q) * K + p]) return 0;
+    return 1;
+}
+
+int or_sweep(const int32_t L[3], const int32_t B[3], int S, int K, const int32_t* epi,
+             uint64_t seed, uint32_t s0, int32_t n, const double* T, uint8_t* sigma,
+             int64_t* E, uint64_t* accepted, int64_t* E_trace, uint64_t* counts_trace)
+{
+    if (!valid_inputs(L, B, S, K, epi) || n < 0) return -1;
+    int64_t N = n_sites(L);
+    for (int64_t i = 0; i < N; ++i)
+        if (sigma[i] >= K) return -1;
+    uint8_t* colour = (uint8_t*)malloc(N);
+    uint8_t* sub = (uint8_t*)malloc(N);
+    int64_t* order = (int64_t*)malloc(sizeof(int64_t) * N);
+    int64_t start[8 * 54 + 1];
+    double tab[768];
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+
+    for (int32_t t = 0; t < n; ++t) {
+        uint32_t s = s0 + (uint32_t)t;
+        or_thresholds(T[t], tab);
+        or_schedule(L, B, seed, s, colour, sub, NULL);
+        /* order: counting sort on (colour, sub-colour), stable in site id */
+        memset(start, 0, sizeof(start));
+        for (int64_t i = 0; i < N; ++i) start[colour[i] * 54 + sub[i] + 1] += 1;
+        for (int g = 0; g < 8 * 54; ++g) start[g + 1] += start[g];
+        for (int64_t i = 0; i < N; ++i) order[start[colour[i] * 54 + sub[i]]++] = i;
+
+        for (int64_t r = 0; r < N; ++r) {
+            int64_t i = order[r];
+            int64_t cell = i >> 1;
+            int b = (int)(i & 1);
+            uint32_t ctr[4] = {(uint32_t)cell, (uint32_t)(cell >> 32), s, colour[i]};
+            uint32_t rnd[4];
+            or_philox4x32_10(ctr, key, rnd);
+            uint32_t u_dir = rnd[2 * b], u_acc = rnd[2 * b + 1];
+            int dir = (int)(u_dir >> 29);
+            int64_t j = or_neighbour(L, i, dir);
+            if (sigma[i] == sigma[j]) continue;
+            int64_t dE = or_delta_energy(L, S, K, epi, sigma, i, j);
+            if (or_accept(dE, u_acc, tab)) {
+                uint8_t tmp = sigma[i];
+                sigma[i] = sigma[j];
+                sigma[j] = tmp;
+                *E += dE;
+                *accepted += 1;
+            }
+        }
+        if (E_trace) E_trace[t] = *E;
+        if (counts_trace) or_pair_counts(L, S, K, sigma, counts_trace + (size_t)t * S * K * K);
+    }
+    free(colour);
+    free(sub);
+    free(order);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exact enumeration (Eq. (1) evaluated by brute force on tiny cells).       */
+/* Visits every arrangement of the multiset given by comp[] in lexicographic */
+/* order (next permutation of a sorted sequence).                            */
+/* ------------------------------------------------------------------------ */
+static int next_multiset_permutation(uint8_t* a, int64_t n)
+{
+    int64_t k = n - 2;
+    while (k >= 0 && a[k] >= a[k + 1]) --k;
+    if (k < 0) return 0;
+    int64_t l = n - 1;
+    while (a[l] <= a[k]) --l;
+    uint8_t t = a[k]; a[k] = a[l]; a[l] = t;
+    for (int64_t p = k + 1, q = n - 1; p < q; ++p, --q) { t = a[p]; a[p] = a[q]; a[q] = t; }
+    return 1;
+}
+
+int64_t or_enumerate(const int32_t L[3], int S, int K, const int32_t* epi,
+                     const int32_t* comp, int64_t max_cfg, int64_t* E_all, uint64_t* counts_all)
+{
+    int64_t N = n_sites(L), tot = 0;
+    for (int p = 0; p < K; ++p) tot += comp[p];
+    if (tot != N) return -1;
+    uint8_t* a = (uint8_t*)malloc(N);
+    int64_t pos = 0;
+    for (int p = 0; p < K; ++p)
+        for (int32_t c = 0; c < comp[p]; ++c) a[pos++] = (uint8_t)p;
+    int64_t cfg = 0;
+    do {
+        if (cfg >= max_cfg) { free(a); return -1; }
+        if (E_all) E_all[cfg] = or_energy(L, S, K, epi, a);
+        if (counts_all) or_pair_counts(L, S, K, a, counts_all + (size_t)cfg * S * K * K);
+        ++cfg;
+    } while (next_multiset_permutation(a, N));
+    free(a);
+    return cfg;
+}
