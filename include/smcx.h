@@ -1,0 +1,235 @@
+/*
+ * smcx.h -- C ABI of libsmcx: canonical-ensemble Metropolis swap sweeps on a
+ * multicomponent BCC lattice with an effective-pair-interaction (EPI)
+ * energy, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Liu, Yang, Zhou, Xu, "SMC-X: A Distributed Scalable Monte Carlo
+ * Simulation Method for Chemically Complex Alloys", arXiv:2509.20949.
+ *   - canonical (NVT) target distribution: Section "Monte Carlo
+ *     simulation", Eq. (1); observables as ensemble averages, Eq. (2);
+ *   - Metropolis acceptance min(1, exp(-beta dE)): Eq. (3);
+ *   - one sweep (MC step) = one trial per lattice site: text after Eq. (3);
+ *   - link cells visited so that every site is tried once per step and
+ *     concurrently updated sites do not interact: Section "Distributed
+ *     SMC-X", equation for P_LC;
+ *   - EPI model (pair interactions only): Section "Results and discussion";
+ *   - Warren-Cowley SRO: Section "Evolution of chemical defects",
+ *     Eq. (SRO);
+ *   - independent temperatures run side by side (temperature
+ *     parallelism) and replica exchange: Section "Distributed SMC-X",
+ *     equations for P_swap and Delta.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Lattice.  Cells (x, y, z), 0 <= x < L[0] etc., periodic on every axis,
+ *   two sites per cell: b = 0 at the cube corner, b = 1 at the body centre.
+ *   Canonical site id i = ((z*L[1] + y)*L[0] + x)*2 + b.  Species arrays
+ *   hold one uint8 per site in canonical order, values 0..K-1.
+ * Energy.  E = 1/2 sum_i sum_{delta in shells 1..S} V_s(sigma_i,
+ *   sigma_{i+delta}); shell 1 = 8 first neighbours (+-a/2, +-a/2, +-a/2),
+ *   shell 2 = 6 at (+-a, 0, 0), shell 3 = 12 at (+-a, +-a, 0).  The EPI table
+ *   is int32 micro-eV, layout epi[s][p][q] (S*K*K entries), symmetric in
+ *   (p, q), |V| < 2^22.  Energies are exact int64 micro-eV.
+ * Trial.  Sweep s, colour phase c: site i draws Philox4x32-10 with key =
+ *   (seed & 0xffffffff, seed >> 32) and counter = (cell & 0xffffffff,
+ *   cell >> 32, s, c); a corner site uses output words 0 and 1, a body
+ *   site words 2 and 3.  The first word's top 3 bits pick the partner
+ *   among the 8 first neighbours (bit a set = +a/2 along axis a); the
+ *   second word u accepts an uphill swap iff dE < 2^24 and
+ *   (double)u < (T2[dE>>16] * T1[(dE>>8)&255]) * T0[dE&255], with
+ *   beta = 1 / (86.17333262 * T) per micro-eV and
+ *   T0[l] = exp(-l beta), T1[m] = exp(-256 m beta),
+ *   T2[h] = 2^32 exp(-65536 h beta), built in FP64 on the host.
+ *   dE <= 0 always accepts.  Swaps of equal species are no-ops.
+ * Schedule.  Per axis n = max(2, min(2*ceil(L/(2B)), 2*floor(L/4))) blocks
+ *   with bounds floor(k L / n); sweep s shifts the block grid by
+ *   o_a = (r_a * L_a) >> 32 with r = Philox4x32-10(key, (0, 0, s, 8)).
+ *   A site's colour is the parity pattern of its block indices, its
+ *   sub-colour (((l_z%3)*3 + l_y%3)*3 + l_x%3)*2 + b from its local cell
+ *   coordinates; phases run c = 0..7, rounds q = 0..53.  Trials of one
+ *   (c, q) set never interact, nor do blocks of one colour, so the result is
+ *   that of the sequential order (c, q, site id) bit for bit.
+ *
+ * Memory and threads.  Every call that takes host pointers copies what it
+ *   needs; the caller keeps ownership.  smcx_create_device borrows a device
+ *   buffer that must outlive the context.  smcx_sweep and smcx_batch_run
+ *   only enqueue work on the context's HIP stream; every query synchronises
+ *   that stream.  One context must not be used from two threads at once;
+ *   distinct contexts may.  No C++ exception crosses this interface.
+ * Errors.  Every status-returning call returns SMCX_OK or a negative code;
+ *   smcx_last_error(ctx) (or smcx_global_error() where no context exists)
+ *   returns a message for the last failing call on that thread/context.
+ */
+#ifndef SMCX_H
+#define SMCX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct smcx_ctx smcx_ctx;
+typedef struct smcx_batch smcx_batch;
+typedef struct smcx_server smcx_server;
+
+typedef enum {
+    SMCX_OK = 0,
+    SMCX_E_INVALID = -1,      /* bad pointer, size, species >= K, asymmetric EPI */
+    SMCX_E_UNSUPPORTED = -2,  /* valid for the method, not for this library (L < 4, B > 12, K > 8, S > 3) */
+    SMCX_E_NOMEM = -3,        /* device or host allocation failed, or over budget */
+    SMCX_E_DEVICE = -4,       /* a HIP runtime call failed */
+    SMCX_E_RANGE = -5,        /* |V| >= 2^22, T outside [1, 5000] K, sweep counter overflow */
+    SMCX_E_STATE = -6         /* call not valid in the object's current state */
+} smcx_status;
+
+enum { SMCX_LATTICE_BCC = 0 };
+enum { SMCX_MAX_SPECIES = 8, SMCX_MAX_SHELLS = 3, SMCX_MAX_BLOCK = 12 };
+
+typedef struct {
+    int32_t lattice;    /* SMCX_LATTICE_BCC */
+    int32_t L[3];       /* cells per axis, each >= 4 */
+    int32_t n_species;  /* K, 2..8 */
+    int32_t n_shells;   /* S, 1..3 */
+    int32_t block[3];   /* schedule block-width parameter B per axis, 2..12;
+                           0 lets the library choose (12, the wavefront-sized
+                           block).  B changes the schedule, hence the
+                           trajectory; the oracle must use the same B. */
+    uint64_t seed;      /* Philox key */
+} smcx_desc;
+
+/* ---- single lattice ----------------------------------------------------
+ * smcx_create: copies N = 2*L0*L1*L2 species bytes and the S*K*K EPI table,
+ * allocates the lattice on the current HIP device and creates a stream.
+ * T is the temperature of every sweep until changed.  The sweep counter
+ * starts at 0.  Errors: INVALID, UNSUPPORTED, RANGE, NOMEM, DEVICE. */
+smcx_status smcx_create(const smcx_desc* desc, const uint8_t* species, const int32_t* epi_ueV,
+                        double T_kelvin, smcx_ctx** out);
+
+/* smcx_create_device: as smcx_create, but the lattice lives in the caller's
+ * device buffer d_species (N bytes, canonical order, already holding the
+ * configuration; borrowed, updated in place), and work is enqueued on
+ * hip_stream (a hipStream_t, or NULL for the null stream).  The species are
+ * validated on the device. */
+smcx_status smcx_create_device(const smcx_desc* desc, uint8_t* d_species, const int32_t* epi_ueV,
+                               double T_kelvin, void* hip_stream, smcx_ctx** out);
+
+/* Temperature of every following sweep (kelvin, 1..5000). */
+smcx_status smcx_set_temperature(smcx_ctx* ctx, double T_kelvin);
+
+/* Temperatures of the next n sweeps (an anneal); later sweeps keep the
+ * last value.  T_per_sweep is copied. */
+smcx_status smcx_set_schedule(smcx_ctx* ctx, const double* T_per_sweep, int32_t n);
+
+/* Enqueue n >= 0 sweeps (Section "Monte Carlo simulation": one trial per
+ * site each).  Asynchronous.  RANGE if the sweep counter would pass 2^32. */
+smcx_status smcx_sweep(smcx_ctx* ctx, int32_t n);
+
+/* Running energy: the initial energy plus every accepted dE (micro-eV). */
+smcx_status smcx_energy(smcx_ctx* ctx, int64_t* E_ueV);
+
+/* Energy recomputed from the current configuration by a full pass. */
+smcx_status smcx_energy_recompute(smcx_ctx* ctx, int64_t* E_ueV);
+
+/* Warren-Cowley SRO, Eq. (SRO): alpha[(m*K + p')*K + p] = 1 - P_m^{p|p'}/c_p,
+ * p' the centre species; NaN when species p or p' is absent.  counts
+ * (nullable) receives the pair counts N_m[p'][p] (S*K*K uint64). */
+smcx_status smcx_sro(smcx_ctx* ctx, double* alpha, uint64_t* counts);
+
+/* Copy the configuration (canonical order) into out (n >= N bytes). */
+smcx_status smcx_get_config(smcx_ctx* ctx, uint8_t* out, size_t n);
+
+/* Counters: sweeps done, attempted trials (N per sweep), accepted swaps
+ * that changed the configuration; block receives the schedule parameter B. */
+smcx_status smcx_get_stats(smcx_ctx* ctx, uint64_t* sweeps, uint64_t* attempted,
+                           uint64_t* accepted, int32_t block[3]);
+
+/* Resume: replace the configuration (N bytes, copied) and set the sweep
+ * counter, recomputing the energy.  With the same seed, B and temperatures
+ * the continuation is bit-identical to an uninterrupted run. */
+smcx_status smcx_set_state(smcx_ctx* ctx, const uint8_t* species, uint64_t sweep_index);
+
+/* Wait for all enqueued work. */
+smcx_status smcx_synchronize(smcx_ctx* ctx);
+
+/* Kernel timing of the sweep kernel: when enabled, every colour-phase
+ * launch is bracketed by HIP events on the context's stream.
+ * smcx_kernel_time returns the summed duration (ms) and launch count since
+ * enabling (synchronises). */
+smcx_status smcx_profile(smcx_ctx* ctx, int32_t enable);
+smcx_status smcx_kernel_time(smcx_ctx* ctx, double* total_ms, uint64_t* launches);
+
+void smcx_destroy(smcx_ctx* ctx);
+const char* smcx_last_error(const smcx_ctx* ctx);
+const char* smcx_global_error(void);
+const char* smcx_status_string(smcx_status s);
+
+/* ---- many lattices in one launch (temperature parallelism) --------------
+ * n independent replicas, each with its own desc (L, K, S, B, seed), species
+ * and EPI table (pointers may repeat) and temperature.  All are resident on
+ * the device.  A replica's trajectory is exactly that of a single context
+ * with the same inputs: work placement never enters the arithmetic. */
+smcx_status smcx_batch_create(int32_t n, const smcx_desc* descs, const uint8_t* const* species,
+                              const int32_t* const* epi_ueV, const double* T_kelvin,
+                              smcx_batch** out);
+/* Advance replica r by n_sweeps[r] >= 0 sweeps.  All phases of all replicas
+ * are captured once into a HIP graph and launched as one graph; each phase
+ * kernel covers the blocks of every replica still running. */
+smcx_status smcx_batch_run(smcx_batch* batch, const int32_t* n_sweeps);
+/* Same work, one launch per replica and phase (the per-instance baseline). */
+smcx_status smcx_batch_run_unbatched(smcx_batch* batch, const int32_t* n_sweeps);
+/* Per-replica view: a context usable with smcx_energy, smcx_energy_recompute,
+ * smcx_sro, smcx_get_config, smcx_get_stats.  Owned by the batch. */
+smcx_status smcx_batch_ctx(smcx_batch* batch, int32_t r, smcx_ctx** view);
+smcx_status smcx_batch_set_temperature(smcx_batch* batch, int32_t r, double T_kelvin);
+/* Replica exchange (equations for P_swap and Delta): for each listed pair
+ * (a[k], b[k]) in order, exchange the temperatures of replicas a and b with
+ * probability min(1, exp((1/kB)(1/T_a - 1/T_b)(E_a - E_b))), deciding with
+ * Philox4x32-10(key = (seed lo, seed hi), counter = (k, round, 0, 9)) word 0
+ * as u: accept iff (double)u < 2^32 * min(1, exp(Delta)).  Replicas must
+ * share L and K.  accepted[k] (nullable) receives the decisions. */
+smcx_status smcx_batch_exchange(smcx_batch* batch, const int32_t* a, const int32_t* b, int32_t n_pairs,
+                                uint64_t seed, uint64_t round, int32_t* accepted);
+smcx_status smcx_batch_synchronize(smcx_batch* batch);
+void smcx_batch_destroy(smcx_batch* batch);
+
+/* ---- serving: continuous batching of sweep requests ---------------------
+ * A server owns an HBM budget and a number of slots.  Submitted requests
+ * wait until their footprint fits and a slot is free; admitted lattices
+ * stay resident; every smcx_server_step advances every resident request by
+ * up to `sweeps_per_step` sweeps in one batched launch per phase and
+ * retires the finished ones.  A request's result equals that of a single
+ * context with the same inputs. */
+smcx_status smcx_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t sweeps_per_step,
+                               smcx_server** out);
+smcx_status smcx_server_submit(smcx_server* srv, const smcx_desc* desc, const uint8_t* species,
+                               const int32_t* epi_ueV, double T_kelvin, int32_t n_sweeps,
+                               uint64_t* request_id);
+/* One scheduling step: admit, run, retire.  Reports counts after the step. */
+smcx_status smcx_server_step(smcx_server* srv, int32_t* n_resident, int32_t* n_waiting,
+                             int32_t* n_finished_this_step);
+/* Status of a request: 0 waiting, 1 resident, 2 finished, 3 failed. */
+smcx_status smcx_server_poll(smcx_server* srv, uint64_t request_id, int32_t* state);
+/* Result of a finished request; config (nullable, n >= N bytes).  Frees it. */
+smcx_status smcx_server_result(smcx_server* srv, uint64_t request_id, int64_t* E_ueV,
+                               uint64_t* accepted, uint8_t* config, size_t n);
+/* Device bytes a request of this shape holds while resident. */
+size_t smcx_server_footprint(const smcx_desc* desc);
+void smcx_server_destroy(smcx_server* srv);
+const char* smcx_server_last_error(const smcx_server* srv);
+
+/* ---- verification hooks ---------------------------------------------------
+ * smcx_threshold_table: the host table the library builds for T (768 doubles:
+ * T0, T1, T2).  smcx_device_thresholds: the threshold products computed by
+ * the device's FP64 unit for n energy changes (host arrays; synchronous).
+ * smcx_device_philox: Philox4x32-10 evaluated on the device for n counters
+ * (host arrays of 4n words; synchronous). */
+smcx_status smcx_threshold_table(double T_kelvin, double* out768);
+smcx_status smcx_device_thresholds(double T_kelvin, const int32_t* dE, int32_t n, double* out);
+smcx_status smcx_device_philox(const uint32_t* ctr, const uint32_t key[2], int32_t n, uint32_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SMCX_H */

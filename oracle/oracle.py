@@ -25,7 +25,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB):
         tmp = LIB + ".tmp"
         subprocess.check_call([
-            "gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+            "gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
             "-fno-fast-math", "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)
     return LIB
@@ -38,6 +38,8 @@ def lib():
             build()
         L = C.CDLL(LIB)
         p = C.POINTER
+        L.or_set_threads.argtypes = [C.c_int]
+        L.or_get_threads.restype = C.c_int
         L.or_philox4x32_10.argtypes = [p(C.c_uint32), p(C.c_uint32), p(C.c_uint32)]
         L.or_philox4x64_10.argtypes = [p(C.c_uint64), p(C.c_uint64), p(C.c_uint64)]
         L.or_thresholds.argtypes = [C.c_double, p(C.c_double)]
@@ -68,6 +70,15 @@ def lib():
         L.or_enumerate.restype = C.c_int64
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Worker threads of the oracle (results are identical for any count)."""
+    lib().or_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().or_get_threads())
 
 
 def _ptr(a, ctype):

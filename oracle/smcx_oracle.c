@@ -35,6 +35,18 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Worker threads for the trials of one (colour, sub-colour) set and for the
+ * pair sums.  The trials of one set never read what another writes (the
+ * schedule guarantees it, the audit test checks it) and the sums are exact
+ * integers, so any thread count gives the same bits as one thread. */
+static int g_threads = 1;
+
+void or_set_threads(int n) { g_threads = n < 1 ? 1 : n; }
+int or_get_threads(void) { return g_threads; }
 
 /* ------------------------------------------------------------------------ */
 /* Philox (Salmon et al., SC'11, "Parallel random numbers: as easy as 1, 2,  */
@@ -145,17 +157,34 @@ static const int* displacement(int k, int* shell)
 
 static int64_t wrap(int64_t v, int64_t m) { v %= m; return v < 0 ? v + m : v; }
 
+/* A site in decoded form: doubled coordinates X, Y, Z (parities equal b). */
+typedef struct { int64_t X, Y, Z; } site_xyz;
+
+static site_xyz decode_site(const int32_t L[3], int64_t i)
+{
+    int64_t b = i & 1, cell = i >> 1;
+    int64_t x = cell % L[0], y = (cell / L[0]) % L[1], z = cell / ((int64_t)L[0] * L[1]);
+    site_xyz p = {2 * x + b, 2 * y + b, 2 * z + b};
+    return p;
+}
+
+/* periodic add of a displacement component in [-2, 2] to X in [0, 2L) */
+static int64_t wrap_small(int64_t v, int64_t twoL) { return v < 0 ? v + twoL : (v >= twoL ? v - twoL : v); }
+
+static int64_t site_at(const int32_t L[3], site_xyz p, const int* d)
+{
+    int64_t X = wrap_small(p.X + d[0], 2 * (int64_t)L[0]);
+    int64_t Y = wrap_small(p.Y + d[1], 2 * (int64_t)L[1]);
+    int64_t Z = wrap_small(p.Z + d[2], 2 * (int64_t)L[2]);
+    int64_t nb = X & 1; /* equal parities on all axes */
+    return ((((Z >> 1) * L[1] + (Y >> 1)) * L[0] + (X >> 1)) << 1) | nb;
+}
+
 int64_t or_neighbour(const int32_t L[3], int64_t i, int k)
 {
     int shell;
     const int* d = displacement(k, &shell);
-    int64_t b = i & 1, cell = i >> 1;
-    int64_t x = cell % L[0], y = (cell / L[0]) % L[1], z = cell / ((int64_t)L[0] * L[1]);
-    int64_t X = wrap(2 * x + b + d[0], 2 * (int64_t)L[0]);
-    int64_t Y = wrap(2 * y + b + d[1], 2 * (int64_t)L[1]);
-    int64_t Z = wrap(2 * z + b + d[2], 2 * (int64_t)L[2]);
-    int64_t nb = X & 1; /* equal parities on all axes */
-    return ((((Z >> 1) * L[1] + (Y >> 1)) * L[0] + (X >> 1)) << 1) | nb;
+    return site_at(L, decode_site(L, i), d);
 }
 
 static int n_displacements(int S)
@@ -174,13 +203,16 @@ int64_t or_energy(const int32_t L[3], int S, int K, const int32_t* epi, const ui
 {
     int64_t N = n_sites(L), twiceE = 0;
     int nd = n_displacements(S);
-    for (int64_t i = 0; i < N; ++i)
+#pragma omp parallel for reduction(+ : twiceE) num_threads(g_threads) schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        site_xyz p = decode_site(L, i);
         for (int k = 0; k < nd; ++k) {
             int s;
-            displacement(k, &s);
-            int64_t n = or_neighbour(L, i, k);
+            const int* d = displacement(k, &s);
+            int64_t n = site_at(L, p, d);
             twiceE += epi[(s * K + sigma[i]) * K + sigma[n]];
         }
+    }
     return twiceE / 2;
 }
 
@@ -194,13 +226,14 @@ int64_t or_delta_energy(const int32_t L[3], int S, int K, const int32_t* epi,
 {
     int nd = n_displacements(S);
     int si = sigma[i], sj = sigma[j];
+    site_xyz pi = decode_site(L, i), pj = decode_site(L, j);
     int64_t dE = 0;
     for (int k = 0; k < nd; ++k) {
         int s;
-        displacement(k, &s);
-        int64_t n = or_neighbour(L, i, k);
+        const int* d = displacement(k, &s);
+        int64_t n = site_at(L, pi, d);
         if (n != j) dE += epi[(s * K + sj) * K + sigma[n]] - epi[(s * K + si) * K + sigma[n]];
-        int64_t m = or_neighbour(L, j, k);
+        int64_t m = site_at(L, pj, d);
         if (m != i) dE += epi[(s * K + si) * K + sigma[m]] - epi[(s * K + sj) * K + sigma[m]];
     }
     return dE;
@@ -212,14 +245,25 @@ void or_pair_counts(const int32_t L[3], int S, int K, const uint8_t* sigma, uint
 {
     int64_t N = n_sites(L);
     int nd = n_displacements(S);
-    memset(counts, 0, sizeof(uint64_t) * S * K * K);
-    for (int64_t i = 0; i < N; ++i)
-        for (int k = 0; k < nd; ++k) {
-            int s;
-            displacement(k, &s);
-            int64_t n = or_neighbour(L, i, k);
-            counts[(s * K + sigma[i]) * K + sigma[n]] += 1;
+    size_t nc = (size_t)S * K * K;
+    memset(counts, 0, sizeof(uint64_t) * nc);
+#pragma omp parallel num_threads(g_threads)
+    {
+        uint64_t* mine = (uint64_t*)calloc(nc, sizeof(uint64_t));
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < N; ++i) {
+            site_xyz p = decode_site(L, i);
+            for (int k = 0; k < nd; ++k) {
+                int s;
+                const int* d = displacement(k, &s);
+                int64_t n = site_at(L, p, d);
+                mine[(s * K + sigma[i]) * K + sigma[n]] += 1;
+            }
         }
+#pragma omp critical
+        for (size_t c = 0; c < nc; ++c) counts[c] += mine[c];
+        free(mine);
+    }
 }
 
 /* Warren-Cowley SRO, Eq. (SRO): alpha_m^{pp'} = 1 - P_m^{p|p'} / c_p with
@@ -290,31 +334,40 @@ void or_schedule(const int32_t L[3], const int32_t B[3], uint64_t seed, uint32_t
 {
     int32_t shift[3];
     or_sweep_shift(L, seed, s, shift);
+    /* per axis and cell coordinate x: block index k and local coordinate l */
     int n[3];
-    int32_t* bounds[3];
+    int32_t* kof[3];
+    int32_t* lof[3];
     for (int a = 0; a < 3; ++a) {
         n[a] = or_axis_blocks(L[a], B[a]);
-        bounds[a] = (int32_t*)malloc(sizeof(int32_t) * (n[a] + 1));
-        or_axis_bounds(L[a], B[a], bounds[a]);
-    }
-    int64_t N = n_sites(L);
-    for (int64_t i = 0; i < N; ++i) {
-        int64_t cell = i >> 1;
-        int b = (int)(i & 1);
-        int64_t xyz[3] = {cell % L[0], (cell / L[0]) % L[1], cell / ((int64_t)L[0] * L[1])};
-        int k[3], l[3];
-        for (int a = 0; a < 3; ++a) {
-            int64_t u = wrap(xyz[a] - shift[a], L[a]);
+        int32_t* bounds = (int32_t*)malloc(sizeof(int32_t) * (n[a] + 1));
+        or_axis_bounds(L[a], B[a], bounds);
+        kof[a] = (int32_t*)malloc(sizeof(int32_t) * L[a]);
+        lof[a] = (int32_t*)malloc(sizeof(int32_t) * L[a]);
+        for (int32_t x = 0; x < L[a]; ++x) {
+            int64_t u = wrap((int64_t)x - shift[a], L[a]);
             int kk = 0;
-            while (!(bounds[a][kk] <= u && u < bounds[a][kk + 1])) ++kk;
-            k[a] = kk;
-            l[a] = (int)(u - bounds[a][kk]);
+            while (!(bounds[kk] <= u && u < bounds[kk + 1])) ++kk;
+            kof[a][x] = kk;
+            lof[a][x] = (int32_t)(u - bounds[kk]);
         }
-        colour[i] = (uint8_t)((k[0] & 1) | ((k[1] & 1) << 1) | ((k[2] & 1) << 2));
-        subcolour[i] = (uint8_t)((((l[2] % 3) * 3 + l[1] % 3) * 3 + l[0] % 3) * 2 + b);
-        if (block) block[i] = ((int64_t)k[2] * n[1] + k[1]) * n[0] + k[0];
+        free(bounds);
     }
-    for (int a = 0; a < 3; ++a) free(bounds[a]);
+    int64_t cell = 0;
+    for (int64_t z = 0; z < L[2]; ++z)
+        for (int64_t y = 0; y < L[1]; ++y)
+            for (int64_t x = 0; x < L[0]; ++x, ++cell) {
+                int kx = kof[0][x], ky = kof[1][y], kz = kof[2][z];
+                int lx = lof[0][x], ly = lof[1][y], lz = lof[2][z];
+                uint8_t c = (uint8_t)((kx & 1) | ((ky & 1) << 1) | ((kz & 1) << 2));
+                uint8_t q = (uint8_t)((((lz % 3) * 3 + ly % 3) * 3 + lx % 3) * 2);
+                for (int b = 0; b < 2; ++b) {
+                    colour[2 * cell + b] = c;
+                    subcolour[2 * cell + b] = (uint8_t)(q + b);
+                    if (block) block[2 * cell + b] = ((int64_t)kz * n[1] + ky) * n[0] + kx;
+                }
+            }
+    for (int a = 0; a < 3; ++a) { free(kof[a]); free(lof[a]); }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -357,25 +410,34 @@ int or_sweep(const int32_t L[3], const int32_t B[3], int S, int K, const int32_t
         for (int g = 0; g < 8 * 54; ++g) start[g + 1] += start[g];
         for (int64_t i = 0; i < N; ++i) order[start[colour[i] * 54 + sub[i]]++] = i;
 
-        for (int64_t r = 0; r < N; ++r) {
-            int64_t i = order[r];
-            int64_t cell = i >> 1;
-            int b = (int)(i & 1);
-            uint32_t ctr[4] = {(uint32_t)cell, (uint32_t)(cell >> 32), s, colour[i]};
-            uint32_t rnd[4];
-            or_philox4x32_10(ctr, key, rnd);
-            uint32_t u_dir = rnd[2 * b], u_acc = rnd[2 * b + 1];
-            int dir = (int)(u_dir >> 29);
-            int64_t j = or_neighbour(L, i, dir);
-            if (sigma[i] == sigma[j]) continue;
-            int64_t dE = or_delta_energy(L, S, K, epi, sigma, i, j);
-            if (or_accept(dE, u_acc, tab)) {
-                uint8_t tmp = sigma[i];
-                sigma[i] = sigma[j];
-                sigma[j] = tmp;
-                *E += dE;
-                *accepted += 1;
+        for (int g = 0; g < 8 * 54; ++g) {
+            int64_t lo = g == 0 ? 0 : start[g - 1], hi = start[g];
+            int64_t dE_set = 0;
+            uint64_t acc_set = 0;
+#pragma omp parallel for reduction(+ : dE_set, acc_set) num_threads(g_threads) schedule(static) \
+    if (hi - lo > 512)
+            for (int64_t r = lo; r < hi; ++r) {
+                int64_t i = order[r];
+                int64_t cell = i >> 1;
+                int b = (int)(i & 1);
+                uint32_t ctr[4] = {(uint32_t)cell, (uint32_t)(cell >> 32), s, colour[i]};
+                uint32_t rnd[4];
+                or_philox4x32_10(ctr, key, rnd);
+                uint32_t u_dir = rnd[2 * b], u_acc = rnd[2 * b + 1];
+                int dir = (int)(u_dir >> 29);
+                int64_t j = or_neighbour(L, i, dir);
+                if (sigma[i] == sigma[j]) continue;
+                int64_t dE = or_delta_energy(L, S, K, epi, sigma, i, j);
+                if (or_accept(dE, u_acc, tab)) {
+                    uint8_t tmp = sigma[i];
+                    sigma[i] = sigma[j];
+                    sigma[j] = tmp;
+                    dE_set += dE;
+                    acc_set += 1;
+                }
             }
+            *E += dE_set;
+            *accepted += acc_set;
         }
         if (E_trace) E_trace[t] = *E;
         if (counts_trace) or_pair_counts(L, S, K, sigma, counts_trace + (size_t)t * S * K * K);

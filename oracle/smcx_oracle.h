@@ -48,6 +48,11 @@
 extern "C" {
 #endif
 
+/* Threads for the trials of one (colour, sub-colour) set and for pair sums;
+ * results are bit-identical for every thread count. */
+void or_set_threads(int n);
+int or_get_threads(void);
+
 /* Philox4x32-10 and its 4x64-10 sibling (same round structure, wider words). */
 void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 void or_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);

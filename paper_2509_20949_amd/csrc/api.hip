@@ -1,0 +1,593 @@
+// api.hip -- C ABI of libsmcx, single-lattice contexts (include/smcx.h).
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/smcx.h"
+#include "ctx.h"
+
+using namespace smcx;
+
+namespace {
+thread_local std::string g_error;
+}
+
+namespace smcx {
+
+smcx_status fail_global(smcx_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return st;
+}
+
+smcx_status fail(smcx_ctx* c, smcx_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    g_error = buf;
+    return st;
+}
+
+smcx_status validate_desc(const smcx_desc* d, int32_t block_out[3], bool for_gpu)
+{
+    if (!d) return fail_global(SMCX_E_INVALID, "desc is NULL");
+    if (d->lattice != SMCX_LATTICE_BCC) return fail_global(SMCX_E_UNSUPPORTED, "only the BCC lattice is supported");
+    for (int a = 0; a < 3; ++a) {
+        if (d->L[a] < 2) return fail_global(SMCX_E_INVALID, "L[%d] = %d < 2", a, d->L[a]);
+        if (for_gpu && d->L[a] < 4)
+            return fail_global(SMCX_E_UNSUPPORTED, "L[%d] = %d: the GPU schedule needs >= 4 cells", a, d->L[a]);
+        if (d->L[a] > (1 << 28)) return fail_global(SMCX_E_UNSUPPORTED, "L[%d] = %d too large", a, d->L[a]);
+        int B = d->block[a] == 0 ? kMaxBlock : d->block[a];
+        if (B < 2) return fail_global(SMCX_E_INVALID, "block[%d] = %d < 2", a, d->block[a]);
+        if (B > kMaxBlock) return fail_global(SMCX_E_UNSUPPORTED, "block[%d] = %d > %d", a, B, kMaxBlock);
+        block_out[a] = B;
+    }
+    if (d->n_species < 1 || d->n_species > kMaxK)
+        return fail_global(d->n_species < 1 ? SMCX_E_INVALID : SMCX_E_UNSUPPORTED, "n_species = %d outside 1..%d",
+                           d->n_species, kMaxK);
+    if (d->n_shells < 1 || d->n_shells > kMaxS)
+        return fail_global(d->n_shells < 1 ? SMCX_E_INVALID : SMCX_E_UNSUPPORTED, "n_shells = %d outside 1..%d",
+                           d->n_shells, kMaxS);
+    return SMCX_OK;
+}
+
+smcx_status validate_epi(const int32_t* epi, int K, int S)
+{
+    if (!epi) return fail_global(SMCX_E_INVALID, "EPI table is NULL");
+    for (int s = 0; s < S; ++s)
+        for (int p = 0; p < K; ++p)
+            for (int q = 0; q < K; ++q) {
+                const int32_t v = epi[(s * K + p) * K + q];
+                if (v != epi[(s * K + q) * K + p])
+                    return fail_global(SMCX_E_INVALID, "EPI shell %d not symmetric at (%d, %d)", s + 1, p, q);
+                if (v <= -(1 << 22) || v >= (1 << 22))
+                    return fail_global(SMCX_E_RANGE, "|EPI| must be < 2^22 micro-eV (shell %d, %d, %d)", s + 1, p, q);
+            }
+    return SMCX_OK;
+}
+
+smcx_status validate_T(double T)
+{
+    if (!(T >= 1.0 && T <= 5000.0)) return fail_global(SMCX_E_RANGE, "T = %g K outside [1, 5000]", T);
+    return SMCX_OK;
+}
+
+size_t n_sites(const int32_t L[3]) { return 2 * (size_t)L[0] * L[1] * L[2]; }
+
+// ---- context internals ------------------------------------------------------
+smcx_status ctx_hip(smcx_ctx* c, hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return SMCX_OK;
+    return fail(c, e == hipErrorOutOfMemory ? SMCX_E_NOMEM : SMCX_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Fill the geometry part of a DevLattice from a validated desc.
+void fill_geometry(DevLattice& L, const smcx_desc* d, const int32_t B[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        L.L[a] = d->L[a];
+        L.nb[a] = axis_blocks(d->L[a], B[a]);
+    }
+    L.key[0] = (uint32_t)d->seed;
+    L.key[1] = (uint32_t)(d->seed >> 32);
+    L.K = d->n_species;
+    L.blocks_per_colour = (L.nb[0] / 2) * (L.nb[1] / 2) * (L.nb[2] / 2);
+}
+
+bool geometry_ok(const DevLattice& L)
+{
+    for (int a = 0; a < 3; ++a) {
+        if (L.nb[a] < 2 || (L.nb[a] & 1)) return false;
+        // every block 2..kMaxBlock cells wide
+        for (int k = 0; k < L.nb[a]; ++k) {
+            const int64_t w = ((int64_t)(k + 1) * L.L[a]) / L.nb[a] - ((int64_t)k * L.L[a]) / L.nb[a];
+            if (w < 2 || w > kMaxBlock) return false;
+        }
+    }
+    return true;
+}
+
+smcx_status upload_tables(smcx_ctx* c, const double* T, int n, uint64_t s0)
+{
+    // tables are read by enqueued sweeps: wait before replacing them
+    smcx_status st = ctx_hip(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    if (st) return st;
+    std::vector<double> h((size_t)n * kTab);
+    for (int k = 0; k < n; ++k) build_thresholds(T[k], h.data() + (size_t)k * kTab);
+    if (n > c->tab_cap) {
+        if (c->d_tabs) (void)hipFree(c->d_tabs);
+        c->d_tabs = nullptr;
+        c->tab_cap = 0;
+        st = ctx_hip(c, hipMalloc(&c->d_tabs, sizeof(double) * kTab * (size_t)n), "hipMalloc(tables)");
+        if (st) return st;
+        c->tab_cap = n;
+    }
+    st = ctx_hip(c, hipMemcpy(c->d_tabs, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice),
+                 "hipMemcpy(tables)");
+    if (st) return st;
+    c->h_lat.tabs = c->d_tabs;
+    c->h_lat.tab_s0 = (uint32_t)s0;
+    c->h_lat.n_tabs = n;
+    return ctx_hip(c, hipMemcpy(c->d_lat, &c->h_lat, sizeof(DevLattice), hipMemcpyHostToDevice),
+                   "hipMemcpy(lattice descriptor)");
+}
+
+smcx_status recompute_energy(smcx_ctx* c, int64_t* E)
+{
+    smcx_status st = ctx_hip(c, hipMemsetAsync(c->d_counts, 0, sizeof(unsigned long long) * kMaxS * kMaxK * kMaxK,
+                                               c->stream), "hipMemsetAsync");
+    if (st) return st;
+    st = ctx_hip(c, launch_pair_counts(c->h_lat.species, c->h_lat.L, c->K, c->S, c->d_counts, c->stream),
+                 "pair_counts launch");
+    if (st) return st;
+    unsigned long long h[kMaxS * kMaxK * kMaxK];
+    st = ctx_hip(c, hipMemcpyAsync(h, c->d_counts, sizeof(h), hipMemcpyDeviceToHost, c->stream), "hipMemcpyAsync");
+    if (st) return st;
+    st = ctx_hip(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    if (st) return st;
+    std::memcpy(c->counts, h, sizeof(h));
+    int64_t twice = 0;
+    for (int s = 0; s < c->S; ++s)
+        for (int p = 0; p < c->K; ++p)
+            for (int q = 0; q < c->K; ++q)
+                twice += (int64_t)h[(s * kMaxK + p) * kMaxK + q] * c->epi[(s * c->K + p) * c->K + q];
+    *E = twice / 2;
+    return SMCX_OK;
+}
+
+static smcx_status ctx_init(smcx_ctx* c, const smcx_desc* d, const int32_t B[3], const int32_t* epi, double T)
+{
+    c->desc = *d;
+    for (int a = 0; a < 3; ++a) c->B[a] = B[a];
+    c->K = d->n_species;
+    c->S = d->n_shells;
+    c->N = n_sites(d->L);
+    c->kmax = kmax_for(c->K);
+    c->smax = c->S;
+    c->epi.assign(epi, epi + (size_t)c->S * c->K * c->K);
+    std::memset(&c->h_lat, 0, sizeof(DevLattice));
+    fill_geometry(c->h_lat, d, B);
+    if (!geometry_ok(c->h_lat)) return fail(c, SMCX_E_UNSUPPORTED, "block geometry outside 2..%d cells", kMaxBlock);
+
+    smcx_status st;
+    st = ctx_hip(c, hipMalloc(&c->d_lat, sizeof(DevLattice)), "hipMalloc(descriptor)");
+    if (st) return st;
+    st = ctx_hip(c, hipMalloc(&c->d_state, sizeof(int64_t) + sizeof(unsigned long long)), "hipMalloc(state)");
+    if (st) return st;
+    st = ctx_hip(c, hipMalloc(&c->d_counts, sizeof(unsigned long long) * kMaxS * kMaxK * kMaxK), "hipMalloc(counts)");
+    if (st) return st;
+    const int wr = wrow(c->kmax, c->smax);
+    std::vector<int32_t> w((size_t)c->kmax * c->kmax * wr);
+    build_wtab(epi, c->K, c->S, c->kmax, c->smax, w.data());
+    st = ctx_hip(c, hipMalloc(&c->d_wtab, sizeof(int32_t) * w.size()), "hipMalloc(weights)");
+    if (st) return st;
+    st = ctx_hip(c, hipMemcpy(c->d_wtab, w.data(), sizeof(int32_t) * w.size(), hipMemcpyHostToDevice), "hipMemcpy(weights)");
+    if (st) return st;
+    c->h_lat.wtab = c->d_wtab;
+    c->h_lat.energy = (int64_t*)c->d_state;
+    c->h_lat.accepted = (unsigned long long*)((char*)c->d_state + sizeof(int64_t));
+    c->h_lat.species = c->d_species;
+    c->h_lat.sweep0 = 0;   // single lattice: launch step t is the sweep index
+    c->T_default = T;
+    st = upload_tables(c, &T, 1, 0);
+    if (st) return st;
+    int64_t E0 = 0;
+    st = recompute_energy(c, &E0);
+    if (st) return st;
+    int64_t init[2] = {E0, 0};
+    return ctx_hip(c, hipMemcpy(c->d_state, init, sizeof(init), hipMemcpyHostToDevice), "hipMemcpy(state)");
+}
+
+void ctx_release(smcx_ctx* c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto& e : c->events) (void)hipEventDestroy(e);
+    c->events.clear();
+    if (c->owns_species && c->d_species) (void)hipFree(c->d_species);
+    if (c->d_lat) (void)hipFree(c->d_lat);
+    if (c->d_state) (void)hipFree(c->d_state);
+    if (c->d_counts) (void)hipFree(c->d_counts);
+    if (c->d_wtab) (void)hipFree(c->d_wtab);
+    if (c->d_tabs) (void)hipFree(c->d_tabs);
+    if (c->owns_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    c->d_species = nullptr;
+    c->d_lat = nullptr;
+    c->d_state = nullptr;
+    c->d_counts = nullptr;
+    c->d_wtab = nullptr;
+    c->d_tabs = nullptr;
+    c->stream = nullptr;
+}
+
+// Temperature of sweep s under the context's schedule.
+double temperature_of(const smcx_ctx* c, uint64_t s)
+{
+    if (c->sched.empty()) return c->T_default;
+    if (s < c->sched_s0) return c->sched.front();
+    const uint64_t k = s - c->sched_s0;
+    return k < c->sched.size() ? c->sched[k] : c->sched.back();
+}
+
+smcx_status enqueue_sweeps(smcx_ctx* c, int32_t n)
+{
+    const int groups = (c->h_lat.blocks_per_colour + kWavesPerGroup - 1) / kWavesPerGroup;
+    for (int32_t k = 0; k < n; ++k) {
+        const uint32_t s = (uint32_t)(c->sweeps + (uint64_t)k);
+        for (int col = 0; col < 8; ++col) {
+            if (c->profiling) {
+                hipEvent_t e0, e1;
+                smcx_status st = ctx_hip(c, hipEventCreate(&e0), "hipEventCreate");
+                if (st) return st;
+                st = ctx_hip(c, hipEventCreate(&e1), "hipEventCreate");
+                if (st) { (void)hipEventDestroy(e0); return st; }
+                c->events.push_back(e0);
+                c->events.push_back(e1);
+                (void)hipEventRecord(e0, c->stream);
+            }
+            hipError_t e = launch_sweep_phase(c->d_lat, nullptr, groups, (int)s, col, c->kmax, c->smax, c->stream);
+            if (e != hipSuccess) return ctx_hip(c, e, "sweep_phase launch");
+            if (c->profiling) (void)hipEventRecord(c->events.back(), c->stream);
+        }
+    }
+    c->sweeps += (uint64_t)n;
+    c->attempted += (uint64_t)n * c->N;
+    return SMCX_OK;
+}
+
+}  // namespace smcx
+
+// =============================================================================
+extern "C" {
+
+const char* smcx_global_error(void) { return g_error.c_str(); }
+
+const char* smcx_last_error(const smcx_ctx* ctx) { return ctx ? ctx->err.c_str() : g_error.c_str(); }
+
+const char* smcx_status_string(smcx_status s)
+{
+    switch (s) {
+    case SMCX_OK: return "ok";
+    case SMCX_E_INVALID: return "invalid argument";
+    case SMCX_E_UNSUPPORTED: return "unsupported";
+    case SMCX_E_NOMEM: return "out of memory";
+    case SMCX_E_DEVICE: return "device error";
+    case SMCX_E_RANGE: return "out of range";
+    case SMCX_E_STATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+static smcx_status create_common(const smcx_desc* desc, const uint8_t* species, uint8_t* d_species,
+                                 const int32_t* epi, double T, void* stream, smcx_ctx** out)
+{
+    if (!out) return fail_global(SMCX_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int32_t B[3];
+    smcx_status st = validate_desc(desc, B, true);
+    if (st) return st;
+    st = validate_epi(epi, desc->n_species, desc->n_shells);
+    if (st) return st;
+    st = validate_T(T);
+    if (st) return st;
+    const size_t N = n_sites(desc->L);
+    if (species) {
+        for (size_t i = 0; i < N; ++i)
+            if (species[i] >= desc->n_species)
+                return fail_global(SMCX_E_INVALID, "species[%zu] = %d >= K = %d", i, species[i], desc->n_species);
+    } else if (!d_species) {
+        return fail_global(SMCX_E_INVALID, "species is NULL");
+    }
+    smcx_ctx* c = new (std::nothrow) smcx_ctx();
+    if (!c) return fail_global(SMCX_E_NOMEM, "host allocation failed");
+    if (stream || d_species) {
+        c->stream = (hipStream_t)stream;
+        c->owns_stream = false;
+    } else {
+        st = ctx_hip(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "hipStreamCreate");
+        if (st) { delete c; return st; }
+        c->owns_stream = true;
+    }
+    if (d_species) {
+        c->d_species = d_species;
+        c->owns_species = false;
+    } else {
+        st = ctx_hip(c, hipMalloc(&c->d_species, N), "hipMalloc(lattice)");
+        if (!st) st = ctx_hip(c, hipMemcpy(c->d_species, species, N, hipMemcpyHostToDevice), "hipMemcpy(lattice)");
+        if (st) { ctx_release(c); delete c; return st; }
+        c->owns_species = true;
+    }
+    if (d_species) {
+        // validate the borrowed configuration on the device
+        unsigned int* d_max = nullptr;
+        unsigned int mx = 0;
+        st = ctx_hip(c, hipMalloc(&d_max, sizeof(unsigned int)), "hipMalloc");
+        if (!st) st = ctx_hip(c, hipMemsetAsync(d_max, 0, sizeof(unsigned int), c->stream), "hipMemsetAsync");
+        if (!st) st = ctx_hip(c, launch_species_max(d_species, N, d_max, c->stream), "species_max launch");
+        if (!st) st = ctx_hip(c, hipMemcpyAsync(&mx, d_max, sizeof(mx), hipMemcpyDeviceToHost, c->stream), "copy");
+        if (!st) st = ctx_hip(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+        if (d_max) (void)hipFree(d_max);
+        if (!st && mx >= (unsigned)desc->n_species)
+            st = fail(c, SMCX_E_INVALID, "device species value %u >= K = %d", mx, desc->n_species);
+        if (st) { ctx_release(c); delete c; return st; }
+    }
+    st = ctx_init(c, desc, B, epi, T);
+    if (st) {
+        g_error = c->err;
+        ctx_release(c);
+        delete c;
+        return st;
+    }
+    *out = c;
+    return SMCX_OK;
+}
+
+smcx_status smcx_create(const smcx_desc* desc, const uint8_t* species, const int32_t* epi_ueV, double T_kelvin,
+                        smcx_ctx** out)
+{
+    if (!species) {
+        if (out) *out = nullptr;
+        return fail_global(SMCX_E_INVALID, "species is NULL");
+    }
+    return create_common(desc, species, nullptr, epi_ueV, T_kelvin, nullptr, out);
+}
+
+smcx_status smcx_create_device(const smcx_desc* desc, uint8_t* d_species, const int32_t* epi_ueV, double T_kelvin,
+                               void* hip_stream, smcx_ctx** out)
+{
+    if (!d_species) {
+        if (out) *out = nullptr;
+        return fail_global(SMCX_E_INVALID, "d_species is NULL");
+    }
+    return create_common(desc, nullptr, d_species, epi_ueV, T_kelvin, hip_stream, out);
+}
+
+smcx_status smcx_set_temperature(smcx_ctx* c, double T)
+{
+    if (!c) return fail_global(SMCX_E_INVALID, "ctx is NULL");
+    if (c->view) return fail(c, SMCX_E_STATE, "batch views take smcx_batch_set_temperature");
+    smcx_status st = validate_T(T);
+    if (st) return fail(c, st, "%s", g_error.c_str());
+    c->sched.clear();
+    c->T_default = T;
+    return upload_tables(c, &T, 1, c->sweeps);
+}
+
+smcx_status smcx_set_schedule(smcx_ctx* c, const double* T, int32_t n)
+{
+    if (!c) return fail_global(SMCX_E_INVALID, "ctx is NULL");
+    if (c->view) return fail(c, SMCX_E_STATE, "batch views have a fixed temperature");
+    if (!T || n < 1) return fail(c, SMCX_E_INVALID, "schedule needs n >= 1 temperatures");
+    for (int32_t k = 0; k < n; ++k) {
+        smcx_status st = validate_T(T[k]);
+        if (st) return fail(c, st, "schedule[%d]: %s", k, g_error.c_str());
+    }
+    c->sched.assign(T, T + n);
+    c->sched_s0 = c->sweeps;
+    c->T_default = T[n - 1];
+    return upload_tables(c, T, n, c->sweeps);
+}
+
+smcx_status smcx_sweep(smcx_ctx* c, int32_t n)
+{
+    if (!c) return fail_global(SMCX_E_INVALID, "ctx is NULL");
+    if (c->view) return fail(c, SMCX_E_STATE, "batch views are advanced by smcx_batch_run");
+    if (n < 0) return fail(c, SMCX_E_INVALID, "n = %d < 0", n);
+    if (c->sweeps + (uint64_t)n > 0xffffffffull) return fail(c, SMCX_E_RANGE, "sweep counter would pass 2^32");
+    return enqueue_sweeps(c, n);
+}
+
+smcx_status smcx_energy(smcx_ctx* c, int64_t* E)
+{
+    if (!c || !E) return fail(c, SMCX_E_INVALID, "NULL argument");
+    int64_t h[2];
+    smcx_status st = ctx_hip(c, hipMemcpyAsync(h, c->d_state, sizeof(h), hipMemcpyDeviceToHost, c->stream),
+                             "hipMemcpyAsync");
+    if (!st) st = ctx_hip(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    if (st) return st;
+    *E = h[0];
+    return SMCX_OK;
+}
+
+smcx_status smcx_energy_recompute(smcx_ctx* c, int64_t* E)
+{
+    if (!c || !E) return fail(c, SMCX_E_INVALID, "NULL argument");
+    return recompute_energy(c, E);
+}
+
+smcx_status smcx_sro(smcx_ctx* c, double* alpha, uint64_t* counts)
+{
+    if (!c || !alpha) return fail(c, SMCX_E_INVALID, "NULL argument");
+    int64_t E;
+    smcx_status st = recompute_energy(c, &E);
+    if (st) return st;
+    const int K = c->K, S = c->S;
+    const double N = (double)c->N;
+    const int Z[3] = {8, 6, 12};
+    std::vector<uint64_t> Np(K, 0);
+    for (int p = 0; p < K; ++p)
+        for (int q = 0; q < K; ++q) Np[p] += c->counts[(0 * kMaxK + p) * kMaxK + q];
+    for (int p = 0; p < K; ++p) Np[p] /= 8;   // each centre has 8 first neighbours
+    for (int m = 0; m < S; ++m)
+        for (int pc = 0; pc < K; ++pc)
+            for (int p = 0; p < K; ++p) {
+                const uint64_t n = c->counts[(m * kMaxK + pc) * kMaxK + p];
+                if (counts) counts[(m * K + pc) * K + p] = n;
+                const double P = (double)n / ((double)Z[m] * (double)Np[pc]);
+                const double cp = (double)Np[p] / N;
+                alpha[(m * K + pc) * K + p] = (Np[p] == 0 || Np[pc] == 0) ? NAN : 1.0 - P / cp;
+            }
+    return SMCX_OK;
+}
+
+smcx_status smcx_get_config(smcx_ctx* c, uint8_t* out, size_t n)
+{
+    if (!c || !out) return fail(c, SMCX_E_INVALID, "NULL argument");
+    if (n < c->N) return fail(c, SMCX_E_INVALID, "buffer of %zu bytes < N = %zu", n, c->N);
+    smcx_status st = ctx_hip(c, hipMemcpyAsync(out, c->h_lat.species, c->N, hipMemcpyDeviceToHost, c->stream),
+                             "hipMemcpyAsync");
+    if (!st) st = ctx_hip(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    return st;
+}
+
+smcx_status smcx_get_stats(smcx_ctx* c, uint64_t* sweeps, uint64_t* attempted, uint64_t* accepted, int32_t block[3])
+{
+    if (!c) return fail_global(SMCX_E_INVALID, "ctx is NULL");
+    int64_t h[2];
+    smcx_status st = ctx_hip(c, hipMemcpyAsync(h, c->d_state, sizeof(h), hipMemcpyDeviceToHost, c->stream),
+                             "hipMemcpyAsync");
+    if (!st) st = ctx_hip(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    if (st) return st;
+    if (sweeps) *sweeps = c->sweeps;
+    if (attempted) *attempted = c->attempted;
+    if (accepted) *accepted = (uint64_t)h[1];
+    if (block)
+        for (int a = 0; a < 3; ++a) block[a] = c->B[a];
+    return SMCX_OK;
+}
+
+smcx_status smcx_set_state(smcx_ctx* c, const uint8_t* species, uint64_t sweep_index)
+{
+    if (!c || !species) return fail(c, SMCX_E_INVALID, "NULL argument");
+    if (c->view) return fail(c, SMCX_E_STATE, "batch views cannot be reset");
+    if (sweep_index > 0xffffffffull) return fail(c, SMCX_E_RANGE, "sweep index >= 2^32");
+    for (size_t i = 0; i < c->N; ++i)
+        if (species[i] >= c->K) return fail(c, SMCX_E_INVALID, "species[%zu] = %d >= K", i, species[i]);
+    smcx_status st = ctx_hip(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    if (!st) st = ctx_hip(c, hipMemcpy(c->h_lat.species, species, c->N, hipMemcpyHostToDevice), "hipMemcpy");
+    if (st) return st;
+    c->sweeps = sweep_index;
+    c->attempted = 0;
+    int64_t E = 0;
+    st = recompute_energy(c, &E);
+    if (st) return st;
+    int64_t init[2] = {E, 0};
+    return ctx_hip(c, hipMemcpy(c->d_state, init, sizeof(init), hipMemcpyHostToDevice), "hipMemcpy(state)");
+}
+
+smcx_status smcx_synchronize(smcx_ctx* c)
+{
+    if (!c) return fail_global(SMCX_E_INVALID, "ctx is NULL");
+    return ctx_hip(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+}
+
+smcx_status smcx_profile(smcx_ctx* c, int32_t enable)
+{
+    if (!c) return fail_global(SMCX_E_INVALID, "ctx is NULL");
+    smcx_status st = ctx_hip(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    if (st) return st;
+    for (auto& e : c->events) (void)hipEventDestroy(e);
+    c->events.clear();
+    c->profiling = enable != 0;
+    return SMCX_OK;
+}
+
+smcx_status smcx_kernel_time(smcx_ctx* c, double* total_ms, uint64_t* launches)
+{
+    if (!c) return fail_global(SMCX_E_INVALID, "ctx is NULL");
+    smcx_status st = ctx_hip(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    if (st) return st;
+    double tot = 0.0;
+    for (size_t k = 0; k + 1 < c->events.size(); k += 2) {
+        float ms = 0.f;
+        st = ctx_hip(c, hipEventElapsedTime(&ms, c->events[k], c->events[k + 1]), "hipEventElapsedTime");
+        if (st) return st;
+        tot += ms;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = c->events.size() / 2;
+    return SMCX_OK;
+}
+
+void smcx_destroy(smcx_ctx* c)
+{
+    if (!c || c->view) return;
+    ctx_release(c);
+    delete c;
+}
+
+// ---- verification hooks ------------------------------------------------------
+smcx_status smcx_threshold_table(double T, double* out)
+{
+    if (!out) return fail_global(SMCX_E_INVALID, "out is NULL");
+    smcx_status st = validate_T(T);
+    if (st) return st;
+    build_thresholds(T, out);
+    return SMCX_OK;
+}
+
+smcx_status smcx_device_thresholds(double T, const int32_t* dE, int32_t n, double* out)
+{
+    if (!dE || !out || n < 0) return fail_global(SMCX_E_INVALID, "bad argument");
+    smcx_status st = validate_T(T);
+    if (st) return st;
+    if (n == 0) return SMCX_OK;
+    double tab[kTab];
+    build_thresholds(T, tab);
+    double *d_tab = nullptr, *d_out = nullptr;
+    int32_t* d_dE = nullptr;
+    hipError_t e = hipMalloc(&d_tab, sizeof(tab));
+    if (e == hipSuccess) e = hipMalloc(&d_out, sizeof(double) * n);
+    if (e == hipSuccess) e = hipMalloc(&d_dE, sizeof(int32_t) * n);
+    if (e == hipSuccess) e = hipMemcpy(d_tab, tab, sizeof(tab), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_dE, dE, sizeof(int32_t) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_thresholds(d_tab, d_dE, n, d_out, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(out, d_out, sizeof(double) * n, hipMemcpyDeviceToHost);
+    if (d_tab) (void)hipFree(d_tab);
+    if (d_out) (void)hipFree(d_out);
+    if (d_dE) (void)hipFree(d_dE);
+    if (e != hipSuccess) return fail_global(SMCX_E_DEVICE, "device thresholds: %s", hipGetErrorString(e));
+    return SMCX_OK;
+}
+
+smcx_status smcx_device_philox(const uint32_t* ctr, const uint32_t key[2], int32_t n, uint32_t* out)
+{
+    if (!ctr || !key || !out || n < 0) return fail_global(SMCX_E_INVALID, "bad argument");
+    if (n == 0) return SMCX_OK;
+    uint32_t *d_c = nullptr, *d_o = nullptr;
+    hipError_t e = hipMalloc(&d_c, sizeof(uint32_t) * 4 * (size_t)n);
+    if (e == hipSuccess) e = hipMalloc(&d_o, sizeof(uint32_t) * 4 * (size_t)n);
+    if (e == hipSuccess) e = hipMemcpy(d_c, ctr, sizeof(uint32_t) * 4 * (size_t)n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_philox(d_c, key[0], key[1], n, d_o, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(out, d_o, sizeof(uint32_t) * 4 * (size_t)n, hipMemcpyDeviceToHost);
+    if (d_c) (void)hipFree(d_c);
+    if (d_o) (void)hipFree(d_o);
+    if (e != hipSuccess) return fail_global(SMCX_E_DEVICE, "device philox: %s", hipGetErrorString(e));
+    return SMCX_OK;
+}
+
+}  // extern "C"

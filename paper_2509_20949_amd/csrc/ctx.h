@@ -1,0 +1,51 @@
+// ctx.h -- library-internal definition of the opaque handles of smcx.h.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/smcx.h"
+#include "smcx_internal.h"
+
+struct smcx_ctx {
+    smcx_desc desc{};
+    int32_t B[3] = {0, 0, 0};
+    int K = 0, S = 0;
+    size_t N = 0;
+    int kmax = 0, smax = 0;
+    std::vector<int32_t> epi;
+    uint8_t* d_species = nullptr;
+    bool owns_species = false;
+    hipStream_t stream = nullptr;
+    bool owns_stream = false;
+    smcx::DevLattice h_lat{};
+    smcx::DevLattice* d_lat = nullptr;
+    void* d_state = nullptr;                 // int64 running energy, uint64 accepted
+    unsigned long long* d_counts = nullptr;  // pair-count scratch [kMaxS][kMaxK][kMaxK]
+    int32_t* d_wtab = nullptr;
+    double* d_tabs = nullptr;
+    int tab_cap = 0;
+    uint64_t sweeps = 0, attempted = 0;
+    double T_default = 0.0;
+    std::vector<double> sched;
+    uint64_t sched_s0 = 0;
+    uint64_t counts[smcx::kMaxS * smcx::kMaxK * smcx::kMaxK] = {};
+    bool profiling = false;
+    std::vector<hipEvent_t> events;
+    bool view = false;                       // replica view owned by a batch
+    std::string err;
+};
+
+namespace smcx {
+smcx_status fail_global(smcx_status st, const char* fmt, ...);
+smcx_status fail(smcx_ctx* c, smcx_status st, const char* fmt, ...);
+smcx_status validate_desc(const smcx_desc* d, int32_t block_out[3], bool for_gpu);
+smcx_status validate_epi(const int32_t* epi, int K, int S);
+smcx_status validate_T(double T);
+size_t n_sites(const int32_t L[3]);
+smcx_status ctx_hip(smcx_ctx* c, hipError_t e, const char* what);
+void fill_geometry(DevLattice& L, const smcx_desc* d, const int32_t B[3]);
+bool geometry_ok(const DevLattice& L);
+smcx_status recompute_energy(smcx_ctx* c, int64_t* E);
+void ctx_release(smcx_ctx* c);
+}  // namespace smcx

@@ -1,0 +1,459 @@
+// kernels.hip -- gfx950 kernels of libsmcx.
+//
+// sweep_phase: one colour phase of a Metropolis swap sweep (paper: Section
+//   "Monte Carlo simulation", Eq. (3); link cells of Section "Distributed
+//   SMC-X").  One wavefront owns one block of the shifted block grid: it
+//   stages the block and its interaction halo from HBM into LDS, runs the 54
+//   sub-colour rounds (64 lanes = the 4 x 4 x 4 same-residue cells of a 12-wide
+//   block, one trial each), writes the block and the first-neighbour ring
+//   back, and reduces its accepted energy changes.  Lanes of one round never
+//   touch each other's sites, and LDS operations of one wavefront complete in
+//   program order, so no barrier separates the rounds.
+// pair_counts: N_m[p'][p] for energy recomputation and Warren-Cowley SRO
+//   (Eq. (SRO)).
+#include "smcx_internal.h"
+
+namespace smcx {
+
+// ---------------------------------------------------------------------------
+// Species codes in LDS.  A site of species v is stored as (F + 32) * v, with
+// F = 5 bits per species field when KMAX <= 6 and F = 4 otherwise: the low 5
+// bits (the only bits a 32-bit shift reads) equal F * v, the top 3 bits equal
+// v.  One shift-add per neighbour then counts species into packed fields.
+template <int KMAX> struct Field { static constexpr int F = KMAX <= 6 ? 5 : 4; };
+
+__device__ __forceinline__ uint32_t encode2(uint32_t two_species, int F)
+{
+    // two species bytes (v0 | v1 << 8) -> ((F+32) v0) | ((F+32) v1) << 8
+    return (two_species << 5) + two_species * (uint32_t)F;
+}
+
+__device__ __forceinline__ uint32_t decode(uint32_t code) { return code >> 5; }
+
+// LDS layout of one block (see smcx_internal.h): corner array at offset 0,
+// body array at kArr.  Local cell (x, y, z):
+//   corner: (z+1)*kPP + (y+1)*kP + (x+1)       x in -1..13
+//   body:   kArr + (z+2)*kPP + (y+2)*kP + (x+2) x in -2..12
+// Offsets of the first shell from a corner site (body sites at cell offsets
+// {-1,0}^3) and from a body site (corner sites at {0,+1}^3):
+constexpr int kS1Corner = kArr;                      // + ex + ey*kP + ez*kPP, e in {0,1}
+constexpr int kS1Body = -kArr - (kPP + kP + 1);      // + ex + ey*kP + ez*kPP, e in {0,1}
+
+template <int SUB> __device__ __forceinline__ constexpr int s1base() { return SUB == 0 ? kS1Corner : kS1Body; }
+
+// Shell offsets inside one sublattice array.
+__device__ __forceinline__ constexpr int s2off(int k)
+{
+    return k == 0 ? 1 : k == 1 ? -1 : k == 2 ? kP : k == 3 ? -kP : k == 4 ? kPP : -kPP;
+}
+__device__ __forceinline__ constexpr int s3off(int k)
+{
+    // (+-1, +-1, 0), (+-1, 0, +-1), (0, +-1, +-1)
+    return k == 0 ? 1 + kP : k == 1 ? 1 - kP : k == 2 ? -1 + kP : k == 3 ? -1 - kP
+         : k == 4 ? 1 + kPP : k == 5 ? 1 - kPP : k == 6 ? -1 + kPP : k == 7 ? -1 - kPP
+         : k == 8 ? kP + kPP : k == 9 ? kP - kPP : k == 10 ? -kP + kPP : -kP - kPP;
+}
+
+// Packed species histogram of the neighbours of the site at LDS byte `a`
+// with sublattice SUB, one 32-bit word per shell.
+template <int SMAX, int SUB>
+__device__ __forceinline__ void histogram(const uint8_t* lat, int a, uint32_t (&h)[kMaxS])
+{
+    const int b1 = a + s1base<SUB>();
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const uint32_t c = lat[b1 + (e & 1) + ((e >> 1) & 1) * kP + ((e >> 2) & 1) * kPP];
+        h[0] += 1u << (c & 31);
+    }
+    if constexpr (SMAX >= 2) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const uint32_t c = lat[a + s2off(k)];
+            h[1] += 1u << (c & 31);
+        }
+    }
+    if constexpr (SMAX >= 3) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const uint32_t c = lat[a + s3off(k)];
+            h[2] += 1u << (c & 31);
+        }
+    }
+}
+
+// One trial: site at LDS byte ai (sublattice SUB), draws (u_dir, u_acc).
+// Returns through dEsum / nacc; updates the LDS image in place.
+template <int KMAX, int SMAX, int SUB>
+__device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u_dir, uint32_t u_acc, bool valid,
+                                      const int32_t* wtab, const double* tab, int64_t& dEsum,
+                                      uint32_t& nacc)
+{
+    constexpr int F = Field<KMAX>::F;
+    constexpr int WR = wrow(KMAX, SMAX);
+    const uint32_t dir = u_dir >> 29;
+    const int aj = ai + s1base<SUB>() + (int)(dir & 1u) + (int)((dir >> 1) & 1u) * kP +
+                   (int)((dir >> 2) & 1u) * kPP;
+    const uint32_t ci = lat[ai];
+    const uint32_t cj = lat[aj];
+
+    // Species histograms of both neighbourhoods (the partner is counted in
+    // the first shell of i and i in that of j; the constant term undoes it).
+    uint32_t hi[kMaxS], hj[kMaxS];
+    constexpr uint32_t bias = F == 5 ? 0x10u * (1u | 1u << 5 | 1u << 10 | 1u << 15 | 1u << 20 | 1u << 25) : 0u;
+#pragma unroll
+    for (int s = 0; s < kMaxS; ++s) { hi[s] = bias; hj[s] = 0u; }
+    histogram<SMAX, SUB>(lat, ai, hi);
+    histogram<SMAX, 1 - SUB>(lat, aj, hj);
+
+    // lanes without a site in this round may decode stale halo bytes: clamp
+    // the row index into the table (their result is discarded)
+    const uint32_t a = min(decode(ci), (uint32_t)(KMAX - 1)), b = min(decode(cj), (uint32_t)(KMAX - 1));
+    const int32_t* w = wtab + (a * KMAX + b) * WR;
+    // Accumulate modulo 2^32: the constant may leave the int32 range for
+    // extreme tables, the true dE (|dE| < 2^29) never does.
+    uint32_t acc = (uint32_t)w[SMAX * KMAX];
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) {
+        if constexpr (F == 5) {
+            const uint32_t d = hi[s] - hj[s];   // fields 16 + n_i - n_j, no borrows
+#pragma unroll
+            for (int p = 0; p < KMAX; ++p)
+                acc += (uint32_t)__mul24((int32_t)((d >> (5 * p)) & 31u), w[s * KMAX + p]);
+        } else {
+#pragma unroll
+            for (int p = 0; p < KMAX; ++p)
+                acc += (uint32_t)__mul24((int32_t)((hi[s] >> (4 * p)) & 15u) -
+                                             (int32_t)((hj[s] >> (4 * p)) & 15u),
+                                         w[s * KMAX + p]);
+        }
+    }
+    const int32_t dE = (int32_t)acc;
+
+    // Metropolis decision, Eq. (3), on the FP64 byte tables.
+    const int e = dE < 1 ? 1 : (dE > (1 << 24) - 1 ? (1 << 24) - 1 : dE);
+    const double thr = (tab[512 + (e >> 16)] * tab[256 + ((e >> 8) & 255)]) * tab[e & 255];
+    const bool up_ok = dE < (1 << 24) && (double)u_acc < thr;
+    const bool accept = valid && ci != cj && (dE <= 0 || up_ok);
+    if (accept) {
+        lat[ai] = (uint8_t)cj;
+        lat[aj] = (uint8_t)ci;
+        dEsum += dE;
+        nacc += 1u;
+    }
+}
+
+__device__ __forceinline__ int wrap_add(int v, int L)   // v in [-L, 2L)
+{
+    v = v < 0 ? v + L : v;
+    return v >= L ? v - L : v;
+}
+
+// ---------------------------------------------------------------------------
+template <int KMAX, int SMAX>
+__global__ __launch_bounds__(kWave * kWavesPerGroup)
+void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __restrict__ items,
+                        int t, int colour)
+{
+    constexpr int F = Field<KMAX>::F;
+    constexpr int WR = wrow(KMAX, SMAX);
+    __shared__ double s_tab[kTab];
+    __shared__ int32_t s_w[KMAX * KMAX * WR];
+    __shared__ __attribute__((aligned(16))) uint8_t s_lat[kWavesPerGroup * kWaveLds];
+
+    const int wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    int li = 0, f = blockIdx.x * kWavesPerGroup;
+    if (items) {
+        li = items[blockIdx.x].lattice;
+        f = items[blockIdx.x].first_block;
+    }
+    const DevLattice& D = lats[li];
+    const uint32_t s = D.sweep0 + (uint32_t)t;
+
+    // per-workgroup tables
+    {
+        int ti = (int)(s - D.tab_s0);
+        ti = ti < 0 ? 0 : (ti >= D.n_tabs ? D.n_tabs - 1 : ti);
+        const double* tab = D.tabs + (size_t)ti * kTab;
+        for (int k = threadIdx.x; k < kTab; k += blockDim.x) s_tab[k] = tab[k];
+        for (int k = threadIdx.x; k < KMAX * KMAX * WR; k += blockDim.x) s_w[k] = D.wtab[k];
+    }
+    __syncthreads();
+
+    f += wave;
+    if (f >= D.blocks_per_colour) return;   // no later barrier
+
+    // block coordinates: same-colour blocks are every other block per axis
+    const int hx = D.nb[0] >> 1, hy = D.nb[1] >> 1;
+    const int kx = 2 * (f % hx) + (colour & 1);
+    const int ky = 2 * ((f / hx) % hy) + ((colour >> 1) & 1);
+    const int kz = 2 * (f / (hx * hy)) + ((colour >> 2) & 1);
+    const int Lx = D.L[0], Ly = D.L[1], Lz = D.L[2];
+
+    // origin shift of sweep s (same for every wave of the sweep)
+    uint32_t sh[4] = {0u, 0u, s, 8u};
+    philox4x32_10(sh, D.key[0], D.key[1]);
+    const int ox = (int)(((uint64_t)sh[0] * (uint32_t)Lx) >> 32);
+    const int oy = (int)(((uint64_t)sh[1] * (uint32_t)Ly) >> 32);
+    const int oz = (int)(((uint64_t)sh[2] * (uint32_t)Lz) >> 32);
+
+    const int x0 = (int)(((int64_t)kx * Lx) / D.nb[0]);
+    const int y0 = (int)(((int64_t)ky * Ly) / D.nb[1]);
+    const int z0 = (int)(((int64_t)kz * Lz) / D.nb[2]);
+    const int wx = (int)(((int64_t)(kx + 1) * Lx) / D.nb[0]) - x0;
+    const int wy = (int)(((int64_t)(ky + 1) * Ly) / D.nb[1]) - y0;
+    const int wz = (int)(((int64_t)(kz + 1) * Lz) / D.nb[2]) - z0;
+    // global coordinate of local cell 0
+    const int gx0 = wrap_add(x0 + ox, Lx), gy0 = wrap_add(y0 + oy, Ly), gz0 = wrap_add(z0 + oz, Lz);
+
+    uint8_t* lat = s_lat + wave * kWaveLds;
+    uint8_t* __restrict__ g = D.species;
+
+    // ---- stage block + halo: local cells -2..w+1 on each axis ----
+    {
+        const int lx = (lane & 15) - 2;
+        const bool okx = lx <= wx + 1;
+        const int gx = wrap_add(gx0 + lx, Lx);
+        for (int r = lane >> 4; r < 256; r += 4) {
+            const int ly = (r & 15) - 2, lz = (r >> 4) - 2;
+            if (!okx || ly > wy + 1 || lz > wz + 1) continue;
+            const int gy = wrap_add(gy0 + ly, Ly), gz = wrap_add(gz0 + lz, Lz);
+            const size_t cell = ((size_t)gz * Ly + gy) * Lx + gx;
+            const uint32_t v = encode2(*(const uint16_t*)(g + 2 * cell), F);
+            if (lx >= -1 && ly >= -1 && lz >= -1)
+                lat[(lz + 1) * kPP + (ly + 1) * kP + (lx + 1)] = (uint8_t)v;
+            if (lx <= wx && ly <= wy && lz <= wz)
+                lat[kArr + (lz + 2) * kPP + (ly + 2) * kP + (lx + 2)] = (uint8_t)(v >> 8);
+        }
+    }
+
+    // ---- 27 residue classes x 2 sublattices = 54 rounds ----
+    const int ix = lane & 3, iy = (lane >> 2) & 3, iz = lane >> 4;
+    int64_t dEsum = 0;
+    uint32_t nacc = 0;
+    const uint32_t k0 = D.key[0], k1 = D.key[1];
+    for (int m = 0; m < 27; ++m) {
+        const int rx = m % 3, ry = (m / 3) % 3, rz = m / 9;
+        const int lx = rx + 3 * ix, ly = ry + 3 * iy, lz = rz + 3 * iz;
+        const bool valid = lx < wx && ly < wy && lz < wz;
+        const int gx = wrap_add(gx0 + lx, Lx), gy = wrap_add(gy0 + ly, Ly), gz = wrap_add(gz0 + lz, Lz);
+        const uint64_t cell = ((uint64_t)gz * (uint32_t)Ly + (uint32_t)gy) * (uint32_t)Lx + (uint32_t)gx;
+        uint32_t r[4] = {(uint32_t)cell, (uint32_t)(cell >> 32), s, (uint32_t)colour};
+        philox4x32_10(r, k0, k1);
+        const int ac = (lz + 1) * kPP + (ly + 1) * kP + (lx + 1);
+        const int ab = kArr + (lz + 2) * kPP + (ly + 2) * kP + (lx + 2);
+        trial<KMAX, SMAX, 0>(lat, ac, r[0], r[1], valid, s_w, s_tab, dEsum, nacc);
+        __builtin_amdgcn_wave_barrier();
+        trial<KMAX, SMAX, 1>(lat, ab, r[2], r[3], valid, s_w, s_tab, dEsum, nacc);
+        __builtin_amdgcn_wave_barrier();
+    }
+
+    // ---- write back: corner cells 0..w, body cells -1..w-1 ----
+    {
+        const int lx = (lane & 15) - 1;
+        const bool okx = lx <= wx;
+        const int gx = wrap_add(gx0 + lx, Lx);
+        for (int r = lane >> 4; r < 256; r += 4) {
+            const int ly = (r & 15) - 1, lz = (r >> 4) - 1;
+            if (!okx || ly > wy || lz > wz) continue;
+            const bool corner = lx >= 0 && ly >= 0 && lz >= 0;
+            const bool body = lx < wx && ly < wy && lz < wz;
+            if (!corner && !body) continue;
+            const int gy = wrap_add(gy0 + ly, Ly), gz = wrap_add(gz0 + lz, Lz);
+            const size_t cell = ((size_t)gz * Ly + gy) * Lx + gx;
+            const uint32_t vc = corner ? decode(lat[(lz + 1) * kPP + (ly + 1) * kP + (lx + 1)]) : 0u;
+            const uint32_t vb = body ? decode(lat[kArr + (lz + 2) * kPP + (ly + 2) * kP + (lx + 2)]) : 0u;
+            if (corner && body)
+                *(uint16_t*)(g + 2 * cell) = (uint16_t)(vc | vb << 8);
+            else if (corner)
+                g[2 * cell] = (uint8_t)vc;
+            else
+                g[2 * cell + 1] = (uint8_t)vb;
+        }
+    }
+
+    // ---- wavefront reduction of the energy change and accepted count ----
+    uint64_t sum = (uint64_t)dEsum;
+    uint32_t cnt = nacc;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)sum, o, kWave);
+        const uint32_t hi = __shfl_xor((uint32_t)(sum >> 32), o, kWave);
+        sum += (uint64_t)lo | ((uint64_t)hi << 32);
+        cnt += __shfl_xor(cnt, o, kWave);
+    }
+    if (lane == 0) {
+        if (sum) atomicAdd((unsigned long long*)D.energy, (unsigned long long)sum);
+        if (cnt) atomicAdd(D.accepted, (unsigned long long)cnt);
+    }
+}
+
+int kmax_for(int K)
+{
+    if (K <= 2) return 2;
+    if (K <= 3) return 3;
+    if (K <= 4) return 4;
+    if (K <= 5) return 5;
+    if (K <= 6) return 6;
+    return 8;
+}
+
+template <int KMAX, int SMAX>
+static hipError_t launch_t(const DevLattice* d_lat, const WorkItem* d_items, int n_groups, int t,
+                           int colour, hipStream_t stream)
+{
+    hipLaunchKernelGGL((sweep_phase_kernel<KMAX, SMAX>), dim3(n_groups), dim3(kWave * kWavesPerGroup), 0,
+                       stream, d_lat, d_items, t, colour);
+    return hipGetLastError();
+}
+
+template <int KMAX>
+static hipError_t launch_k(const DevLattice* d_lat, const WorkItem* d_items, int n_groups, int t,
+                           int colour, int smax, hipStream_t stream)
+{
+    switch (smax) {
+    case 1: return launch_t<KMAX, 1>(d_lat, d_items, n_groups, t, colour, stream);
+    case 2: return launch_t<KMAX, 2>(d_lat, d_items, n_groups, t, colour, stream);
+    case 3: return launch_t<KMAX, 3>(d_lat, d_items, n_groups, t, colour, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_sweep_phase(const DevLattice* d_lat, const WorkItem* d_items, int n_groups, int t,
+                              int colour, int kmax, int smax, hipStream_t stream)
+{
+    if (n_groups <= 0) return hipSuccess;
+    switch (kmax) {
+    case 2: return launch_k<2>(d_lat, d_items, n_groups, t, colour, smax, stream);
+    case 3: return launch_k<3>(d_lat, d_items, n_groups, t, colour, smax, stream);
+    case 4: return launch_k<4>(d_lat, d_items, n_groups, t, colour, smax, stream);
+    case 5: return launch_k<5>(d_lat, d_items, n_groups, t, colour, smax, stream);
+    case 6: return launch_k<6>(d_lat, d_items, n_groups, t, colour, smax, stream);
+    case 8: return launch_k<8>(d_lat, d_items, n_groups, t, colour, smax, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Pair counts N_m[p'][p] (Eq. (SRO) numerator; also the energy, as
+// E = 1/2 sum N_m[p'][p] V_m(p', p)).  One thread per cell, neighbours read
+// straight from HBM through the caches; per-workgroup LDS counters.
+__global__ __launch_bounds__(256)
+void pair_counts_kernel(const uint8_t* __restrict__ g, int Lx, int Ly, int Lz, int K, int S,
+                        unsigned long long* __restrict__ counts)
+{
+    __shared__ unsigned int c[kMaxS * kMaxK * kMaxK];
+    for (int k = threadIdx.x; k < kMaxS * kMaxK * kMaxK; k += blockDim.x) c[k] = 0u;
+    __syncthreads();
+    const size_t ncell = (size_t)Lx * Ly * Lz;
+    for (size_t cell = (size_t)blockIdx.x * blockDim.x + threadIdx.x; cell < ncell;
+         cell += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(cell % Lx), y = (int)((cell / Lx) % Ly), z = (int)(cell / ((size_t)Lx * Ly));
+        auto at = [&](int X, int Y, int Z, int b) -> uint32_t {
+            X = X < 0 ? X + Lx : (X >= Lx ? X - Lx : X);
+            Y = Y < 0 ? Y + Ly : (Y >= Ly ? Y - Ly : Y);
+            Z = Z < 0 ? Z + Lz : (Z >= Lz ? Z - Lz : Z);
+            return g[2 * (((size_t)Z * Ly + Y) * Lx + X) + b];
+        };
+        for (int b = 0; b < 2; ++b) {
+            const uint32_t si = at(x, y, z, b);
+            uint32_t h[3] = {0u, 0u, 0u};   // 4-bit species fields per shell
+            // shell 1: other sublattice, cells {-1,0}^3 (corner) or {0,1}^3 (body)
+            for (int e = 0; e < 8; ++e) {
+                const int d = b == 0 ? -1 : 0;
+                h[0] += 1u << (4 * at(x + d + (e & 1), y + d + ((e >> 1) & 1), z + d + ((e >> 2) & 1), 1 - b));
+            }
+            if (S >= 2) {
+                h[1] += 1u << (4 * at(x + 1, y, z, b));
+                h[1] += 1u << (4 * at(x - 1, y, z, b));
+                h[1] += 1u << (4 * at(x, y + 1, z, b));
+                h[1] += 1u << (4 * at(x, y - 1, z, b));
+                h[1] += 1u << (4 * at(x, y, z + 1, b));
+                h[1] += 1u << (4 * at(x, y, z - 1, b));
+            }
+            if (S >= 3) {
+                for (int u = -1; u <= 1; u += 2)
+                    for (int v = -1; v <= 1; v += 2) {
+                        h[2] += 1u << (4 * at(x + u, y + v, z, b));
+                        h[2] += 1u << (4 * at(x + u, y, z + v, b));
+                        h[2] += 1u << (4 * at(x, y + u, z + v, b));
+                    }
+            }
+            for (int m = 0; m < S; ++m)
+                for (int p = 0; p < K; ++p) {
+                    const uint32_t n = (h[m] >> (4 * p)) & 15u;
+                    if (n) atomicAdd(&c[(m * kMaxK + si) * kMaxK + p], n);
+                }
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kMaxS * kMaxK * kMaxK; k += blockDim.x)
+        if (c[k]) atomicAdd(&counts[k], (unsigned long long)c[k]);
+}
+
+hipError_t launch_pair_counts(const uint8_t* species, const int32_t L[3], int K, int S,
+                              unsigned long long* d_counts, hipStream_t stream)
+{
+    const size_t ncell = (size_t)L[0] * L[1] * L[2];
+    size_t groups = (ncell + 255) / 256;
+    if (groups > 8192) groups = 8192;
+    hipLaunchKernelGGL(pair_counts_kernel, dim3((unsigned)groups), dim3(256), 0, stream, species, L[0], L[1],
+                       L[2], K, S, d_counts);
+    return hipGetLastError();
+}
+
+__global__ void species_max_kernel(const uint8_t* __restrict__ g, size_t n, unsigned int* __restrict__ out)
+{
+    unsigned int m = 0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        m = max(m, (unsigned int)g[i]);
+    for (int o = 32; o >= 1; o >>= 1) m = max(m, (unsigned int)__shfl_xor(m, o, kWave));
+    if ((threadIdx.x % kWave) == 0) atomicMax(out, m);
+}
+
+hipError_t launch_species_max(const uint8_t* species, size_t n, unsigned int* d_max, hipStream_t stream)
+{
+    size_t groups = (n + 255) / 256;
+    if (groups > 4096) groups = 4096;
+    if (groups == 0) groups = 1;
+    hipLaunchKernelGGL(species_max_kernel, dim3((unsigned)groups), dim3(256), 0, stream, species, n, d_max);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Verification hooks: the device's FP64 threshold products and Philox.
+__global__ void thresholds_kernel(const double* __restrict__ tab, const int32_t* __restrict__ dE, int n,
+                                  double* __restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int e = dE[k] < 1 ? 1 : (dE[k] > (1 << 24) - 1 ? (1 << 24) - 1 : dE[k]);
+    out[k] = (tab[512 + (e >> 16)] * tab[256 + ((e >> 8) & 255)]) * tab[e & 255];
+}
+
+hipError_t launch_thresholds(const double* d_tab, const int32_t* d_dE, int n, double* d_out, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(thresholds_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, d_tab, d_dE, n, d_out);
+    return hipGetLastError();
+}
+
+__global__ void philox_kernel(const uint32_t* __restrict__ ctr, uint32_t k0, uint32_t k1, int n,
+                              uint32_t* __restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    uint32_t c[4] = {ctr[4 * k], ctr[4 * k + 1], ctr[4 * k + 2], ctr[4 * k + 3]};
+    philox4x32_10(c, k0, k1);
+    for (int w = 0; w < 4; ++w) out[4 * k + w] = c[w];
+}
+
+hipError_t launch_philox(const uint32_t* d_ctr, uint32_t k0, uint32_t k1, int n, uint32_t* d_out,
+                         hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(philox_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, d_ctr, k0, k1, n, d_out);
+    return hipGetLastError();
+}
+
+}  // namespace smcx

@@ -1,0 +1,108 @@
+// smcx_internal.h -- types shared by the host and device parts of libsmcx.
+//
+// Nothing here is part of the C ABI (include/smcx.h).  The library is written
+// for gfx950 (CDNA4, wave64) only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace smcx {
+
+constexpr int kWave = 64;            // CDNA wavefront width
+constexpr int kWavesPerGroup = 4;    // blocks (one per wave) per workgroup
+constexpr int kMaxBlock = 12;        // widest block: 4 x 4 x 4 cells per sub-colour round
+constexpr int kMaxK = 8;
+constexpr int kMaxS = 3;
+
+// LDS image of one block: two byte arrays (corner and body sublattice) of
+// 15 x 15 x 15 cells.  Corner array covers local cells -1..13, body array
+// -2..12, so a block of width <= 12 plus its interaction halo fits.
+constexpr int kP = 15;               // row pitch (cells)
+constexpr int kPP = kP * kP;         // plane pitch
+constexpr int kArr = 3376;           // bytes per sublattice array (15^3 = 3375, padded)
+constexpr int kWaveLds = 2 * kArr;   // bytes per wave
+
+// Threshold tables: T0 | T1 | T2, 256 doubles each.
+constexpr int kTab = 768;
+
+// Row of the pair-weight table for one (sigma_i, sigma_j) = (a, b):
+// W[s][p] = V_s(b, p) - V_s(a, p) for s < SMAX, p < KMAX, then a constant.
+__host__ __device__ constexpr int wrow(int kmax, int smax) { return ((smax * kmax + 1) + 3) & ~3; }
+
+// Per-lattice state the kernels read (device memory).
+struct DevLattice {
+    uint8_t* species;        // 2*Lx*Ly*Lz bytes, canonical order
+    const double* tabs;      // n_tabs x 768 thresholds
+    const int32_t* wtab;     // KMAX*KMAX rows of wrow(KMAX, SMAX) ints
+    int64_t* energy;         // running energy (micro-eV)
+    unsigned long long* accepted;
+    int32_t L[3];
+    int32_t nb[3];           // blocks per axis (even)
+    uint32_t key[2];
+    uint32_t sweep0;         // sweep index of launch step t = 0
+    uint32_t tab_s0;         // sweep index of tabs[0]
+    int32_t n_tabs;          // later sweeps reuse the last table
+    int32_t K;
+    int32_t blocks_per_colour;
+    int32_t pad;
+};
+
+// One workgroup's share of a batched phase: kWavesPerGroup consecutive
+// same-colour blocks of one lattice.
+struct WorkItem {
+    int32_t lattice;
+    int32_t first_block;     // index among that lattice's blocks of the colour
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64
+// multiplies; key bumped by the Weyl constants between rounds.
+__host__ __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+    uint32_t x0 = c[0], x1 = c[1], x2 = c[2], x3 = c[3];
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * x0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        x1 = (uint32_t)p1;
+        x3 = (uint32_t)p0;
+        x0 = n0;
+        x2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    c[0] = x0; c[1] = x1; c[2] = x2; c[3] = x3;
+}
+
+// Per-axis schedule: number of blocks for L cells and width parameter B.
+__host__ __device__ inline int axis_blocks(int L, int B)
+{
+    int n = 2 * ((L + 2 * B - 1) / (2 * B));
+    const int cap = 2 * (L / 4);
+    if (n > cap) n = cap;
+    if (n < 2) n = 2;
+    return n;
+}
+
+// Host helpers (tables.cpp).
+void build_thresholds(double T, double* out768);
+void build_wtab(const int32_t* epi, int K, int S, int kmax, int smax, int32_t* out);
+
+// Launchers (kernels.hip).  Return hipSuccess or the launch error.
+hipError_t launch_sweep_phase(const DevLattice* d_lat, const WorkItem* d_items, int n_groups,
+                              int t, int colour, int kmax, int smax, hipStream_t stream);
+hipError_t launch_pair_counts(const uint8_t* species, const int32_t L[3], int K, int S,
+                              unsigned long long* d_counts, hipStream_t stream);
+hipError_t launch_species_max(const uint8_t* species, size_t n, unsigned int* d_max, hipStream_t stream);
+hipError_t launch_thresholds(const double* d_tab, const int32_t* d_dE, int n, double* d_out, hipStream_t stream);
+hipError_t launch_philox(const uint32_t* d_ctr, uint32_t k0, uint32_t k1, int n, uint32_t* d_out,
+                         hipStream_t stream);
+
+// Kernel template keys: the smallest instantiated KMAX >= K.
+int kmax_for(int K);
+
+}  // namespace smcx

@@ -64,9 +64,11 @@ def dirichlet_counts(K: int, N: int, alpha: float, rng: np.random.Generator) -> 
 
 
 def configuration(counts, rng: np.random.Generator) -> np.ndarray:
-    """Uniformly random arrangement (canonical site order) of the multiset."""
+    """Uniformly random arrangement (canonical site order) of the multiset
+    (in-place Fisher-Yates shuffle of the sorted species array)."""
     sigma = np.repeat(np.arange(len(counts), dtype=np.uint8), np.asarray(counts))
-    return sigma[rng.permutation(sigma.size)].astype(np.uint8)
+    rng.shuffle(sigma)
+    return sigma
 
 
 def linear_anneal(T0: float, T1: float, n: int) -> np.ndarray:

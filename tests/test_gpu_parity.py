@@ -1,0 +1,214 @@
+"""GPU parity: the HIP library against the CPU oracle, through the C ABI.
+
+The bar is bit-for-bit: species array and int64 energy after every sweep,
+the accepted count, pair counts / SRO, the device's Philox words and FP64
+threshold products.  Inputs come from the seeded generators in
+paper_2509_20949_amd.workloads; the oracle never sees library output.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2509_20949_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def note(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def smcx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_20949_amd import smcx as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module", autouse=True)
+def oracle_threads(orc):
+    orc.set_threads(min(16, os.cpu_count() or 1))
+    yield
+    orc.set_threads(1)
+
+
+def run_parity(smcx, orc, job, block, n_sweeps, T=None, every=1, check_sro=False):
+    """Advance GPU and oracle side by side; compare after every `every` sweeps."""
+    T = job.T if T is None else T
+    note(f"{job.name or 'lattice'} L={job.L} K={job.K} S={job.S} B={block} sweeps={n_sweeps}")
+    lat = smcx.Lattice(job.L, job.epi, job.sigma, job.seed, float(T[0]), block=block)
+    ref = orc.OracleState(job.L, block, job.epi, job.sigma, job.seed)
+    try:
+        if len(set(np.asarray(T[:n_sweeps]).tolist())) > 1:
+            lat.set_schedule(T[:n_sweeps])
+        assert lat.energy() == int(ref.E[0])
+        done = 0
+        while done < n_sweeps:
+            k = min(every, n_sweeps - done)
+            lat.sweep(k)
+            ref.sweep(T[done:done + k], k)
+            done += k
+            got = lat.config()
+            if not np.array_equal(got, ref.sigma):
+                bad = np.nonzero(got != ref.sigma)[0]
+                raise AssertionError(f"config differs after sweep {done}: {bad.size} sites, first {bad[:8]}")
+            assert lat.energy() == int(ref.E[0]), f"energy differs after sweep {done}"
+            if check_sro:
+                alpha, counts = lat.sro()
+                a_ref, c_ref = orc.sro(job.L, job.S, job.K, ref.sigma)
+                assert np.array_equal(counts, c_ref)
+                assert np.array_equal(np.isnan(alpha), np.isnan(a_ref))
+                assert np.allclose(alpha, a_ref, rtol=0, atol=1e-12, equal_nan=True)
+        st = lat.stats()
+        assert st["accepted"] == int(ref.accepted[0])
+        if job.K > 1 and len(np.unique(job.sigma)) > 1:
+            # the trajectory really moved (guards against two idle sides)
+            assert st["accepted"] > 0 and not np.array_equal(ref.sigma, job.sigma)
+        assert st["attempted"] == n_sweeps * job.N
+        assert lat.energy_recompute() == int(ref.E[0])
+        return lat.energy(), st
+    finally:
+        lat.close()
+
+
+def test_device_philox_matches_oracle(smcx, orc):
+    note("device philox")
+    rng = np.random.default_rng(1)
+    ctr = rng.integers(0, 2**32, size=(4096, 4), dtype=np.uint64).astype(np.uint32)
+    key = np.array([0xDEADBEEF, 0x12345678], np.uint32)
+    got = smcx.smcx_device_philox(ctr, key)
+    for k in range(0, 4096, 37):
+        assert np.array_equal(got[k], orc.philox4x32(ctr[k], key))
+
+
+@pytest.mark.parametrize("T", [1.0, 250.0, 800.0, 2000.0, 5000.0])
+def test_device_fp64_threshold_products(smcx, orc, T):
+    """The device's FP64 products of the byte tables equal the oracle's bits
+    (IEEE round to nearest, no contraction), including tiny and denormal
+    products at low temperature."""
+    note(f"device thresholds T={T}")
+    rng = np.random.default_rng(int(T))
+    dE = np.concatenate([np.arange(1, 2000), rng.integers(1, 1 << 24, 20000),
+                         [(1 << 24) - 1, 65535, 65536, 65537, 255, 256, 257]]).astype(np.int32)
+    got = smcx.smcx_device_thresholds(T, dE)
+    tab = orc.thresholds(T)
+    want = np.array([(tab[512 + (e >> 16)] * tab[256 + ((e >> 8) & 255)]) * tab[e & 255] for e in dE.tolist()])
+    assert got.tobytes() == want.tobytes()
+
+
+def test_config1_parity_every_sweep(smcx, orc):
+    job = W.config1(n_sweeps=100)
+    run_parity(smcx, orc, job, (12, 12, 12), 100)
+
+
+@pytest.mark.parametrize("block", [(2, 2, 2), (3, 4, 2), (4, 4, 4)])
+def test_config1_parity_small_blocks(smcx, orc, block):
+    job = W.config1(n_sweeps=30)
+    run_parity(smcx, orc, job, block, 30)
+
+
+def test_16cube_three_shells(smcx, orc):
+    job = W.lattice_job((16, 16, 16), 5, 3, 30.0, np.full(40, 800.0), stream=31, name="bcc16_k5_s3")
+    run_parity(smcx, orc, job, (12, 12, 12), 40, check_sro=True)
+
+
+@pytest.mark.parametrize("L,block", [((13, 9, 22), (5, 4, 12)), ((4, 4, 4), (2, 2, 2)),
+                                     ((5, 7, 31), (12, 3, 7)), ((26, 25, 27), (12, 12, 12)),
+                                     ((37, 12, 9), (10, 6, 4))])
+def test_ragged_lattices(smcx, orc, L, block):
+    job = W.lattice_job(L, 3, 3, 40.0, np.full(12, 1100.0), stream=41, name="ragged")
+    run_parity(smcx, orc, job, block, 12)
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("S", [1, 2, 3])
+def test_every_species_and_shell_count(smcx, orc, K, S):
+    job = W.lattice_job((8, 9, 10), K, S, 25.0, np.full(5, 900.0), stream=50 + K, name=f"K{K}S{S}")
+    run_parity(smcx, orc, job, (4, 5, 6), 5)
+
+
+def test_extreme_interactions_and_temperatures(smcx, orc):
+    rng = np.random.default_rng(9)
+    K, S = 4, 3
+    v = rng.choice([-(1 << 22) + 1, (1 << 22) - 1, 0, 123456], size=(S, K, K)).astype(np.int32)
+    epi = np.triu(v) + np.transpose(np.triu(v, 1), (0, 2, 1))
+    sigma = W.configuration(W.equiatomic(K, W.n_sites((10, 10, 10))), rng)
+    for T in (1.0, 5000.0):
+        job = W.Lattice((10, 10, 10), epi, sigma, 77, np.full(6, T), name=f"extreme T={T}")
+        run_parity(smcx, orc, job, (5, 5, 5), 6)
+
+
+def test_anneal_schedule_config2_prefix(smcx, orc):
+    """64^3 quinary, 3 shells, linear anneal 2000 K -> 600 K: per-sweep
+    parity of configuration, energy and SRO over the first 40 sweeps."""
+    job = W.config2(n_sweeps=40)
+    run_parity(smcx, orc, job, (12, 12, 12), 40, check_sro=True)
+
+
+def test_checkpoint_resume_is_bit_identical(smcx, orc):
+    job = W.lattice_job((12, 12, 12), 5, 3, 30.0, np.full(20, 900.0), stream=61, name="resume")
+    note("resume")
+    a = smcx.Lattice(job.L, job.epi, job.sigma, job.seed, 900.0)
+    try:
+        a.sweep(20)
+        full = a.config()
+        E_full = a.energy()
+    finally:
+        a.close()
+    b = smcx.Lattice(job.L, job.epi, job.sigma, job.seed, 900.0)
+    try:
+        b.sweep(9)
+        mid = b.config()
+    finally:
+        b.close()
+    c = smcx.Lattice(job.L, job.epi, mid, job.seed, 900.0)
+    try:
+        smcx.smcx_set_state(c.ctx, mid, 9)
+        c.sweep(11)
+        assert np.array_equal(c.config(), full)
+        assert c.energy() == E_full
+    finally:
+        c.close()
+
+
+def test_zero_sweeps_and_uniform_lattice(smcx, orc):
+    job = W.lattice_job((6, 6, 6), 1, 3, 30.0, np.full(3, 900.0), stream=62, name="uniform")
+    note("uniform")
+    lat = smcx.Lattice(job.L, job.epi, job.sigma, job.seed, 900.0)
+    try:
+        E0 = lat.energy()
+        lat.sweep(0)
+        lat.sweep(3)
+        assert lat.energy() == E0 and lat.stats()["accepted"] == 0
+        assert np.array_equal(lat.config(), job.sigma)
+    finally:
+        lat.close()
+
+
+def test_create_device_borrows_torch_memory(smcx, orc):
+    import torch
+    job = W.lattice_job((10, 11, 12), 4, 3, 30.0, np.full(6, 950.0), stream=63, name="device")
+    note("create_device")
+    dev = torch.from_numpy(job.sigma.copy()).to("cuda:0")
+    stream = torch.cuda.Stream()
+    d = smcx.make_desc(job.L, job.K, job.S, (5, 5, 5), job.seed)
+    ctx = smcx.smcx_create_device(d, dev.data_ptr(), job.epi, 950.0, stream.cuda_stream)
+    ref = orc.OracleState(job.L, (5, 5, 5), job.epi, job.sigma, job.seed)
+    try:
+        smcx.smcx_sweep(ctx, 6)
+        ref.sweep(950.0, 6)
+        smcx.smcx_synchronize(ctx)
+        assert np.array_equal(dev.cpu().numpy(), ref.sigma)
+        assert smcx.smcx_energy(ctx) == int(ref.E[0])
+    finally:
+        smcx.smcx_destroy(ctx)
+    bad = torch.full((job.N,), 9, dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(smcx.SmcxError) as e:
+        smcx.smcx_create_device(d, bad.data_ptr(), job.epi, 950.0, stream.cuda_stream)
+    assert e.value.status == smcx.E_INVALID

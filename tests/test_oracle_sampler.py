@@ -165,3 +165,21 @@ def test_bcc_ising_order_disorder_temperature(orc):
         ms[f] = float(np.mean(vals))
     assert ms[0.7] > 0.6, ms
     assert ms[1.5] < 0.2, ms
+
+
+def test_threaded_oracle_is_bit_identical(orc):
+    """Trials of one (colour, sub-colour) set never interact, so running
+    them on several threads must reproduce the one-thread trajectory."""
+    job = W.lattice_job((24, 26, 25), 5, 3, 30.0, np.full(3, 700.0), stream=21)
+    runs = []
+    for nt in (1, 4):
+        orc.set_threads(nt)
+        try:
+            st = orc.OracleState(job.L, (12, 12, 12), job.epi, job.sigma, job.seed)
+            Et, Ct = st.sweep(job.T, 3, trace_E=True, trace_counts=True)
+            runs.append((st.sigma.copy(), Et, Ct, int(st.accepted[0])))
+        finally:
+            orc.set_threads(1)
+    a, b = runs
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert np.array_equal(a[2], b[2]) and a[3] == b[3]
