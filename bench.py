@@ -1,0 +1,187 @@
+"""Benchmark: attempted Metropolis swaps per second on one MI355X.
+
+Workload (one step = one full sweep, every site tried once): BCC 512^3 cells
+(268,435,456 sites), 5 species with a Dirichlet(5) composition, EPI over
+shells 1-3 (int32 micro-eV, entries ~ N(0, 30 meV)), T = 800 K, synthetic
+seeded inputs shaped like the paper's quinary alloy workload.  The lattice
+is resident in HBM before the timed region starts.
+
+Prints one JSON line (the driver's contract) with, besides throughput:
+  roofline      the sweep kernel against the integer-VALU peak (the path is
+                ALU-bound), timed with HIP events on the stream it runs on;
+  hbm           the same kernel's algorithmic HBM bytes against 8 TB/s;
+  cpu_baseline  the CPU oracle timed on this host on one full sweep of the
+                same lattice (bounded sample), with the threads it used;
+  check         running energy vs a full recompute after the timed sweeps.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# --- roofline constants (MI355X, gfx950) -------------------------------------
+N_CU = 256
+CLOCK_HZ = 2.4e9
+LANES_PER_CU_CYCLE = 64          # 4 SIMDs x 16 lanes: one wave64 VALU op per SIMD per 4 cycles
+VALU_PEAK = N_CU * LANES_PER_CU_CYCLE * CLOCK_HZ   # lane-ops/s = 3.93e13
+HBM_PEAK = 8.0e12                 # bytes/s
+
+# Algorithmic integer work of one trial (K = 5 species, S = 3 shells), counted
+# in VALU issue slots of one lane (quarter-rate 32x32->64 multiplies = 4,
+# FP64 multiply/convert/compare = 2), the minimum the method needs:
+#   Philox4x32-10, one call per two trials: 10 x (2 x 4 + 2) / 2   = 50
+#   species counts of the 2 x 26 neighbours, one op each           = 52
+#   dE from the counts: 3 shell differences + 15 x (extract + mad) = 33
+#   Metropolis test: 2 FP64 mul + convert + compare                =  8
+OPS_PER_TRIAL = 50 + 52 + 33 + 8          # = 143
+# Algorithmic HBM bytes of one trial: each site is read once and written
+# once per sweep (uint8 species).
+BYTES_PER_TRIAL = 2
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--L", type=int, default=512, help="cells per axis (512 = the benchmark workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0 = all host cores)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 1 GiB (5 times) to calibrate HBM byte counters")
+    return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain copy kernel of known size: 1 GiB read + 1 GiB written per
+    launch.  Its FETCH_SIZE / WRITE_SIZE counter readings give the factor
+    that turns those counters into bytes for the sweep kernel."""
+    import torch
+    n = 1 << 30
+    src = torch.empty(n, dtype=torch.uint8, device="cuda:0").random_(0, 255)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}), flush=True)
+
+
+def cpu_baseline(job, n_threads):
+    """The oracle as it stands on one full sweep of the benchmark lattice."""
+    from oracle import oracle
+    oracle.set_threads(n_threads)
+    st = oracle.OracleState(job.L, (12, 12, 12), job.epi, job.sigma, job.seed)
+    t0 = time.perf_counter()
+    st.sweep(float(job.T[0]), 1)
+    dt = time.perf_counter() - t0
+    oracle.set_threads(1)
+    return {"value": job.N / dt, "unit": "swaps/s", "cores": n_threads, "kind": "oracle",
+            "sample": f"1 sweep of the {job.L[0]}^3 lattice ({job.N} trials), {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: the path has no multi-GPU form in this build "
+              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2509_20949_amd import smcx
+    from paper_2509_20949_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    t_gen = time.perf_counter()
+    progress(f"generating the {args.L}^3 lattice")
+    job = W.config3(n_sweeps=1, L=args.L)
+    t_gen = time.perf_counter() - t_gen
+    progress(f"input ready in {t_gen:.1f} s; warmup {args.warmup} sweeps")
+
+    lat = smcx.Lattice(job.L, job.epi, job.sigma, job.seed, 800.0)   # block 12: one wave per block
+    E0 = lat.energy()
+    lat.sweep(args.warmup)
+    smcx.smcx_synchronize(lat.ctx)
+    smcx.smcx_profile(lat.ctx, True)          # HIP events around every sweep-kernel launch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.sweep(args.steps)
+    smcx.smcx_synchronize(lat.ctx)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+
+    progress(f"timed {args.steps} sweeps in {t1 - t0:.2f} s")
+    kernel_ms, launches = smcx.smcx_kernel_time(lat.ctx)
+    smcx.smcx_profile(lat.ctx, False)
+    elapsed = t1 - t0
+    trials = job.N * args.steps
+    value = trials / elapsed
+    avg_launch_s = kernel_ms / 1e3 / max(launches, 1)
+    trials_per_launch = job.N / 8.0            # one colour phase: an eighth of the sites
+    ops = OPS_PER_TRIAL * trials_per_launch
+    achieved_ops = ops / avg_launch_s
+    hbm_bytes = BYTES_PER_TRIAL * trials_per_launch
+    E_run = lat.energy()
+    E_re = lat.energy_recompute()
+    stats = lat.stats()
+    cfg = lat.config()
+    comp_ok = bool(np.array_equal(np.bincount(cfg, minlength=job.K), np.bincount(job.sigma, minlength=job.K)))
+    lat.close()
+
+    out = {
+        "metric": "attempted swaps/s on 1 MI355X (268M-site BCC); batched p50/p99 latency",
+        "value": value,
+        "unit": "swaps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"bcc{job.L[0]}^3 quinary EPI sweep", "sites": job.N, "species": job.K,
+                   "shells": job.S, "T_K": 800.0, "composition": "Dirichlet(5)", "block": 12,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved_ops / 1e12, "peak": VALU_PEAK / 1e12,
+                     "unit": "Tops/s", "frac": achieved_ops / VALU_PEAK, "traffic": None,
+                     "kernel": "sweep_phase_kernel<5,3>", "avg_launch_ms": avg_launch_s * 1e3,
+                     "launches": launches, "ops_per_trial": OPS_PER_TRIAL},
+        "hbm": {"achieved": hbm_bytes / avg_launch_s / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": hbm_bytes / avg_launch_s / HBM_PEAK, "bytes_per_trial": BYTES_PER_TRIAL},
+        "check": {"energy_running_eq_recompute": E_run == E_re, "composition_conserved": comp_ok,
+                  "E0_ueV": E0, "E_ueV": E_run, "accepted": stats["accepted"],
+                  "acceptance": stats["accepted"] / max(stats["attempted"], 1)},
+        "context": {"paper_h800_atom_steps_per_s": 3.5e9, "paper_lattice": "FCC HEA, size not stated",
+                    "input_generation_s": t_gen},
+    }
+    if not args.no_cpu_baseline:
+        n = args.cpu_threads or min(os.cpu_count() or 1, 16)
+        progress(f"timing the oracle on one sweep with {n} threads")
+        out["cpu_baseline"] = cpu_baseline(job, n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

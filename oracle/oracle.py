@@ -65,6 +65,9 @@ def lib():
                                C.c_uint64, C.c_uint32, C.c_int32, p(C.c_double), p(C.c_uint8),
                                p(C.c_int64), p(C.c_uint64), p(C.c_int64), p(C.c_uint64)]
         L.or_sweep.restype = C.c_int
+        L.or_exchange_accept.argtypes = [C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_uint64,
+                                         C.c_uint32, C.c_uint64]
+        L.or_exchange_accept.restype = C.c_int
         L.or_enumerate.argtypes = [p(C.c_int32), C.c_int, C.c_int, p(C.c_int32), p(C.c_int32),
                                    C.c_int64, p(C.c_int64), p(C.c_uint64)]
         L.or_enumerate.restype = C.c_int64
@@ -181,6 +184,11 @@ def sro(L, S, K, sigma):
     lib().or_sro(_ptr(_L(L), C.c_int32), S, K, _ptr(s, C.c_uint8), _ptr(alpha, C.c_double),
                  _ptr(counts, C.c_uint64))
     return alpha, counts
+
+
+def exchange_accept(Ea, Eb, Ta, Tb, seed, k, round_):
+    return bool(lib().or_exchange_accept(int(Ea), int(Eb), float(Ta), float(Tb), C.c_uint64(seed),
+                                         C.c_uint32(k), C.c_uint64(round_)))
 
 
 class OracleState:

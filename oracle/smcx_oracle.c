@@ -485,3 +485,24 @@ int64_t or_enumerate(const int32_t L[3], int S, int K, const int32_t* epi,
     free(a);
     return cfg;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Replica exchange (Section "Distributed SMC-X", equations for P_swap and  */
+/* Delta): configurations at T_a and T_b with energies E_a, E_b swap with   */
+/* probability min(1, exp(Delta)), Delta = (1/k_B)(1/T_a - 1/T_b)(E_a - E_b).*/
+/* Reading for reproducibility: pair k of exchange round `round` draws       */
+/* u = word 0 of Philox4x32-10(key = seed, counter = (k, round lo, round hi, */
+/* 9)) and accepts iff (double)u < 2^32 min(1, exp(Delta)).                  */
+/* ------------------------------------------------------------------------ */
+int or_exchange_accept(int64_t Ea, int64_t Eb, double Ta, double Tb, uint64_t seed, uint32_t k,
+                       uint64_t round)
+{
+    const double kB_ueV_per_K = 86.17333262;
+    double delta = (1.0 / kB_ueV_per_K) * (1.0 / Ta - 1.0 / Tb) * ((double)Ea - (double)Eb);
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t ctr[4] = {k, (uint32_t)round, (uint32_t)(round >> 32), 9u};
+    uint32_t r[4];
+    or_philox4x32_10(ctr, key, r);
+    double p = delta >= 0.0 ? 1.0 : exp(delta);
+    return (double)r[0] < ldexp(p, 32);
+}

@@ -98,6 +98,10 @@ int or_sweep(const int32_t L[3], const int32_t B[3], int S, int K, const int32_t
              uint64_t seed, uint32_t s0, int32_t n, const double* T, uint8_t* sigma,
              int64_t* E, uint64_t* accepted, int64_t* E_trace, uint64_t* counts_trace);
 
+/* Replica-exchange decision for pair k of exchange round `round`. */
+int or_exchange_accept(int64_t Ea, int64_t Eb, double Ta, double Tb, uint64_t seed, uint32_t k,
+                       uint64_t round);
+
 /* Exact enumeration over every configuration with the given composition.
  * Fills E_all[cfg] (nullable) and returns the number of configurations, or
  * -1 if it exceeds max_cfg. */

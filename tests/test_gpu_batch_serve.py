@@ -1,0 +1,257 @@
+"""GPU tests of the batched and served paths against the oracle.
+
+A replica advanced inside a batch, a replica after replica exchange, and a
+request served while others are resident must each be bit-identical to the
+oracle run of the same inputs alone (configuration, energy, accepted count).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2509_20949_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def note(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def smcx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_20949_amd import smcx as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module", autouse=True)
+def oracle_threads(orc):
+    orc.set_threads(min(16, os.cpu_count() or 1))
+    yield
+    orc.set_threads(1)
+
+
+def mixed_jobs():
+    jobs = []
+    shapes = [((8, 8, 8), 4, 2), ((13, 9, 22), 5, 3), ((16, 16, 16), 5, 3), ((5, 6, 7), 3, 1),
+              ((24, 20, 18), 4, 3), ((10, 10, 10), 8, 3), ((4, 4, 4), 2, 2)]
+    for k, (L, K, S) in enumerate(shapes):
+        T = 400.0 + 250.0 * k
+        jobs.append(W.lattice_job(L, K, S, 30.0, np.full(1, T), stream=100 + k, name=f"mix{k}"))
+    return jobs
+
+
+def check_replica(smcx, view, job, ref):
+    N = job.N
+    assert np.array_equal(smcx.smcx_get_config(view, N), ref.sigma), job.name
+    assert smcx.smcx_energy(view) == int(ref.E[0]), job.name
+    assert smcx.smcx_energy_recompute(view) == int(ref.E[0]), job.name
+    assert smcx.smcx_get_stats(view)["accepted"] == int(ref.accepted[0]), job.name
+
+
+def test_batch_replicas_equal_oracle(smcx, orc):
+    jobs = mixed_jobs()
+    note(f"batch of {len(jobs)} mixed replicas")
+    descs = [smcx.make_desc(j.L, j.K, j.S, (0, 0, 0), j.seed) for j in jobs]
+    b = smcx.smcx_batch_create(descs, [j.sigma for j in jobs], [j.epi for j in jobs], [float(j.T[0]) for j in jobs])
+    refs = [orc.OracleState(j.L, (12, 12, 12), j.epi, j.sigma, j.seed) for j in jobs]
+    try:
+        # three runs: uneven counts, new counts (new graph), same counts (graph reused)
+        for counts in ([5, 3, 0, 7, 5, 1, 2], [2, 2, 4, 1, 0, 3, 6], [2, 2, 4, 1, 0, 3, 6]):
+            smcx.smcx_batch_run(b, counts)
+            for j, st, n in zip(jobs, refs, counts):
+                if n:
+                    st.sweep(float(j.T[0]), n)
+            smcx.smcx_batch_synchronize(b)
+            for r, (j, st) in enumerate(zip(jobs, refs)):
+                check_replica(smcx, smcx.smcx_batch_ctx(b, r), j, st)
+        alpha, counts = smcx.smcx_sro(smcx.smcx_batch_ctx(b, 2), jobs[2].S, jobs[2].K)
+        a_ref, c_ref = orc.sro(jobs[2].L, jobs[2].S, jobs[2].K, refs[2].sigma)
+        assert np.array_equal(counts, c_ref)
+    finally:
+        smcx.smcx_batch_destroy(b)
+
+
+def test_batched_equals_per_instance_launches(smcx, orc):
+    jobs = W.config4(n_replicas=12, n_sweeps=1, Lmin=8, Lmax=30)
+    note("batched vs per-instance")
+    descs = [smcx.make_desc(j.L, j.K, j.S, (0, 0, 0), j.seed) for j in jobs]
+    args = ([j.sigma for j in jobs], [j.epi for j in jobs], [float(j.T[0]) for j in jobs])
+    b1 = smcx.smcx_batch_create(descs, *args)
+    b2 = smcx.smcx_batch_create(descs, *args)
+    counts = [3 + (r % 4) for r in range(len(jobs))]
+    try:
+        smcx.smcx_batch_run(b1, counts)
+        smcx.smcx_batch_run_unbatched(b2, counts)
+        smcx.smcx_batch_synchronize(b1)
+        smcx.smcx_batch_synchronize(b2)
+        for r, j in enumerate(jobs):
+            v1, v2 = smcx.smcx_batch_ctx(b1, r), smcx.smcx_batch_ctx(b2, r)
+            assert np.array_equal(smcx.smcx_get_config(v1, j.N), smcx.smcx_get_config(v2, j.N))
+            assert smcx.smcx_energy(v1) == smcx.smcx_energy(v2)
+        # and one replica against the oracle
+        ref = orc.OracleState(jobs[5].L, (12, 12, 12), jobs[5].epi, jobs[5].sigma, jobs[5].seed)
+        ref.sweep(float(jobs[5].T[0]), counts[5])
+        check_replica(smcx, smcx.smcx_batch_ctx(b1, 5), jobs[5], ref)
+    finally:
+        smcx.smcx_batch_destroy(b1)
+        smcx.smcx_batch_destroy(b2)
+
+
+def test_config4_shapes_sampled_against_oracle(smcx, orc):
+    """The batched workload's own shapes (edge 16..96, K 4-5, T 300-2000 K):
+    every replica checked for exact running energy, four against the oracle."""
+    jobs = W.config4(n_replicas=24, n_sweeps=1)
+    note("config4 shapes, 24 replicas x 6 sweeps")
+    descs = [smcx.make_desc(j.L, j.K, j.S, (0, 0, 0), j.seed) for j in jobs]
+    b = smcx.smcx_batch_create(descs, [j.sigma for j in jobs], [j.epi for j in jobs], [float(j.T[0]) for j in jobs])
+    try:
+        smcx.smcx_batch_run(b, [6] * len(jobs))
+        smcx.smcx_batch_synchronize(b)
+        for r, j in enumerate(jobs):
+            v = smcx.smcx_batch_ctx(b, r)
+            assert smcx.smcx_energy(v) == smcx.smcx_energy_recompute(v)
+            cfg = smcx.smcx_get_config(v, j.N)
+            assert np.array_equal(np.bincount(cfg, minlength=j.K), np.bincount(j.sigma, minlength=j.K))
+        for r in (0, 7, 13, 23):
+            j = jobs[r]
+            ref = orc.OracleState(j.L, (12, 12, 12), j.epi, j.sigma, j.seed)
+            ref.sweep(float(j.T[0]), 6)
+            check_replica(smcx, smcx.smcx_batch_ctx(b, r), j, ref)
+    finally:
+        smcx.smcx_batch_destroy(b)
+
+
+def test_replica_exchange_equals_oracle(smcx, orc):
+    """Temperature ladder of one system; sweeps alternate with exchanges of
+    neighbouring temperatures.  The library's decisions, temperatures and
+    trajectories must equal the oracle's."""
+    base = W.lattice_job((10, 10, 10), 4, 3, 20.0, np.full(1, 800.0), stream=130, name="re")
+    ladder = [700.0, 760.0, 830.0, 900.0]
+    rng = np.random.default_rng(130)
+    sigmas = [W.configuration(np.bincount(base.sigma, minlength=4), rng) for _ in ladder]
+    seeds = [base.seed + r for r in range(len(ladder))]
+    note("replica exchange, 4 replicas")
+    descs = [smcx.make_desc(base.L, 4, 3, (0, 0, 0), s) for s in seeds]
+    b = smcx.smcx_batch_create(descs, sigmas, [base.epi] * 4, ladder)
+    refs = [orc.OracleState(base.L, (12, 12, 12), base.epi, sg, s) for sg, s in zip(sigmas, seeds)]
+    T = list(ladder)
+    n_acc = 0
+    try:
+        for rnd in range(12):
+            smcx.smcx_batch_run(b, [2, 2, 2, 2])
+            for r in range(4):
+                refs[r].sweep(T[r], 2)
+            # exchange pairs by temperature rank: (0,1),(2,3) or (1,2)
+            order = sorted(range(4), key=lambda r: T[r])
+            pairs = [(order[0], order[1]), (order[2], order[3])] if rnd % 2 == 0 else [(order[1], order[2])]
+            a = [p[0] for p in pairs]
+            c = [p[1] for p in pairs]
+            got = smcx.smcx_batch_exchange(b, a, c, 4242, rnd)
+            for k, (x, y) in enumerate(pairs):
+                want = orc.exchange_accept(int(refs[x].E[0]), int(refs[y].E[0]), T[x], T[y], 4242, k, rnd)
+                assert bool(got[k]) == want
+                if want:
+                    T[x], T[y] = T[y], T[x]
+                    n_acc += 1
+        smcx.smcx_batch_synchronize(b)
+        for r in range(4):
+            v = smcx.smcx_batch_ctx(b, r)
+            assert np.array_equal(smcx.smcx_get_config(v, base.N), refs[r].sigma)
+            assert smcx.smcx_energy(v) == int(refs[r].E[0])
+        assert n_acc > 0
+    finally:
+        smcx.smcx_batch_destroy(b)
+
+
+def serve_requests():
+    epi = W.epi_table(3, 5, 30.0, np.random.default_rng(140))
+    rng = np.random.default_rng(141)
+    reqs = []
+    for k, (L, n) in enumerate([((6, 6, 6), 7), ((20, 20, 20), 12), ((4, 4, 4), 3), ((31, 30, 29), 9),
+                                ((12, 12, 12), 20), ((9, 9, 9), 1), ((16, 16, 16), 5), ((25, 25, 25), 16)]):
+        comp = W.dirichlet_counts(5, W.n_sites(L), 5.0, rng)
+        reqs.append(W.Lattice(L, epi, W.configuration(comp, rng), 1000 + k, np.full(n, 300.0 + 200.0 * k),
+                              name=f"req{k}"))
+    return reqs
+
+
+def run_server(smcx, reqs, budget, slots, per_step, arrivals):
+    """arrivals[k] = step index at which request k is submitted."""
+    srv = smcx.smcx_server_create(budget, slots, per_step)
+    ids = {}
+    results = {}
+    try:
+        step = 0
+        while len(results) < len(reqs):
+            for k, j in enumerate(reqs):
+                if arrivals[k] == step:
+                    d = smcx.make_desc(j.L, j.K, j.S, (0, 0, 0), j.seed)
+                    ids[k] = smcx.smcx_server_submit(srv, d, j.sigma, j.epi, float(j.T[0]), j.n_sweeps)
+            smcx.smcx_server_step(srv)
+            for k, rid in ids.items():
+                if k not in results and smcx.smcx_server_poll(srv, rid) in (2, 3):
+                    try:
+                        results[k] = smcx.smcx_server_result(srv, rid, reqs[k].N)
+                    except smcx.SmcxError as e:
+                        results[k] = e
+            step += 1
+            assert step < 500
+    finally:
+        smcx.smcx_server_destroy(srv)
+    return results
+
+
+def test_server_results_equal_oracle_alone(smcx, orc):
+    reqs = serve_requests()
+    note("server, 8 requests, staggered arrivals, tight budget")
+    budget = 2 * max(smcx.smcx_server_footprint(smcx.make_desc(j.L, 5, 3)) for j in reqs)
+    results = run_server(smcx, reqs, budget, 3, 4, arrivals=[0, 0, 1, 1, 2, 5, 5, 9])
+    for k, j in enumerate(reqs):
+        E, acc, cfg = results[k]
+        ref = orc.OracleState(j.L, (12, 12, 12), j.epi, j.sigma, j.seed)
+        ref.sweep(float(j.T[0]), j.n_sweeps)
+        assert np.array_equal(cfg, ref.sigma), j.name
+        assert E == int(ref.E[0]) and acc == int(ref.accepted[0]), j.name
+
+
+def test_server_alone_equals_mix(smcx, orc):
+    reqs = serve_requests()
+    note("server alone vs mix")
+    big = 1 << 34
+    mix = run_server(smcx, reqs, big, 8, 3, arrivals=[0] * len(reqs))
+    for k in (1, 3, 7):
+        alone = run_server(smcx, [reqs[k]], big, 1, 5, arrivals=[0])
+        assert alone[0][0] == mix[k][0]
+        assert np.array_equal(alone[0][2], mix[k][2])
+
+
+def test_server_forced_admission_failure_isolated(smcx, orc, monkeypatch):
+    reqs = serve_requests()[:4]
+    note("server fault injection")
+    monkeypatch.setenv("SMCX_FAULT_REQUEST", "2")   # ids start at 1: fail the second request
+    results = run_server(smcx, reqs, 1 << 34, 4, 4, arrivals=[0, 0, 0, 0])
+    assert isinstance(results[1], smcx.SmcxError) and results[1].status == smcx.E_STATE
+    for k in (0, 2, 3):
+        E, acc, cfg = results[k]
+        j = reqs[k]
+        ref = orc.OracleState(j.L, (12, 12, 12), j.epi, j.sigma, j.seed)
+        ref.sweep(float(j.T[0]), j.n_sweeps)
+        assert np.array_equal(cfg, ref.sigma) and E == int(ref.E[0])
+
+
+def test_server_rejects_oversized_request(smcx):
+    srv = smcx.smcx_server_create(1 << 20, 2, 2)
+    try:
+        j = W.lattice_job((80, 80, 80), 5, 3, 30.0, np.full(2, 800.0), stream=150)
+        with pytest.raises(smcx.SmcxError) as e:
+            smcx.smcx_server_submit(srv, smcx.make_desc(j.L, 5, 3), j.sigma, j.epi, 800.0, 2)
+        assert e.value.status == smcx.E_NOMEM
+    finally:
+        smcx.smcx_server_destroy(srv)

@@ -183,3 +183,51 @@ def test_threaded_oracle_is_bit_identical(orc):
     a, b = runs
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
     assert np.array_equal(a[2], b[2]) and a[3] == b[3]
+
+
+def test_replica_exchange_keeps_each_temperature_boltzmann(orc):
+    """Replica exchange (P_swap = min(1, exp(Delta))): two 16-site replicas
+    at T1 < T2 that sweep and exchange must each sample the exact canonical
+    distribution of their temperature; a sign error in Delta would pull the
+    cold temperature towards high energies."""
+    L = (2, 2, 2)
+    rng = np.random.default_rng(12)
+    epi = W.epi_table(3, 2, 30.0, rng)
+    comp = [8, 8]
+    T1, T2 = 500.0, 1400.0
+    E_all, _ = orc.enumerate_configs(L, epi, comp)
+    exact = {}
+    for T in (T1, T2):
+        w = np.exp(-(E_all - E_all.min()) / (KB * T))
+        exact[T] = float((w * E_all).sum() / w.sum())
+    a = orc.OracleState(L, (2, 2, 2), epi, W.configuration(comp, rng), seed=1)
+    b = orc.OracleState(L, (2, 2, 2), epi, W.configuration(comp, rng), seed=2)
+    temps = [T1, T2]            # temperature of replica a, b
+    reps = [a, b]
+    samples = {T1: [], T2: []}
+    n_acc = 0
+    for rnd in range(30000):
+        for r, st in enumerate(reps):
+            st.sweep(temps[r], 1)
+        acc = orc.exchange_accept(int(a.E[0]), int(b.E[0]), temps[0], temps[1], 77, 0, rnd)
+        if acc:
+            temps = temps[::-1]
+            n_acc += 1
+        for r, st in enumerate(reps):
+            samples[temps[r]].append(int(st.E[0]))
+    assert 0.05 < n_acc / 30000 < 0.95
+    for T in (T1, T2):
+        batch_mean_check(np.array(samples[T][500:], np.float64), exact[T], nb=40, nsd=5.0)
+
+
+def test_replica_exchange_rule_closed_form(orc):
+    """Delta >= 0 always accepts; otherwise the acceptance rate is exp(Delta)."""
+    T1, T2 = 600.0, 700.0
+    # the cold replica holds the higher energy: Delta > 0
+    assert all(orc.exchange_accept(1000, 0, T1, T2, 5, k, 0) for k in range(200))
+    Ea, Eb = 0, 5000
+    delta = (1.0 / KB) * (1.0 / T1 - 1.0 / T2) * (Ea - Eb)
+    n = 20000
+    acc = sum(orc.exchange_accept(Ea, Eb, T1, T2, 5, k, 3) for k in range(n))
+    p = math.exp(delta)
+    assert abs(acc / n - p) < 6 * math.sqrt(p * (1 - p) / n)
