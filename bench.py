@@ -59,6 +59,14 @@ def parse():
     ap.add_argument("--L", type=int, default=512, help="cells per axis (512 = the benchmark workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0 = all host cores)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 256-replica batched leg")
+    ap.add_argument("--batched-sweeps", type=int, default=500)
+    ap.add_argument("--unbatched-sweeps", type=int, default=20,
+                    help="sweeps of the per-instance comparison (one launch per replica and phase)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-window", type=float, default=10.0, help="seconds of Poisson arrivals")
+    ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--serve-step", type=int, default=10, help="sweeps per server step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (5 times) to calibrate HBM byte counters")
     return ap.parse_args()
@@ -77,6 +85,107 @@ def copy_calibration():
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}), flush=True)
+
+
+def batched_leg(args, smcx, W):
+    """256 independent replicas (edge 16..96, K 4-5, T 300-2000 K): one HIP
+    graph launch for all sweeps against one launch per replica and phase."""
+    import torch
+    jobs = W.config4(n_replicas=256, n_sweeps=1)
+    descs = [smcx.make_desc(j.L, j.K, j.S, (0, 0, 0), j.seed) for j in jobs]
+    arrays = ([j.sigma for j in jobs], [j.epi for j in jobs], [float(j.T[0]) for j in jobs])
+    n_sites = sum(j.N for j in jobs)
+    a = smcx.smcx_batch_create(descs, *arrays)
+    b = smcx.smcx_batch_create(descs, *arrays)
+    try:
+        k = args.unbatched_sweeps
+        # identical trajectories: k sweeps batched vs k sweeps per instance
+        smcx.smcx_batch_run(a, [k] * len(jobs))
+        smcx.smcx_batch_synchronize(a)
+        t0 = time.perf_counter()
+        smcx.smcx_batch_run_unbatched(b, [k] * len(jobs))
+        smcx.smcx_batch_synchronize(b)
+        t_unb = time.perf_counter() - t0
+        same = True
+        for r, j in enumerate(jobs):
+            va, vb = smcx.smcx_batch_ctx(a, r), smcx.smcx_batch_ctx(b, r)
+            if smcx.smcx_energy(va) != smcx.smcx_energy(vb) or not np.array_equal(
+                    smcx.smcx_get_config(va, j.N), smcx.smcx_get_config(vb, j.N)):
+                same = False
+        # timed: all replicas, args.batched_sweeps sweeps, one graph launch
+        n = args.batched_sweeps
+        smcx.smcx_batch_run(a, [n] * len(jobs))          # capture + warm
+        smcx.smcx_batch_synchronize(a)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        smcx.smcx_batch_run(a, [n] * len(jobs))          # cached graph
+        smcx.smcx_batch_synchronize(a)
+        t_b = time.perf_counter() - t0
+        ok = all(smcx.smcx_energy(smcx.smcx_batch_ctx(a, r)) == smcx.smcx_energy_recompute(smcx.smcx_batch_ctx(a, r))
+                 for r in range(0, len(jobs), 17))
+    finally:
+        smcx.smcx_batch_destroy(a)
+        smcx.smcx_batch_destroy(b)
+    return {"replicas": len(jobs), "sites": n_sites, "sweeps": n,
+            "value": n_sites * n / t_b, "unit": "swaps/s", "seconds": t_b,
+            "per_instance": {"sweeps": k, "value": n_sites * k / t_unb, "seconds": t_unb,
+                             "launches": 8 * k * len(jobs)},
+            "speedup_vs_per_instance": (n_sites * n / t_b) / (n_sites * k / t_unb),
+            "identical_trajectories": same, "energy_checks_ok": ok}
+
+
+def serve_leg(args, smcx, W):
+    """Poisson request stream through the continuous-batching server:
+    requests are submitted at their arrival times, the server steps while
+    anything is resident or waiting, latency = completion - arrival."""
+    reqs = W.config5(rate_hz=args.serve_rate, window_s=args.serve_window, materialize=False)
+    # configuration bytes: windows of one random pool (the input content does
+    # not affect the work of a sweep), species relabelled per request
+    rng = np.random.default_rng(W.BASE_SEED + 55)
+    max_n = max(r.job.N for r in reqs)
+    pool = rng.choice(5, size=max_n * 2, p=rng.dirichlet(np.full(5, 5.0))).astype(np.uint8)
+    offered = sum(r.job.N * r.job.n_sweeps for r in reqs) / args.serve_window
+    srv = smcx.smcx_server_create(200 << 30, 512, args.serve_step)
+    lat, done_work = [], 0
+    ids = {}
+    try:
+        t0 = time.perf_counter()
+        nxt = 0
+        pending = set()
+        while nxt < len(reqs) or pending:
+            now = time.perf_counter() - t0
+            while nxt < len(reqs) and reqs[nxt].arrival_s <= now:
+                j = reqs[nxt].job
+                off = int(rng.integers(0, max_n))
+                perm = rng.permutation(5).astype(np.uint8)
+                sigma = perm[pool[off:off + j.N]]
+                d = smcx.make_desc(j.L, j.K, j.S, (0, 0, 0), j.seed)
+                ids[nxt] = smcx.smcx_server_submit(srv, d, sigma, j.epi, float(j.T[0]), j.n_sweeps)
+                pending.add(nxt)
+                nxt += 1
+            if not pending:
+                time.sleep(max(0.0, reqs[nxt].arrival_s - (time.perf_counter() - t0)))
+                continue
+            smcx.smcx_server_step(srv)
+            tnow = time.perf_counter() - t0
+            for k in list(pending):
+                st = smcx.smcx_server_poll(srv, ids[k])
+                if st == 2:
+                    smcx.smcx_server_result(srv, ids[k])
+                    lat.append(tnow - reqs[k].arrival_s)
+                    done_work += reqs[k].job.N * reqs[k].job.n_sweeps
+                    pending.discard(k)
+                elif st == 3:
+                    pending.discard(k)
+        t_end = time.perf_counter() - t0
+    finally:
+        smcx.smcx_server_destroy(srv)
+    lat = np.array(lat)
+    return {"requests": len(reqs), "completed": int(lat.size), "rate_hz": args.serve_rate,
+            "window_s": args.serve_window, "sweeps_per_step": args.serve_step,
+            "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "value": done_work / t_end, "unit": "swaps/s", "wall_s": t_end,
+            "offered_swaps_per_s": offered}
 
 
 def cpu_baseline(job, n_threads):
@@ -176,6 +285,12 @@ def main():
         "context": {"paper_h800_atom_steps_per_s": 3.5e9, "paper_lattice": "FCC HEA, size not stated",
                     "input_generation_s": t_gen},
     }
+    if not args.no_batched:
+        progress("batched leg: 256 replicas")
+        out["batched"] = batched_leg(args, smcx, W)
+    if not args.no_serve:
+        progress(f"serving leg: {args.serve_rate} req/s for {args.serve_window} s")
+        out["serving"] = serve_leg(args, smcx, W)
     if not args.no_cpu_baseline:
         n = args.cpu_threads or min(os.cpu_count() or 1, 16)
         progress(f"timing the oracle on one sweep with {n} threads")

@@ -108,8 +108,8 @@ smcx_status smcx_create(const smcx_desc* desc, const uint8_t* species, const int
                         double T_kelvin, smcx_ctx** out);
 
 /* smcx_create_device: as smcx_create, but the lattice lives in the caller's
- * device buffer d_species (N bytes, canonical order, already holding the
- * configuration; borrowed, updated in place), and work is enqueued on
+ * device buffer d_species (N bytes, canonical order, 4-byte aligned, already
+ * holding the configuration; borrowed, updated in place), and work is enqueued on
  * hip_stream (a hipStream_t, or NULL for the null stream).  The species are
  * validated on the device. */
 smcx_status smcx_create_device(const smcx_desc* desc, uint8_t* d_species, const int32_t* epi_ueV,

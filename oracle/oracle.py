@@ -49,26 +49,28 @@ def lib():
         L.or_axis_blocks.restype = C.c_int
         L.or_axis_bounds.argtypes = [C.c_int, C.c_int, p(C.c_int32)]
         L.or_sweep_shift.argtypes = [p(C.c_int32), C.c_uint64, C.c_uint32, p(C.c_int32)]
-        L.or_schedule.argtypes = [p(C.c_int32), p(C.c_int32), C.c_uint64, C.c_uint32,
+        L.or_schedule.argtypes = [C.c_int, p(C.c_int32), p(C.c_int32), C.c_uint64, C.c_uint32,
                                   p(C.c_uint8), p(C.c_uint8), p(C.c_int64)]
-        L.or_neighbour.argtypes = [p(C.c_int32), C.c_int64, C.c_int]
+        L.or_neighbour.argtypes = [C.c_int, p(C.c_int32), C.c_int64, C.c_int]
+        L.or_shell_size.argtypes = [C.c_int, C.c_int]
+        L.or_n_sub.argtypes = [C.c_int]
         L.or_neighbour.restype = C.c_int64
-        L.or_energy.argtypes = [p(C.c_int32), C.c_int, C.c_int, p(C.c_int32), p(C.c_uint8)]
+        L.or_energy.argtypes = [C.c_int, p(C.c_int32), C.c_int, C.c_int, p(C.c_int32), p(C.c_uint8)]
         L.or_energy.restype = C.c_int64
-        L.or_delta_energy.argtypes = [p(C.c_int32), C.c_int, C.c_int, p(C.c_int32), p(C.c_uint8),
+        L.or_delta_energy.argtypes = [C.c_int, p(C.c_int32), C.c_int, C.c_int, p(C.c_int32), p(C.c_uint8),
                                       C.c_int64, C.c_int64]
         L.or_delta_energy.restype = C.c_int64
-        L.or_pair_counts.argtypes = [p(C.c_int32), C.c_int, C.c_int, p(C.c_uint8), p(C.c_uint64)]
-        L.or_sro.argtypes = [p(C.c_int32), C.c_int, C.c_int, p(C.c_uint8), p(C.c_double),
+        L.or_pair_counts.argtypes = [C.c_int, p(C.c_int32), C.c_int, C.c_int, p(C.c_uint8), p(C.c_uint64)]
+        L.or_sro.argtypes = [C.c_int, p(C.c_int32), C.c_int, C.c_int, p(C.c_uint8), p(C.c_double),
                              p(C.c_uint64)]
-        L.or_sweep.argtypes = [p(C.c_int32), p(C.c_int32), C.c_int, C.c_int, p(C.c_int32),
+        L.or_sweep.argtypes = [C.c_int, p(C.c_int32), p(C.c_int32), C.c_int, C.c_int, p(C.c_int32),
                                C.c_uint64, C.c_uint32, C.c_int32, p(C.c_double), p(C.c_uint8),
                                p(C.c_int64), p(C.c_uint64), p(C.c_int64), p(C.c_uint64)]
         L.or_sweep.restype = C.c_int
         L.or_exchange_accept.argtypes = [C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_uint64,
                                          C.c_uint32, C.c_uint64]
         L.or_exchange_accept.restype = C.c_int
-        L.or_enumerate.argtypes = [p(C.c_int32), C.c_int, C.c_int, p(C.c_int32), p(C.c_int32),
+        L.or_enumerate.argtypes = [C.c_int, p(C.c_int32), C.c_int, C.c_int, p(C.c_int32), p(C.c_int32),
                                    C.c_int64, p(C.c_int64), p(C.c_uint64)]
         L.or_enumerate.restype = C.c_int64
         _lib = L
@@ -136,52 +138,67 @@ def sweep_shift(L, seed, s):
     return out
 
 
-def schedule(L, B, seed, s):
+BCC, FCC = 0, 1
+
+
+def n_sub(lattice=BCC):
+    return 4 if lattice == FCC else 2
+
+
+def shell_size(s, lattice=BCC):
+    return lib().or_shell_size(int(lattice), int(s))
+
+
+def n_sites(L, lattice=BCC):
+    return n_sub(lattice) * int(np.prod(np.asarray(L, dtype=np.int64)))
+
+
+def schedule(L, B, seed, s, lattice=BCC):
     Lv = _L(L)
-    N = 2 * int(np.prod(Lv.astype(np.int64)))
+    N = n_sites(Lv, lattice)
     col = np.zeros(N, np.uint8)
     sub = np.zeros(N, np.uint8)
     blk = np.zeros(N, np.int64)
-    lib().or_schedule(_ptr(Lv, C.c_int32), _ptr(_L(B), C.c_int32), C.c_uint64(seed),
+    lib().or_schedule(int(lattice), _ptr(Lv, C.c_int32), _ptr(_L(B), C.c_int32), C.c_uint64(seed),
                       C.c_uint32(s), _ptr(col, C.c_uint8), _ptr(sub, C.c_uint8),
                       _ptr(blk, C.c_int64))
     return col, sub, blk
 
 
-def neighbour(L, i, k):
-    return lib().or_neighbour(_ptr(_L(L), C.c_int32), int(i), int(k))
+def neighbour(L, i, k, lattice=BCC):
+    return lib().or_neighbour(int(lattice), _ptr(_L(L), C.c_int32), int(i), int(k))
 
 
 def _epi(epi):
     return np.ascontiguousarray(epi, dtype=np.int32)
 
 
-def energy(L, epi, sigma):
+def energy(L, epi, sigma, lattice=BCC):
     e = _epi(epi)
     S, K = e.shape[0], e.shape[1]
     s = np.ascontiguousarray(sigma, dtype=np.uint8)
-    return lib().or_energy(_ptr(_L(L), C.c_int32), S, K, _ptr(e, C.c_int32), _ptr(s, C.c_uint8))
+    return lib().or_energy(int(lattice), _ptr(_L(L), C.c_int32), S, K, _ptr(e, C.c_int32), _ptr(s, C.c_uint8))
 
 
-def delta_energy(L, epi, sigma, i, j):
+def delta_energy(L, epi, sigma, i, j, lattice=BCC):
     e = _epi(epi)
     s = np.ascontiguousarray(sigma, dtype=np.uint8)
-    return lib().or_delta_energy(_ptr(_L(L), C.c_int32), e.shape[0], e.shape[1],
+    return lib().or_delta_energy(int(lattice), _ptr(_L(L), C.c_int32), e.shape[0], e.shape[1],
                                  _ptr(e, C.c_int32), _ptr(s, C.c_uint8), int(i), int(j))
 
 
-def pair_counts(L, S, K, sigma):
+def pair_counts(L, S, K, sigma, lattice=BCC):
     s = np.ascontiguousarray(sigma, dtype=np.uint8)
     out = np.zeros((S, K, K), np.uint64)
-    lib().or_pair_counts(_ptr(_L(L), C.c_int32), S, K, _ptr(s, C.c_uint8), _ptr(out, C.c_uint64))
+    lib().or_pair_counts(int(lattice), _ptr(_L(L), C.c_int32), S, K, _ptr(s, C.c_uint8), _ptr(out, C.c_uint64))
     return out
 
 
-def sro(L, S, K, sigma):
+def sro(L, S, K, sigma, lattice=BCC):
     s = np.ascontiguousarray(sigma, dtype=np.uint8)
     alpha = np.zeros((S, K, K), np.float64)
     counts = np.zeros((S, K, K), np.uint64)
-    lib().or_sro(_ptr(_L(L), C.c_int32), S, K, _ptr(s, C.c_uint8), _ptr(alpha, C.c_double),
+    lib().or_sro(int(lattice), _ptr(_L(L), C.c_int32), S, K, _ptr(s, C.c_uint8), _ptr(alpha, C.c_double),
                  _ptr(counts, C.c_uint64))
     return alpha, counts
 
@@ -194,7 +211,8 @@ def exchange_accept(Ea, Eb, Ta, Tb, seed, k, round_):
 class OracleState:
     """A lattice advanced by the oracle, sweep by sweep."""
 
-    def __init__(self, L, B, epi, sigma, seed, s0=0):
+    def __init__(self, L, B, epi, sigma, seed, s0=0, lattice=BCC):
+        self.lattice = int(lattice)
         self.L = _L(L)
         self.B = _L(B)
         self.epi = _epi(epi)
@@ -203,7 +221,7 @@ class OracleState:
         self.seed = int(seed)
         self.s = int(s0)
         self.E = np.zeros(1, np.int64)
-        self.E[0] = energy(self.L, self.epi, self.sigma)
+        self.E[0] = energy(self.L, self.epi, self.sigma, self.lattice)
         self.accepted = np.zeros(1, np.uint64)
 
     def sweep(self, T, n=1, trace_E=False, trace_counts=False):
@@ -211,7 +229,7 @@ class OracleState:
         Et = np.zeros(n, np.int64) if trace_E else None
         Ct = np.zeros((n, self.S, self.K, self.K), np.uint64) if trace_counts else None
         rc = lib().or_sweep(
-            _ptr(self.L, C.c_int32), _ptr(self.B, C.c_int32), self.S, self.K,
+            self.lattice, _ptr(self.L, C.c_int32), _ptr(self.B, C.c_int32), self.S, self.K,
             _ptr(self.epi, C.c_int32), C.c_uint64(self.seed), C.c_uint32(self.s), n,
             _ptr(Ts, C.c_double), _ptr(self.sigma, C.c_uint8), _ptr(self.E, C.c_int64),
             _ptr(self.accepted, C.c_uint64),
@@ -223,7 +241,7 @@ class OracleState:
         return Et, Ct
 
 
-def enumerate_configs(L, epi, comp, max_cfg=5_000_000, with_counts=False):
+def enumerate_configs(L, epi, comp, max_cfg=5_000_000, with_counts=False, lattice=BCC):
     e = _epi(epi)
     S, K = e.shape[0], e.shape[1]
     c = np.ascontiguousarray(comp, dtype=np.int32)
@@ -235,7 +253,7 @@ def enumerate_configs(L, epi, comp, max_cfg=5_000_000, with_counts=False):
         raise ValueError("too many configurations")
     E = np.zeros(n, np.int64)
     counts = np.zeros((n, S, K, K), np.uint64) if with_counts else None
-    got = lib().or_enumerate(_ptr(_L(L), C.c_int32), S, K, _ptr(e, C.c_int32),
+    got = lib().or_enumerate(int(lattice), _ptr(_L(L), C.c_int32), S, K, _ptr(e, C.c_int32),
                              _ptr(c, C.c_int32), n, _ptr(E, C.c_int64),
                              _ptr(counts, C.c_uint64) if counts is not None else None)
     if got != n:

@@ -132,84 +132,124 @@ int or_accept(int64_t dE, uint32_t u, const double tab[768])
 }
 
 /* ------------------------------------------------------------------------ */
-/* Geometry                                                                  */
+/* Geometry.  lat = 0: BCC, two sites per cubic cell (corner, body centre);  */
+/* lat = 1: FCC, four sites per cubic cell (corner and three face centres). */
+/* In doubled coordinates (units of half the lattice constant) site b of   */
+/* cell (x, y, z) sits at (2x, 2y, 2z) + SUB[b].  Site id = cell * n_sub + b, */
+/* cell = (z*Ly + y)*Lx + x.                                                 */
 /* ------------------------------------------------------------------------ */
-static const int SHELL1[8][3] = {
+static const int SUB_BCC[2][3] = {{0, 0, 0}, {1, 1, 1}};
+static const int SUB_FCC[4][3] = {{0, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
+
+/* BCC shells: 8 first neighbours (+-1,+-1,+-1) -- vector number dir has +1
+ * on axis a when bit a of dir is set --, 6 second (+-2,0,0), 12 third
+ * (+-2,+-2,0). */
+static const int BCC1[8][3] = {
     {-1, -1, -1}, {+1, -1, -1}, {-1, +1, -1}, {+1, +1, -1},
     {-1, -1, +1}, {+1, -1, +1}, {-1, +1, +1}, {+1, +1, +1}};
 static const int SHELL2[6][3] = {
     {+2, 0, 0}, {-2, 0, 0}, {0, +2, 0}, {0, -2, 0}, {0, 0, +2}, {0, 0, -2}};
-static const int SHELL3[12][3] = {
+static const int BCC3[12][3] = {
     {+2, +2, 0}, {+2, -2, 0}, {-2, +2, 0}, {-2, -2, 0},
     {+2, 0, +2}, {+2, 0, -2}, {-2, 0, +2}, {-2, 0, -2},
     {0, +2, +2}, {0, +2, -2}, {0, -2, +2}, {0, -2, -2}};
+/* FCC shells: 12 first neighbours (+-1,+-1,0) and permutations, 6 second
+ * (+-2,0,0), 24 third (+-2,+-1,+-1) and permutations. */
+static const int FCC1[12][3] = {
+    {+1, +1, 0}, {+1, -1, 0}, {-1, +1, 0}, {-1, -1, 0},
+    {+1, 0, +1}, {+1, 0, -1}, {-1, 0, +1}, {-1, 0, -1},
+    {0, +1, +1}, {0, +1, -1}, {0, -1, +1}, {0, -1, -1}};
+static const int FCC3[24][3] = {
+    {+2, +1, +1}, {+2, +1, -1}, {+2, -1, +1}, {+2, -1, -1},
+    {-2, +1, +1}, {-2, +1, -1}, {-2, -1, +1}, {-2, -1, -1},
+    {+1, +2, +1}, {+1, +2, -1}, {-1, +2, +1}, {-1, +2, -1},
+    {+1, -2, +1}, {+1, -2, -1}, {-1, -2, +1}, {-1, -2, -1},
+    {+1, +1, +2}, {+1, -1, +2}, {-1, +1, +2}, {-1, -1, +2},
+    {+1, +1, -2}, {+1, -1, -2}, {-1, +1, -2}, {-1, -1, -2}};
 
-int or_shell_size(int s) { return s == 0 ? 8 : (s == 1 ? 6 : 12); }
+int or_n_sub(int lat) { return lat == 1 ? 4 : 2; }
+
+int or_shell_size(int lat, int s)
+{
+    if (lat == 1) return s == 0 ? 12 : (s == 1 ? 6 : 24);
+    return s == 0 ? 8 : (s == 1 ? 6 : 12);
+}
 
 /* displacement k of the concatenated list shell1 ++ shell2 ++ shell3 */
-static const int* displacement(int k, int* shell)
+static const int* displacement(int lat, int k, int* shell)
 {
-    if (k < 8) { *shell = 0; return SHELL1[k]; }
-    if (k < 14) { *shell = 1; return SHELL2[k - 8]; }
+    int n1 = or_shell_size(lat, 0), n2 = or_shell_size(lat, 1);
+    if (k < n1) { *shell = 0; return lat == 1 ? FCC1[k] : BCC1[k]; }
+    if (k < n1 + n2) { *shell = 1; return SHELL2[k - n1]; }
     *shell = 2;
-    return SHELL3[k - 14];
+    return lat == 1 ? FCC3[k - n1 - n2] : BCC3[k - n1 - n2];
 }
 
 static int64_t wrap(int64_t v, int64_t m) { v %= m; return v < 0 ? v + m : v; }
 
-/* A site in decoded form: doubled coordinates X, Y, Z (parities equal b). */
+/* A site in decoded form: doubled coordinates X, Y, Z. */
 typedef struct { int64_t X, Y, Z; } site_xyz;
 
-static site_xyz decode_site(const int32_t L[3], int64_t i)
+static site_xyz decode_site(int lat, const int32_t L[3], int64_t i)
 {
-    int64_t b = i & 1, cell = i >> 1;
+    int nsub = or_n_sub(lat);
+    int64_t b = i % nsub, cell = i / nsub;
     int64_t x = cell % L[0], y = (cell / L[0]) % L[1], z = cell / ((int64_t)L[0] * L[1]);
-    site_xyz p = {2 * x + b, 2 * y + b, 2 * z + b};
+    const int* o = lat == 1 ? SUB_FCC[b] : SUB_BCC[b];
+    site_xyz p = {2 * x + o[0], 2 * y + o[1], 2 * z + o[2]};
     return p;
 }
 
 /* periodic add of a displacement component in [-2, 2] to X in [0, 2L) */
 static int64_t wrap_small(int64_t v, int64_t twoL) { return v < 0 ? v + twoL : (v >= twoL ? v - twoL : v); }
 
-static int64_t site_at(const int32_t L[3], site_xyz p, const int* d)
+static int64_t site_at(int lat, const int32_t L[3], site_xyz p, const int* d)
 {
     int64_t X = wrap_small(p.X + d[0], 2 * (int64_t)L[0]);
     int64_t Y = wrap_small(p.Y + d[1], 2 * (int64_t)L[1]);
     int64_t Z = wrap_small(p.Z + d[2], 2 * (int64_t)L[2]);
-    int64_t nb = X & 1; /* equal parities on all axes */
-    return ((((Z >> 1) * L[1] + (Y >> 1)) * L[0] + (X >> 1)) << 1) | nb;
+    int64_t cell = ((Z >> 1) * L[1] + (Y >> 1)) * L[0] + (X >> 1);
+    int parity = (int)((X & 1) | (Y & 1) << 1 | (Z & 1) << 2);
+    int b;
+    if (lat == 1) {
+        static const int SUB_OF_PARITY[8] = {0, -1, -1, 1, -1, 2, 3, -1};
+        b = SUB_OF_PARITY[parity];
+    } else {
+        b = parity == 7 ? 1 : 0;
+    }
+    return cell * or_n_sub(lat) + b;
 }
 
-int64_t or_neighbour(const int32_t L[3], int64_t i, int k)
+int64_t or_neighbour(int lat, const int32_t L[3], int64_t i, int k)
 {
     int shell;
-    const int* d = displacement(k, &shell);
-    return site_at(L, decode_site(L, i), d);
+    const int* d = displacement(lat, k, &shell);
+    return site_at(lat, L, decode_site(lat, L, i), d);
 }
 
-static int n_displacements(int S)
+static int n_displacements(int lat, int S)
 {
     int n = 0;
-    for (int s = 0; s < S; ++s) n += or_shell_size(s);
+    for (int s = 0; s < S; ++s) n += or_shell_size(lat, s);
     return n;
 }
 
-static int64_t n_sites(const int32_t L[3]) { return 2 * (int64_t)L[0] * L[1] * L[2]; }
+static int64_t n_sites(int lat, const int32_t L[3]) { return or_n_sub(lat) * (int64_t)L[0] * L[1] * L[2]; }
 
 /* ------------------------------------------------------------------------ */
 /* Energy, energy change, pair counts, SRO                                   */
 /* ------------------------------------------------------------------------ */
-int64_t or_energy(const int32_t L[3], int S, int K, const int32_t* epi, const uint8_t* sigma)
+int64_t or_energy(int lat, const int32_t L[3], int S, int K, const int32_t* epi, const uint8_t* sigma)
 {
-    int64_t N = n_sites(L), twiceE = 0;
-    int nd = n_displacements(S);
+    int64_t N = n_sites(lat, L), twiceE = 0;
+    int nd = n_displacements(lat, S);
 #pragma omp parallel for reduction(+ : twiceE) num_threads(g_threads) schedule(static)
     for (int64_t i = 0; i < N; ++i) {
-        site_xyz p = decode_site(L, i);
+        site_xyz p = decode_site(lat, L, i);
         for (int k = 0; k < nd; ++k) {
             int s;
-            const int* d = displacement(k, &s);
-            int64_t n = site_at(L, p, d);
+            const int* d = displacement(lat, k, &s);
+            int64_t n = site_at(lat, L, p, d);
             twiceE += epi[(s * K + sigma[i]) * K + sigma[n]];
         }
     }
@@ -221,19 +261,19 @@ int64_t or_energy(const int32_t L[3], int S, int K, const int32_t* epi, const ui
  * is unchanged because V is symmetric:
  *   dE = sum_{delta, i+delta != j} [V(sj, s_{i+delta}) - V(si, s_{i+delta})]
  *      + sum_{delta, j+delta != i} [V(si, s_{j+delta}) - V(sj, s_{j+delta})]  */
-int64_t or_delta_energy(const int32_t L[3], int S, int K, const int32_t* epi,
+int64_t or_delta_energy(int lat, const int32_t L[3], int S, int K, const int32_t* epi,
                         const uint8_t* sigma, int64_t i, int64_t j)
 {
-    int nd = n_displacements(S);
+    int nd = n_displacements(lat, S);
     int si = sigma[i], sj = sigma[j];
-    site_xyz pi = decode_site(L, i), pj = decode_site(L, j);
+    site_xyz pi = decode_site(lat, L, i), pj = decode_site(lat, L, j);
     int64_t dE = 0;
     for (int k = 0; k < nd; ++k) {
         int s;
-        const int* d = displacement(k, &s);
-        int64_t n = site_at(L, pi, d);
+        const int* d = displacement(lat, k, &s);
+        int64_t n = site_at(lat, L, pi, d);
         if (n != j) dE += epi[(s * K + sj) * K + sigma[n]] - epi[(s * K + si) * K + sigma[n]];
-        int64_t m = site_at(L, pj, d);
+        int64_t m = site_at(lat, L, pj, d);
         if (m != i) dE += epi[(s * K + si) * K + sigma[m]] - epi[(s * K + sj) * K + sigma[m]];
     }
     return dE;
@@ -241,10 +281,10 @@ int64_t or_delta_energy(const int32_t L[3], int S, int K, const int32_t* epi,
 
 /* counts[m][p'][p] = number of (centre i of species p', displacement of
  * shell m, neighbour of species p). */
-void or_pair_counts(const int32_t L[3], int S, int K, const uint8_t* sigma, uint64_t* counts)
+void or_pair_counts(int lat, const int32_t L[3], int S, int K, const uint8_t* sigma, uint64_t* counts)
 {
-    int64_t N = n_sites(L);
-    int nd = n_displacements(S);
+    int64_t N = n_sites(lat, L);
+    int nd = n_displacements(lat, S);
     size_t nc = (size_t)S * K * K;
     memset(counts, 0, sizeof(uint64_t) * nc);
 #pragma omp parallel num_threads(g_threads)
@@ -252,11 +292,11 @@ void or_pair_counts(const int32_t L[3], int S, int K, const uint8_t* sigma, uint
         uint64_t* mine = (uint64_t*)calloc(nc, sizeof(uint64_t));
 #pragma omp for schedule(static)
         for (int64_t i = 0; i < N; ++i) {
-            site_xyz p = decode_site(L, i);
+            site_xyz p = decode_site(lat, L, i);
             for (int k = 0; k < nd; ++k) {
                 int s;
-                const int* d = displacement(k, &s);
-                int64_t n = site_at(L, p, d);
+                const int* d = displacement(lat, k, &s);
+                int64_t n = site_at(lat, L, p, d);
                 mine[(s * K + sigma[i]) * K + sigma[n]] += 1;
             }
         }
@@ -269,17 +309,17 @@ void or_pair_counts(const int32_t L[3], int S, int K, const uint8_t* sigma, uint
 /* Warren-Cowley SRO, Eq. (SRO): alpha_m^{pp'} = 1 - P_m^{p|p'} / c_p with
  * P_m^{p|p'} = counts[m][p'][p] / (Z_m N_{p'}), c_p = N_p / N.  Stored at
  * alpha[(m*K + p')*K + p].  NaN when N_p or N_{p'} is zero (reading). */
-void or_sro(const int32_t L[3], int S, int K, const uint8_t* sigma, double* alpha, uint64_t* counts)
+void or_sro(int lat, const int32_t L[3], int S, int K, const uint8_t* sigma, double* alpha, uint64_t* counts)
 {
-    int64_t N = n_sites(L);
+    int64_t N = n_sites(lat, L);
     uint64_t* c = counts ? counts : (uint64_t*)malloc(sizeof(uint64_t) * S * K * K);
-    or_pair_counts(L, S, K, sigma, c);
+    or_pair_counts(lat, L, S, K, sigma, c);
     int64_t Np[256] = {0};
     for (int64_t i = 0; i < N; ++i) Np[sigma[i]] += 1;
     for (int m = 0; m < S; ++m)
         for (int pc = 0; pc < K; ++pc)
             for (int p = 0; p < K; ++p) {
-                double P = (double)c[(m * K + pc) * K + p] / ((double)or_shell_size(m) * (double)Np[pc]);
+                double P = (double)c[(m * K + pc) * K + p] / ((double)or_shell_size(lat, m) * (double)Np[pc]);
                 double cp = (double)Np[p] / (double)N;
                 alpha[(m * K + pc) * K + p] = (Np[p] == 0 || Np[pc] == 0) ? NAN : 1.0 - P / cp;
             }
@@ -300,7 +340,8 @@ void or_sro(const int32_t L[3], int S, int K, const uint8_t* sigma, double* alph
 /* Cell coordinate x_a maps to u_a = (x_a - o_a) mod L_a, block k_a with     */
 /* b_k <= u_a < b_{k+1}, local coordinate l_a = u_a - b_k.                   */
 /* Colour c = (k_x & 1) | (k_y & 1) << 1 | (k_z & 1) << 2, phases c = 0..7.  */
-/* Sub-colour q = (((l_z%3)*3 + l_y%3)*3 + l_x%3)*2 + b, rounds q = 0..53.   */
+/* Sub-colour q = (((l_z%3)*3 + l_y%3)*3 + l_x%3)*n_sub + b: 54 rounds      */
+/* (BCC) or 108 (FCC).                                                      */
 /* Trials run colour by colour, sub-colour by sub-colour, and inside one     */
 /* (c, q) set in ascending site id (the trials of one set commute).          */
 /* ------------------------------------------------------------------------ */
@@ -329,9 +370,10 @@ void or_sweep_shift(const int32_t L[3], uint64_t seed, uint32_t s, int32_t shift
     for (int a = 0; a < 3; ++a) shift[a] = (int32_t)(((uint64_t)r[a] * (uint64_t)L[a]) >> 32);
 }
 
-void or_schedule(const int32_t L[3], const int32_t B[3], uint64_t seed, uint32_t s,
+void or_schedule(int lat, const int32_t L[3], const int32_t B[3], uint64_t seed, uint32_t s,
                  uint8_t* colour, uint8_t* subcolour, int64_t* block)
 {
+    const int nsub = or_n_sub(lat);
     int32_t shift[3];
     or_sweep_shift(L, seed, s, shift);
     /* per axis and cell coordinate x: block index k and local coordinate l */
@@ -360,11 +402,11 @@ void or_schedule(const int32_t L[3], const int32_t B[3], uint64_t seed, uint32_t
                 int kx = kof[0][x], ky = kof[1][y], kz = kof[2][z];
                 int lx = lof[0][x], ly = lof[1][y], lz = lof[2][z];
                 uint8_t c = (uint8_t)((kx & 1) | ((ky & 1) << 1) | ((kz & 1) << 2));
-                uint8_t q = (uint8_t)((((lz % 3) * 3 + ly % 3) * 3 + lx % 3) * 2);
-                for (int b = 0; b < 2; ++b) {
-                    colour[2 * cell + b] = c;
-                    subcolour[2 * cell + b] = (uint8_t)(q + b);
-                    if (block) block[2 * cell + b] = ((int64_t)kz * n[1] + ky) * n[0] + kx;
+                uint8_t q = (uint8_t)((((lz % 3) * 3 + ly % 3) * 3 + lx % 3) * nsub);
+                for (int b = 0; b < nsub; ++b) {
+                    colour[nsub * cell + b] = c;
+                    subcolour[nsub * cell + b] = (uint8_t)(q + b);
+                    if (block) block[nsub * cell + b] = ((int64_t)kz * n[1] + ky) * n[0] + kx;
                 }
             }
     for (int a = 0; a < 3; ++a) { free(kof[a]); free(lof[a]); }
@@ -385,32 +427,34 @@ static int valid_inputs(const int32_t L[3], const int32_t B[3], int S, int K, co
     return 1;
 }
 
-int or_sweep(const int32_t L[3], const int32_t B[3], int S, int K, const int32_t* epi,
+int or_sweep(int lat, const int32_t L[3], const int32_t B[3], int S, int K, const int32_t* epi,
              uint64_t seed, uint32_t s0, int32_t n, const double* T, uint8_t* sigma,
              int64_t* E, uint64_t* accepted, int64_t* E_trace, uint64_t* counts_trace)
 {
-    if (!valid_inputs(L, B, S, K, epi) || n < 0) return -1;
-    int64_t N = n_sites(L);
+    if ((lat != 0 && lat != 1) || !valid_inputs(L, B, S, K, epi) || n < 0) return -1;
+    const int nsub = or_n_sub(lat);
+    const int ngroups = 8 * 27 * nsub;
+    int64_t N = n_sites(lat, L);
     for (int64_t i = 0; i < N; ++i)
         if (sigma[i] >= K) return -1;
     uint8_t* colour = (uint8_t*)malloc(N);
     uint8_t* sub = (uint8_t*)malloc(N);
     int64_t* order = (int64_t*)malloc(sizeof(int64_t) * N);
-    int64_t start[8 * 54 + 1];
+    int64_t start[8 * 27 * 4 + 1];
     double tab[768];
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
 
     for (int32_t t = 0; t < n; ++t) {
         uint32_t s = s0 + (uint32_t)t;
         or_thresholds(T[t], tab);
-        or_schedule(L, B, seed, s, colour, sub, NULL);
+        or_schedule(lat, L, B, seed, s, colour, sub, NULL);
         /* order: counting sort on (colour, sub-colour), stable in site id */
         memset(start, 0, sizeof(start));
-        for (int64_t i = 0; i < N; ++i) start[colour[i] * 54 + sub[i] + 1] += 1;
-        for (int g = 0; g < 8 * 54; ++g) start[g + 1] += start[g];
-        for (int64_t i = 0; i < N; ++i) order[start[colour[i] * 54 + sub[i]]++] = i;
+        for (int64_t i = 0; i < N; ++i) start[colour[i] * 27 * nsub + sub[i] + 1] += 1;
+        for (int g = 0; g < ngroups; ++g) start[g + 1] += start[g];
+        for (int64_t i = 0; i < N; ++i) order[start[colour[i] * 27 * nsub + sub[i]]++] = i;
 
-        for (int g = 0; g < 8 * 54; ++g) {
+        for (int g = 0; g < ngroups; ++g) {
             int64_t lo = g == 0 ? 0 : start[g - 1], hi = start[g];
             int64_t dE_set = 0;
             uint64_t acc_set = 0;
@@ -418,16 +462,21 @@ int or_sweep(const int32_t L[3], const int32_t B[3], int S, int K, const int32_t
     if (hi - lo > 512)
             for (int64_t r = lo; r < hi; ++r) {
                 int64_t i = order[r];
-                int64_t cell = i >> 1;
-                int b = (int)(i & 1);
-                uint32_t ctr[4] = {(uint32_t)cell, (uint32_t)(cell >> 32), s, colour[i]};
+                int64_t cell = i / nsub;
+                int b = (int)(i % nsub);
+                /* sites 0, 1 of a cell share one Philox call, sites 2, 3 (FCC)
+                 * another one with counter word 3 raised by 16 */
+                uint32_t ctr[4] = {(uint32_t)cell, (uint32_t)(cell >> 32), s,
+                                   (uint32_t)colour[i] + 16u * (uint32_t)(b >> 1)};
                 uint32_t rnd[4];
                 or_philox4x32_10(ctr, key, rnd);
-                uint32_t u_dir = rnd[2 * b], u_acc = rnd[2 * b + 1];
-                int dir = (int)(u_dir >> 29);
-                int64_t j = or_neighbour(L, i, dir);
+                uint32_t u_dir = rnd[2 * (b & 1)], u_acc = rnd[2 * (b & 1) + 1];
+                /* partner: uniform over the first shell (8 BCC vectors from the
+                 * top 3 bits; 12 FCC vectors from the high word of u * 12) */
+                int dir = lat == 1 ? (int)(((uint64_t)u_dir * 12u) >> 32) : (int)(u_dir >> 29);
+                int64_t j = or_neighbour(lat, L, i, dir);
                 if (sigma[i] == sigma[j]) continue;
-                int64_t dE = or_delta_energy(L, S, K, epi, sigma, i, j);
+                int64_t dE = or_delta_energy(lat, L, S, K, epi, sigma, i, j);
                 if (or_accept(dE, u_acc, tab)) {
                     uint8_t tmp = sigma[i];
                     sigma[i] = sigma[j];
@@ -440,7 +489,7 @@ int or_sweep(const int32_t L[3], const int32_t B[3], int S, int K, const int32_t
             *accepted += acc_set;
         }
         if (E_trace) E_trace[t] = *E;
-        if (counts_trace) or_pair_counts(L, S, K, sigma, counts_trace + (size_t)t * S * K * K);
+        if (counts_trace) or_pair_counts(lat, L, S, K, sigma, counts_trace + (size_t)t * S * K * K);
     }
     free(colour);
     free(sub);
@@ -465,10 +514,10 @@ static int next_multiset_permutation(uint8_t* a, int64_t n)
     return 1;
 }
 
-int64_t or_enumerate(const int32_t L[3], int S, int K, const int32_t* epi,
+int64_t or_enumerate(int lat, const int32_t L[3], int S, int K, const int32_t* epi,
                      const int32_t* comp, int64_t max_cfg, int64_t* E_all, uint64_t* counts_all)
 {
-    int64_t N = n_sites(L), tot = 0;
+    int64_t N = n_sites(lat, L), tot = 0;
     for (int p = 0; p < K; ++p) tot += comp[p];
     if (tot != N) return -1;
     uint8_t* a = (uint8_t*)malloc(N);
@@ -478,8 +527,8 @@ int64_t or_enumerate(const int32_t L[3], int S, int K, const int32_t* epi,
     int64_t cfg = 0;
     do {
         if (cfg >= max_cfg) { free(a); return -1; }
-        if (E_all) E_all[cfg] = or_energy(L, S, K, epi, a);
-        if (counts_all) or_pair_counts(L, S, K, a, counts_all + (size_t)cfg * S * K * K);
+        if (E_all) E_all[cfg] = or_energy(lat, L, S, K, epi, a);
+        if (counts_all) or_pair_counts(lat, L, S, K, a, counts_all + (size_t)cfg * S * K * K);
         ++cfg;
     } while (next_multiset_permutation(a, N));
     free(a);

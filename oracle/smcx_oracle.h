@@ -34,7 +34,8 @@
  *     generator.
  *
  * Conventions (all readings, see smcx_oracle.c):
- *   site id   i = ((z*Ly + y)*Lx + x)*2 + b, b = 0 corner, b = 1 body centre
+ *   lat       0 = BCC (2 sites per cubic cell), 1 = FCC (4 sites per cell)
+ *   site id   i = ((z*Ly + y)*Lx + x)*n_sub + b
  *   energies  int32 micro-eV per pair, table epi[s][p][q], s = shell 0..S-1
  *   k_B       86.17333262 micro-eV/K (CODATA 2018)
  */
@@ -73,20 +74,21 @@ void or_sweep_shift(const int32_t L[3], uint64_t seed, uint32_t s, int32_t shift
 
 /* Per-site schedule of sweep s: colour (0..7), sub-colour (0..53) and the
  * linear index of the block the site belongs to. */
-void or_schedule(const int32_t L[3], const int32_t B[3], uint64_t seed, uint32_t s,
+void or_schedule(int lat, const int32_t L[3], const int32_t B[3], uint64_t seed, uint32_t s,
                  uint8_t* colour, uint8_t* subcolour, int64_t* block);
 
 /* Site index of neighbour `k` of site i, k indexing the displacement set of
  * shells 1..S in the order documented in smcx_oracle.c. */
-int64_t or_neighbour(const int32_t L[3], int64_t i, int k);
-int or_shell_size(int s);
+int64_t or_neighbour(int lat, const int32_t L[3], int64_t i, int k);
+int or_shell_size(int lat, int s);
+int or_n_sub(int lat);
 
 /* Total energy (micro-eV), pair counts and Warren-Cowley SRO. */
-int64_t or_energy(const int32_t L[3], int S, int K, const int32_t* epi, const uint8_t* sigma);
-int64_t or_delta_energy(const int32_t L[3], int S, int K, const int32_t* epi,
+int64_t or_energy(int lat, const int32_t L[3], int S, int K, const int32_t* epi, const uint8_t* sigma);
+int64_t or_delta_energy(int lat, const int32_t L[3], int S, int K, const int32_t* epi,
                         const uint8_t* sigma, int64_t i, int64_t j);
-void or_pair_counts(const int32_t L[3], int S, int K, const uint8_t* sigma, uint64_t* counts);
-void or_sro(const int32_t L[3], int S, int K, const uint8_t* sigma, double* alpha,
+void or_pair_counts(int lat, const int32_t L[3], int S, int K, const uint8_t* sigma, uint64_t* counts);
+void or_sro(int lat, const int32_t L[3], int S, int K, const uint8_t* sigma, double* alpha,
             uint64_t* counts /* nullable */);
 
 /* Run n sweeps, sweep indices s0 .. s0+n-1, temperature T[k] for sweep s0+k.
@@ -94,7 +96,7 @@ void or_sro(const int32_t L[3], int S, int K, const uint8_t* sigma, double* alph
  * E_trace (nullable) receives the energy after every sweep; counts_trace
  * (nullable) the pair counts [S][K][K] after every sweep.
  * Returns 0, or -1 on invalid arguments. */
-int or_sweep(const int32_t L[3], const int32_t B[3], int S, int K, const int32_t* epi,
+int or_sweep(int lat, const int32_t L[3], const int32_t B[3], int S, int K, const int32_t* epi,
              uint64_t seed, uint32_t s0, int32_t n, const double* T, uint8_t* sigma,
              int64_t* E, uint64_t* accepted, int64_t* E_trace, uint64_t* counts_trace);
 
@@ -105,7 +107,7 @@ int or_exchange_accept(int64_t Ea, int64_t Eb, double Ta, double Tb, uint64_t se
 /* Exact enumeration over every configuration with the given composition.
  * Fills E_all[cfg] (nullable) and returns the number of configurations, or
  * -1 if it exceeds max_cfg. */
-int64_t or_enumerate(const int32_t L[3], int S, int K, const int32_t* epi,
+int64_t or_enumerate(int lat, const int32_t L[3], int S, int K, const int32_t* epi,
                      const int32_t* comp, int64_t max_cfg, int64_t* E_all,
                      uint64_t* counts_all /* nullable: [cfg][S][K][K] */);
 

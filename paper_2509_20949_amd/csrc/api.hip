@@ -369,9 +369,9 @@ smcx_status smcx_create(const smcx_desc* desc, const uint8_t* species, const int
 smcx_status smcx_create_device(const smcx_desc* desc, uint8_t* d_species, const int32_t* epi_ueV, double T_kelvin,
                                void* hip_stream, smcx_ctx** out)
 {
-    if (!d_species) {
+    if (!d_species || ((uintptr_t)d_species & 3u)) {
         if (out) *out = nullptr;
-        return fail_global(SMCX_E_INVALID, "d_species is NULL");
+        return fail_global(SMCX_E_INVALID, "d_species is NULL or not 4-byte aligned");
     }
     return create_common(desc, nullptr, d_species, epi_ueV, T_kelvin, hip_stream, out);
 }

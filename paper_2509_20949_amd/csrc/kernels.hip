@@ -30,6 +30,16 @@ __device__ __forceinline__ uint32_t encode2(uint32_t two_species, int F)
 
 __device__ __forceinline__ uint32_t decode(uint32_t code) { return code >> 5; }
 
+// acc + a * b on the 24-bit multiplier (a, b signed 24-bit), modulo 2^32:
+// one v_mad_i32_i24 (the compiler otherwise splits it into a multiply and a
+// three-input add)
+__device__ __forceinline__ uint32_t mad24(uint32_t a, int32_t b, uint32_t acc)
+{
+    uint32_t r;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(acc));
+    return r;
+}
+
 // LDS layout of one block (see smcx_internal.h): corner array at offset 0,
 // body array at kArr.  Local cell (x, y, z):
 //   corner: (z+1)*kPP + (y+1)*kP + (x+1)       x in -1..13
@@ -109,8 +119,9 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u_dir, uint
     // the row index into the table (their result is discarded)
     const uint32_t a = min(decode(ci), (uint32_t)(KMAX - 1)), b = min(decode(cj), (uint32_t)(KMAX - 1));
     const int32_t* w = wtab + (a * KMAX + b) * WR;
-    // Accumulate modulo 2^32: the constant may leave the int32 range for
-    // extreme tables, the true dE (|dE| < 2^29) never does.
+    // The constant may leave the int32 range for extreme tables while the
+    // true dE (|dE| < 2^29) never does: the 32-bit multiply-adds wrap, and
+    // the wrapped sum is exact.
     uint32_t acc = (uint32_t)w[SMAX * KMAX];
 #pragma unroll
     for (int s = 0; s < SMAX; ++s) {
@@ -118,13 +129,12 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u_dir, uint
             const uint32_t d = hi[s] - hj[s];   // fields 16 + n_i - n_j, no borrows
 #pragma unroll
             for (int p = 0; p < KMAX; ++p)
-                acc += (uint32_t)__mul24((int32_t)((d >> (5 * p)) & 31u), w[s * KMAX + p]);
+                acc = mad24((d >> (5 * p)) & 31u, w[s * KMAX + p], acc);
         } else {
 #pragma unroll
             for (int p = 0; p < KMAX; ++p)
-                acc += (uint32_t)__mul24((int32_t)((hi[s] >> (4 * p)) & 15u) -
-                                             (int32_t)((hj[s] >> (4 * p)) & 15u),
-                                         w[s * KMAX + p]);
+                acc = mad24((uint32_t)((int32_t)((hi[s] >> (4 * p)) & 15u) - (int32_t)((hj[s] >> (4 * p)) & 15u)),
+                            w[s * KMAX + p], acc);
         }
     }
     const int32_t dE = (int32_t)acc;
@@ -209,8 +219,41 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
     uint8_t* lat = s_lat + wave * kWaveLds;
     uint8_t* __restrict__ g = D.species;
 
+    // cell ids fit 32 bits and the 24-bit multiplier (the usual case)
+    const uint32_t LxLy = (uint32_t)Lx * (uint32_t)Ly;
+    const bool narrow = LxLy < (1u << 24) && (uint64_t)LxLy * (uint32_t)Lz < (1ull << 32);
+
     // ---- stage block + halo: local cells -2..w+1 on each axis ----
-    {
+    // Fast path (the block's x-range does not cross the periodic boundary):
+    // 8 lanes per row, each reading two cells (corner, body, corner, body
+    // bytes) as one aligned dword, or two when the cells start 2 bytes into
+    // a dword (rows of an odd-length lattice alternate).  The lattice base is
+    // 4-byte aligned.
+    if (gx0 >= 3 && gx0 + wx + 4 <= Lx) {
+        const int lx0 = 2 * (lane & 7) - 2;       // cells lx0, lx0 + 1
+        const bool lane_ok = lx0 <= wx + 1;
+        const bool c0 = lx0 >= -1, c1 = lx0 + 1 <= wx + 1, b0 = lx0 <= wx, b1 = lx0 + 1 <= wx;
+        for (int r = lane >> 3; r < 256; r += 8) {
+            const int ly = (r & 15) - 2, lz = (r >> 4) - 2;
+            if (!lane_ok || ly > wy + 1 || lz > wz + 1) continue;
+            const uint32_t gy = (uint32_t)wrap_add(gy0 + ly, Ly), gz = (uint32_t)wrap_add(gz0 + lz, Lz);
+            const size_t row = narrow ? (size_t)(__umul24(gz, LxLy) + __umul24(gy, (uint32_t)Lx))
+                                      : ((size_t)gz * (uint32_t)Ly + gy) * (uint32_t)Lx;
+            const size_t at = 2 * (row + (size_t)(gx0 + lx0));      // byte of corner(lx0)
+            const uint32_t* q = (const uint32_t*)(g + (at & ~(size_t)3));
+            uint32_t v = q[0];
+            if (at & 2) v = __builtin_amdgcn_alignbyte(q[1], v, 2);
+            v = encode2(v, F);
+            const int crow = (lz + 1) * kPP + (ly + 1) * kP + (lx0 + 1);
+            const int brow = kArr + (lz + 2) * kPP + (ly + 2) * kP + (lx0 + 2);
+            const bool cy = ly >= -1 && lz >= -1, by = ly <= wy && lz <= wz;
+            if (cy && c0) lat[crow] = (uint8_t)v;
+            if (cy && c1) lat[crow + 1] = (uint8_t)(v >> 16);
+            if (by && b0) lat[brow] = (uint8_t)(v >> 8);
+            if (by && b1) lat[brow + 1] = (uint8_t)(v >> 24);
+        }
+    } else {
+        // a periodic wrap along x: one cell (two bytes) per lane
         const int lx = (lane & 15) - 2;
         const bool okx = lx <= wx + 1;
         const int gx = wrap_add(gx0 + lx, Lx);
@@ -228,28 +271,77 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
     }
 
     // ---- 27 residue classes x 2 sublattices = 54 rounds ----
+    // Lane (ix, iy, iz) takes local cell (rx + 3 ix, ry + 3 iy, rz + 3 iz) of
+    // residue class (rx, ry, rz); lanes past the block edge only compute.
     const int ix = lane & 3, iy = (lane >> 2) & 3, iz = lane >> 4;
+    const int lane_c = (3 * iz + 1) * kPP + (3 * iy + 1) * kP + (3 * ix + 1);
+    constexpr int kBodyFromCorner = kArr + kPP + kP + 1;
+    // global coordinates of the lane's cell in class (0,0,0); below 2L, and
+    // below 2L after adding r < 3 for every lane that holds a site
+    const uint32_t bx = (uint32_t)(gx0 + 3 * ix), by = (uint32_t)(gy0 + 3 * iy), bz = (uint32_t)(gz0 + 3 * iz);
     int64_t dEsum = 0;
     uint32_t nacc = 0;
     const uint32_t k0 = D.key[0], k1 = D.key[1];
     for (int m = 0; m < 27; ++m) {
         const int rx = m % 3, ry = (m / 3) % 3, rz = m / 9;
-        const int lx = rx + 3 * ix, ly = ry + 3 * iy, lz = rz + 3 * iz;
-        const bool valid = lx < wx && ly < wy && lz < wz;
-        const int gx = wrap_add(gx0 + lx, Lx), gy = wrap_add(gy0 + ly, Ly), gz = wrap_add(gz0 + lz, Lz);
-        const uint64_t cell = ((uint64_t)gz * (uint32_t)Ly + (uint32_t)gy) * (uint32_t)Lx + (uint32_t)gx;
+        const bool valid = 3 * ix < wx - rx && 3 * iy < wy - ry && 3 * iz < wz - rz;
+        uint32_t gx = bx + rx, gy = by + ry, gz = bz + rz;
+        gx = min(gx, gx - (uint32_t)Lx);   // periodic wrap of [0, 2L)
+        gy = min(gy, gy - (uint32_t)Ly);
+        gz = min(gz, gz - (uint32_t)Lz);
+        uint64_t cell;
+        if (narrow)
+            cell = __umul24(gz, LxLy) + __umul24(gy, (uint32_t)Lx) + gx;
+        else
+            cell = ((uint64_t)gz * (uint32_t)Ly + gy) * (uint32_t)Lx + gx;
         uint32_t r[4] = {(uint32_t)cell, (uint32_t)(cell >> 32), s, (uint32_t)colour};
         philox4x32_10(r, k0, k1);
-        const int ac = (lz + 1) * kPP + (ly + 1) * kP + (lx + 1);
-        const int ab = kArr + (lz + 2) * kPP + (ly + 2) * kP + (lx + 2);
+        const int ac = lane_c + (rz * kPP + ry * kP + rx);
         trial<KMAX, SMAX, 0>(lat, ac, r[0], r[1], valid, s_w, s_tab, dEsum, nacc);
         __builtin_amdgcn_wave_barrier();
-        trial<KMAX, SMAX, 1>(lat, ab, r[2], r[3], valid, s_w, s_tab, dEsum, nacc);
+        trial<KMAX, SMAX, 1>(lat, ac + kBodyFromCorner, r[2], r[3], valid, s_w, s_tab, dEsum, nacc);
         __builtin_amdgcn_wave_barrier();
     }
 
     // ---- write back: corner cells 0..w, body cells -1..w-1 ----
-    {
+    // Fast path (no periodic wrap along x): 8 lanes per row, each owning one
+    // aligned dword of the row's span (corner(-1) .. body(w)); it stores the
+    // dword whole, or only its bytes that belong to the corner box [0, w]^3
+    // or the body box [-1, w-1]^3 where the span or a box ends.
+    if (gx0 >= 1 && gx0 + wx < Lx) {
+        for (int r = lane >> 3; r < 256; r += 8) {
+            const int ly = (r & 15) - 1, lz = (r >> 4) - 1;
+            if (ly > wy || lz > wz) continue;
+            const uint32_t gy = (uint32_t)wrap_add(gy0 + ly, Ly), gz = (uint32_t)wrap_add(gz0 + lz, Lz);
+            const size_t row = narrow ? (size_t)(__umul24(gz, LxLy) + __umul24(gy, (uint32_t)Lx))
+                                      : ((size_t)gz * (uint32_t)Ly + gy) * (uint32_t)Lx;
+            const size_t at0 = 2 * (row + (size_t)gx0);             // byte of corner(0)
+            const size_t d = ((at0 - 2) & ~(size_t)3) + 4u * (uint32_t)(lane & 7);
+            const int lxa = (int)((int64_t)(d - at0) / 2);          // cells lxa, lxa + 1
+            const bool cy = ly >= 0 && lz >= 0, by = ly < wy && lz < wz;
+            const bool v0 = cy && lxa >= 0 && lxa <= wx;              // corner(lxa)
+            const bool v1 = by && lxa >= -1 && lxa < wx;              // body(lxa)
+            const bool v2 = cy && lxa + 1 >= 0 && lxa + 1 <= wx;      // corner(lxa + 1)
+            const bool v3 = by && lxa + 1 >= -1 && lxa + 1 < wx;      // body(lxa + 1)
+            if (!(v0 || v1 || v2 || v3)) continue;
+            const int crow = (lz + 1) * kPP + (ly + 1) * kP + (lxa + 1);
+            const int brow = kArr + (lz + 2) * kPP + (ly + 2) * kP + (lxa + 2);
+            const uint32_t e0 = v0 ? decode(lat[crow]) : 0u;
+            const uint32_t e1 = v1 ? decode(lat[brow]) : 0u;
+            const uint32_t e2 = v2 ? decode(lat[crow + 1]) : 0u;
+            const uint32_t e3 = v3 ? decode(lat[brow + 1]) : 0u;
+            uint8_t* q = g + d;
+            if (v0 && v1 && v2 && v3) {
+                *(uint32_t*)q = e0 | e1 << 8 | e2 << 16 | e3 << 24;
+            } else {
+                if (v0) q[0] = (uint8_t)e0;
+                if (v1) q[1] = (uint8_t)e1;
+                if (v2) q[2] = (uint8_t)e2;
+                if (v3) q[3] = (uint8_t)e3;
+            }
+        }
+    } else {
+        // a periodic wrap along x: one cell (two bytes) per lane
         const int lx = (lane & 15) - 1;
         const bool okx = lx <= wx;
         const int gx = wrap_add(gx0 + lx, Lx);

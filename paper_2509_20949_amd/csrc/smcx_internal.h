@@ -58,7 +58,17 @@ struct WorkItem {
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64
-// multiplies; key bumped by the Weyl constants between rounds.
+// multiplies; key bumped by the Weyl constants between rounds.  On the
+// device each round's two three-way XORs are single v_bitop3 instructions.
+__host__ __device__ inline uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+#else
+    return a ^ b ^ c;
+#endif
+}
+
 __host__ __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1)
 {
     uint32_t x0 = c[0], x1 = c[1], x2 = c[2], x3 = c[3];
@@ -66,8 +76,8 @@ __host__ __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * x0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), x1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), x3, k1);
         x1 = (uint32_t)p1;
         x3 = (uint32_t)p0;
         x0 = n0;
