@@ -22,20 +22,26 @@
  * Conventions shared by every entry point
  * ---------------------------------------
  * Lattice.  Cells (x, y, z), 0 <= x < L[0] etc., periodic on every axis,
- *   two sites per cell: b = 0 at the cube corner, b = 1 at the body centre.
- *   Canonical site id i = ((z*L[1] + y)*L[0] + x)*2 + b.  Species arrays
- *   hold one uint8 per site in canonical order, values 0..K-1.
+ *   n_sub sites per cell at offsets (in units of a/2) BCC: b = 0 (0,0,0),
+ *   b = 1 (1,1,1); FCC: (0,0,0), (1,1,0), (1,0,1), (0,1,1).  Canonical site
+ *   id i = ((z*L[1] + y)*L[0] + x)*n_sub + b.  Species arrays hold one
+ *   uint8 per site in canonical order, values 0..K-1.
  * Energy.  E = 1/2 sum_i sum_{delta in shells 1..S} V_s(sigma_i,
- *   sigma_{i+delta}); shell 1 = 8 first neighbours (+-a/2, +-a/2, +-a/2),
- *   shell 2 = 6 at (+-a, 0, 0), shell 3 = 12 at (+-a, +-a, 0).  The EPI table
+ *   sigma_{i+delta}).  BCC shells: 8 at (+-a/2, +-a/2, +-a/2), 6 at
+ *   (+-a, 0, 0), 12 at (+-a, +-a, 0); FCC shells: 12 at (+-a/2, +-a/2, 0),
+ *   6 at (+-a, 0, 0), 24 at (+-a, +-a/2, +-a/2) (and permutations).  The EPI table
  *   is int32 micro-eV, layout epi[s][p][q] (S*K*K entries), symmetric in
  *   (p, q), |V| < 2^22.  Energies are exact int64 micro-eV.
- * Trial.  Sweep s, colour phase c: site i draws Philox4x32-10 with key =
- *   (seed & 0xffffffff, seed >> 32) and counter = (cell & 0xffffffff,
- *   cell >> 32, s, c); a corner site uses output words 0 and 1, a body
- *   site words 2 and 3.  The first word's top 3 bits pick the partner
- *   among the 8 first neighbours (bit a set = +a/2 along axis a); the
- *   second word u accepts an uphill swap iff dE < 2^24 and
+ * Trial.  Sweep s, colour phase c: site b of a cell draws Philox4x32-10
+ *   with key = (seed & 0xffffffff, seed >> 32) and counter = (cell &
+ *   0xffffffff, cell >> 32, s, c + 16*(b >> 1)), using output words
+ *   2*(b & 1) and 2*(b & 1) + 1.  BCC: the first word's top 3 bits pick the
+ *   partner among the 8 first neighbours (bit a set = +a/2 along axis a).
+ *   FCC: all trials of one (sweep, colour, sub-colour q) set take their
+ *   partner in one sublattice b' = the k-th sublattice other than b, k =
+ *   (t * 3) >> 32, t = word 0 of Philox4x32-10(key, (q, 0, s, c + 64)); bits
+ *   30 and 31 of the first word give the signs (+a/2 when set) on the two
+ *   axes where b and b' differ.  The second word u accepts an uphill swap iff dE < 2^24 and
  *   (double)u < (T2[dE>>16] * T1[(dE>>8)&255]) * T0[dE&255], with
  *   beta = 1 / (86.17333262 * T) per micro-eV and
  *   T0[l] = exp(-l beta), T1[m] = exp(-256 m beta),
@@ -45,8 +51,8 @@
  *   with bounds floor(k L / n); sweep s shifts the block grid by
  *   o_a = (r_a * L_a) >> 32 with r = Philox4x32-10(key, (0, 0, s, 8)).
  *   A site's colour is the parity pattern of its block indices, its
- *   sub-colour (((l_z%3)*3 + l_y%3)*3 + l_x%3)*2 + b from its local cell
- *   coordinates; phases run c = 0..7, rounds q = 0..53.  Trials of one
+ *   sub-colour (((l_z%3)*3 + l_y%3)*3 + l_x%3)*n_sub + b from its local cell
+ *   coordinates; phases run c = 0..7, rounds q = 0..27*n_sub-1.  Trials of one
  *   (c, q) set never interact, nor do blocks of one colour, so the result is
  *   that of the sequential order (c, q, site id) bit for bit.
  *
@@ -77,18 +83,20 @@ typedef struct smcx_server smcx_server;
 typedef enum {
     SMCX_OK = 0,
     SMCX_E_INVALID = -1,      /* bad pointer, size, species >= K, asymmetric EPI */
-    SMCX_E_UNSUPPORTED = -2,  /* valid for the method, not for this library (L < 4, B > 12, K > 8, S > 3) */
+    SMCX_E_UNSUPPORTED = -2,  /* valid for the method, not for this library (L < 4, B > 12, K > 8, S > 3,
+                                 FCC with K > 5) */
     SMCX_E_NOMEM = -3,        /* device or host allocation failed, or over budget */
     SMCX_E_DEVICE = -4,       /* a HIP runtime call failed */
     SMCX_E_RANGE = -5,        /* |V| >= 2^22, T outside [1, 5000] K, sweep counter overflow */
     SMCX_E_STATE = -6         /* call not valid in the object's current state */
 } smcx_status;
 
-enum { SMCX_LATTICE_BCC = 0 };
+enum { SMCX_LATTICE_BCC = 0, SMCX_LATTICE_FCC = 1 };
 enum { SMCX_MAX_SPECIES = 8, SMCX_MAX_SHELLS = 3, SMCX_MAX_BLOCK = 12 };
 
 typedef struct {
-    int32_t lattice;    /* SMCX_LATTICE_BCC */
+    int32_t lattice;    /* SMCX_LATTICE_BCC (2 sites per cubic cell) or
+                           SMCX_LATTICE_FCC (4 sites per cell, K <= 5) */
     int32_t L[3];       /* cells per axis, each >= 4 */
     int32_t n_species;  /* K, 2..8 */
     int32_t n_shells;   /* S, 1..3 */
@@ -100,7 +108,7 @@ typedef struct {
 } smcx_desc;
 
 /* ---- single lattice ----------------------------------------------------
- * smcx_create: copies N = 2*L0*L1*L2 species bytes and the S*K*K EPI table,
+ * smcx_create: copies N = n_sub*L0*L1*L2 species bytes and the S*K*K EPI table,
  * allocates the lattice on the current HIP device and creates a stream.
  * T is the temperature of every sweep until changed.  The sweep counter
  * starts at 0.  Errors: INVALID, UNSUPPORTED, RANGE, NOMEM, DEVICE. */

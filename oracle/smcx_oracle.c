@@ -8,20 +8,20 @@
  * Paper: arXiv:2509.20949 (SMC-X).  Citations name the section and equation.
  *
  * ---------------------------------------------------------------------------
- * Geometry (reading; the paper's production lattice is FCC, this path is BCC)
- *   Cells (x, y, z), 0 <= x < Lx etc., two sites per cell: b = 0 at the cube
- *   corner, b = 1 at the body centre.  In "doubled" coordinates (units of half
- *   the lattice constant) a site sits at X = 2x + b, Y = 2y + b, Z = 2z + b.
- *   Boundaries are periodic on every axis (the paper simulates supercells;
- *   it states no boundary condition).
- *   Site id i = ((z*Ly + y)*Lx + x)*2 + b.
+ * Geometry (reading; the paper's production lattice is FCC, the benchmark
+ * lattice is BCC; both are implemented)
+ *   Cells (x, y, z), 0 <= x < Lx etc., n_sub sites per cell: BCC 2 (corner,
+ *   body centre), FCC 4 (corner, three face centres).  In "doubled"
+ *   coordinates (units of half the lattice constant) site b of a cell sits at
+ *   (2x, 2y, 2z) + SUB[b].  Periodic on every axis (the paper simulates
+ *   supercells; it states no boundary condition).
+ *   Site id i = ((z*Ly + y)*Lx + x)*n_sub + b.
  *
  * Neighbour shells in doubled coordinates:
- *   shell 1 (8):  (+-1, +-1, +-1)        first neighbours, other sublattice
- *   shell 2 (6):  (+-2, 0, 0) and perms   second neighbours, same sublattice
- *   shell 3 (12): (+-2, +-2, 0) and perms third neighbours, same sublattice
- *   Shell-1 vector number `dir` (0..7) has component +1 on axis a when bit a
- *   of dir is set, -1 otherwise.
+ *   BCC: 8 (+-1,+-1,+-1); 6 (+-2,0,0); 12 (+-2,+-2,0) and permutations
+ *   FCC: 12 (+-1,+-1,0); 6 (+-2,0,0); 24 (+-2,+-1,+-1) and permutations
+ *   BCC first-shell vector number `dir` (0..7) has component +1 on axis a
+ *   when bit a of dir is set, -1 otherwise.
  *
  * Energy (reading of the EPI model, Section "Results and discussion": pair
  * interactions only):  E = 1/2 sum_i sum_{delta in shells 1..S}
@@ -427,6 +427,41 @@ static int valid_inputs(const int32_t L[3], const int32_t B[3], int S, int K, co
     return 1;
 }
 
+/* FCC partner choice (reading; the paper states none).  A site of
+ * sublattice b has 12 first neighbours, 4 in each other sublattice.  The
+ * partner sublattice b' of every trial of one (sweep s, colour c,
+ * sub-colour q) set is drawn once: k = (t * 3) >> 32 with t = word 0 of
+ * Philox4x32-10(key, (q, 0, s, c + 64)), b' = the k-th sublattice other
+ * than b in increasing order.  The trial then takes the neighbour
+ * (+-1, +-1) on the two axes where b and b' differ, the top two bits of its
+ * direction word giving the signs (bit 30: first axis, bit 31: second,
+ * set = +1).  Marginally each trial's partner is uniform over the 12. */
+static int fcc_partner_sublattice(const uint32_t key[2], uint32_t s, int c, int q)
+{
+    uint32_t ctr[4] = {(uint32_t)q, 0u, s, (uint32_t)c + 64u};
+    uint32_t r[4];
+    or_philox4x32_10(ctr, key, r);
+    int b = q % 4, k = (int)(((uint64_t)r[0] * 3u) >> 32);
+    for (int bp = 0; bp < 4; ++bp) {
+        if (bp == b) continue;
+        if (k-- == 0) return bp;
+    }
+    return -1;
+}
+
+static int64_t fcc_partner(const int32_t L[3], int64_t i, int bp, uint32_t u_dir)
+{
+    int b = (int)(i % 4);
+    int d[3] = {0, 0, 0};
+    int bit = 30;
+    for (int a = 0; a < 3; ++a)
+        if (SUB_FCC[b][a] != SUB_FCC[bp][a]) {
+            d[a] = ((u_dir >> bit) & 1u) ? +1 : -1;
+            ++bit;
+        }
+    return site_at(1, L, decode_site(1, L, i), d);
+}
+
 int or_sweep(int lat, const int32_t L[3], const int32_t B[3], int S, int K, const int32_t* epi,
              uint64_t seed, uint32_t s0, int32_t n, const double* T, uint8_t* sigma,
              int64_t* E, uint64_t* accepted, int64_t* E_trace, uint64_t* counts_trace)
@@ -441,6 +476,7 @@ int or_sweep(int lat, const int32_t L[3], const int32_t B[3], int S, int K, cons
     uint8_t* sub = (uint8_t*)malloc(N);
     int64_t* order = (int64_t*)malloc(sizeof(int64_t) * N);
     int64_t start[8 * 27 * 4 + 1];
+    int partner_sub[8 * 27 * 4];
     double tab[768];
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
 
@@ -454,6 +490,10 @@ int or_sweep(int lat, const int32_t L[3], const int32_t B[3], int S, int K, cons
         for (int g = 0; g < ngroups; ++g) start[g + 1] += start[g];
         for (int64_t i = 0; i < N; ++i) order[start[colour[i] * 27 * nsub + sub[i]]++] = i;
 
+        /* FCC: one partner sublattice per (colour, sub-colour) set */
+        if (lat == 1)
+            for (int g = 0; g < ngroups; ++g)
+                partner_sub[g] = fcc_partner_sublattice(key, s, g / (27 * nsub), g % (27 * nsub));
         for (int g = 0; g < ngroups; ++g) {
             int64_t lo = g == 0 ? 0 : start[g - 1], hi = start[g];
             int64_t dE_set = 0;
@@ -471,10 +511,8 @@ int or_sweep(int lat, const int32_t L[3], const int32_t B[3], int S, int K, cons
                 uint32_t rnd[4];
                 or_philox4x32_10(ctr, key, rnd);
                 uint32_t u_dir = rnd[2 * (b & 1)], u_acc = rnd[2 * (b & 1) + 1];
-                /* partner: uniform over the first shell (8 BCC vectors from the
-                 * top 3 bits; 12 FCC vectors from the high word of u * 12) */
-                int dir = lat == 1 ? (int)(((uint64_t)u_dir * 12u) >> 32) : (int)(u_dir >> 29);
-                int64_t j = or_neighbour(lat, L, i, dir);
+                int64_t j = lat == 1 ? fcc_partner(L, i, partner_sub[g], u_dir)
+                                     : or_neighbour(lat, L, i, (int)(u_dir >> 29));
                 if (sigma[i] == sigma[j]) continue;
                 int64_t dE = or_delta_energy(lat, L, S, K, epi, sigma, i, j);
                 if (or_accept(dE, u_acc, tab)) {

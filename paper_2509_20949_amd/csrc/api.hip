@@ -45,7 +45,8 @@ smcx_status fail(smcx_ctx* c, smcx_status st, const char* fmt, ...)
 smcx_status validate_desc(const smcx_desc* d, int32_t block_out[3], bool for_gpu)
 {
     if (!d) return fail_global(SMCX_E_INVALID, "desc is NULL");
-    if (d->lattice != SMCX_LATTICE_BCC) return fail_global(SMCX_E_UNSUPPORTED, "only the BCC lattice is supported");
+    if (d->lattice != SMCX_LATTICE_BCC && d->lattice != SMCX_LATTICE_FCC)
+        return fail_global(SMCX_E_INVALID, "lattice = %d is neither BCC (0) nor FCC (1)", d->lattice);
     for (int a = 0; a < 3; ++a) {
         if (d->L[a] < 2) return fail_global(SMCX_E_INVALID, "L[%d] = %d < 2", a, d->L[a]);
         if (for_gpu && d->L[a] < 4)
@@ -62,6 +63,8 @@ smcx_status validate_desc(const smcx_desc* d, int32_t block_out[3], bool for_gpu
     if (d->n_shells < 1 || d->n_shells > kMaxS)
         return fail_global(d->n_shells < 1 ? SMCX_E_INVALID : SMCX_E_UNSUPPORTED, "n_shells = %d outside 1..%d",
                            d->n_shells, kMaxS);
+    if (d->lattice == SMCX_LATTICE_FCC && d->n_species > 5)
+        return fail_global(SMCX_E_UNSUPPORTED, "FCC lattices support up to 5 species");
     return SMCX_OK;
 }
 
@@ -86,7 +89,10 @@ smcx_status validate_T(double T)
     return SMCX_OK;
 }
 
-size_t n_sites(const int32_t L[3]) { return 2 * (size_t)L[0] * L[1] * L[2]; }
+size_t n_sites(int lattice, const int32_t L[3])
+{
+    return (size_t)sites_per_cell(lattice) * (size_t)L[0] * L[1] * L[2];
+}
 
 // ---- context internals ------------------------------------------------------
 smcx_status ctx_hip(smcx_ctx* c, hipError_t e, const char* what)
@@ -105,6 +111,7 @@ void fill_geometry(DevLattice& L, const smcx_desc* d, const int32_t B[3])
     L.key[0] = (uint32_t)d->seed;
     L.key[1] = (uint32_t)(d->seed >> 32);
     L.K = d->n_species;
+    L.lattice = d->lattice;
     L.blocks_per_colour = (L.nb[0] / 2) * (L.nb[1] / 2) * (L.nb[2] / 2);
 }
 
@@ -151,8 +158,8 @@ smcx_status recompute_energy(smcx_ctx* c, int64_t* E)
     smcx_status st = ctx_hip(c, hipMemsetAsync(c->d_counts, 0, sizeof(unsigned long long) * kMaxS * kMaxK * kMaxK,
                                                c->stream), "hipMemsetAsync");
     if (st) return st;
-    st = ctx_hip(c, launch_pair_counts(c->h_lat.species, c->h_lat.L, c->K, c->S, c->d_counts, c->stream),
-                 "pair_counts launch");
+    st = ctx_hip(c, launch_pair_counts(c->h_lat.lattice, c->h_lat.species, c->h_lat.L, c->K, c->S, c->d_counts,
+                                       c->stream), "pair_counts launch");
     if (st) return st;
     unsigned long long h[kMaxS * kMaxK * kMaxK];
     st = ctx_hip(c, hipMemcpyAsync(h, c->d_counts, sizeof(h), hipMemcpyDeviceToHost, c->stream), "hipMemcpyAsync");
@@ -175,8 +182,8 @@ static smcx_status ctx_init(smcx_ctx* c, const smcx_desc* d, const int32_t B[3],
     for (int a = 0; a < 3; ++a) c->B[a] = B[a];
     c->K = d->n_species;
     c->S = d->n_shells;
-    c->N = n_sites(d->L);
-    c->kmax = kmax_for(c->K);
+    c->N = n_sites(d->lattice, d->L);
+    c->kmax = kmax_for(d->lattice, c->K);
     c->smax = c->S;
     c->epi.assign(epi, epi + (size_t)c->S * c->K * c->K);
     std::memset(&c->h_lat, 0, sizeof(DevLattice));
@@ -192,7 +199,7 @@ static smcx_status ctx_init(smcx_ctx* c, const smcx_desc* d, const int32_t B[3],
     if (st) return st;
     const int wr = wrow(c->kmax, c->smax);
     std::vector<int32_t> w((size_t)c->kmax * c->kmax * wr);
-    build_wtab(epi, c->K, c->S, c->kmax, c->smax, w.data());
+    build_wtab(epi, c->K, c->S, c->kmax, c->smax, wtab_bias(d->lattice, c->kmax), w.data());
     st = ctx_hip(c, hipMalloc(&c->d_wtab, sizeof(int32_t) * w.size()), "hipMalloc(weights)");
     if (st) return st;
     st = ctx_hip(c, hipMemcpy(c->d_wtab, w.data(), sizeof(int32_t) * w.size(), hipMemcpyHostToDevice), "hipMemcpy(weights)");
@@ -259,7 +266,8 @@ smcx_status enqueue_sweeps(smcx_ctx* c, int32_t n)
                 c->events.push_back(e1);
                 (void)hipEventRecord(e0, c->stream);
             }
-            hipError_t e = launch_sweep_phase(c->d_lat, nullptr, groups, (int)s, col, c->kmax, c->smax, c->stream);
+            hipError_t e = launch_sweep_phase(c->h_lat.lattice, c->d_lat, nullptr, groups, (int)s, col, c->kmax, c->smax,
+                                              c->stream);
             if (e != hipSuccess) return ctx_hip(c, e, "sweep_phase launch");
             if (c->profiling) (void)hipEventRecord(c->events.back(), c->stream);
         }
@@ -304,7 +312,7 @@ static smcx_status create_common(const smcx_desc* desc, const uint8_t* species, 
     if (st) return st;
     st = validate_T(T);
     if (st) return st;
-    const size_t N = n_sites(desc->L);
+    const size_t N = n_sites(desc->lattice, desc->L);
     if (species) {
         for (size_t i = 0; i < N; ++i)
             if (species[i] >= desc->n_species)
@@ -437,11 +445,12 @@ smcx_status smcx_sro(smcx_ctx* c, double* alpha, uint64_t* counts)
     if (st) return st;
     const int K = c->K, S = c->S;
     const double N = (double)c->N;
-    const int Z[3] = {8, 6, 12};
+    const int lat = c->h_lat.lattice;
+    const int Z[3] = {shell_size(lat, 0), shell_size(lat, 1), shell_size(lat, 2)};
     std::vector<uint64_t> Np(K, 0);
     for (int p = 0; p < K; ++p)
         for (int q = 0; q < K; ++q) Np[p] += c->counts[(0 * kMaxK + p) * kMaxK + q];
-    for (int p = 0; p < K; ++p) Np[p] /= 8;   // each centre has 8 first neighbours
+    for (int p = 0; p < K; ++p) Np[p] /= (uint64_t)Z[0];   // every centre has Z_1 first neighbours
     for (int m = 0; m < S; ++m)
         for (int pc = 0; pc < K; ++pc)
             for (int p = 0; p < K; ++p) {

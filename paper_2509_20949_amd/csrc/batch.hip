@@ -21,7 +21,7 @@ using namespace smcx;
 
 struct smcx_batch {
     int n = 0;
-    int kmax = 2, smax = 1;
+    int kmax = 2, smax = 1, lattice = 0;
     hipStream_t stream = nullptr;
     uint8_t* d_species = nullptr;               // all lattices, 256-byte aligned slices
     DevLattice* d_lats = nullptr;
@@ -99,16 +99,19 @@ smcx_status smcx_batch_create(int32_t n, const smcx_desc* descs, const uint8_t* 
         if (!st) st = validate_T(T[r]);
         if (!st && !species[r]) st = fail_global(SMCX_E_INVALID, "species is NULL");
         if (st) return fail_global(st, "replica %d: %s", r, smcx_global_error());
-        const size_t N = n_sites(descs[r].L);
+        const size_t N = n_sites(descs[r].lattice, descs[r].L);
         for (size_t i = 0; i < N; ++i)
             if (species[r][i] >= descs[r].n_species)
                 return fail_global(SMCX_E_INVALID, "replica %d: species[%zu] >= K", r, i);
-        kmax = std::max(kmax, kmax_for(descs[r].n_species));
+        if (descs[r].lattice != descs[0].lattice)
+            return fail_global(SMCX_E_INVALID, "replica %d: all replicas of a batch share one lattice type", r);
+        kmax = std::max(kmax, kmax_for(descs[r].lattice, descs[r].n_species));
         smax = std::max(smax, (int)descs[r].n_shells);
     }
     smcx_batch* b = new (std::nothrow) smcx_batch();
     if (!b) return fail_global(SMCX_E_NOMEM, "host allocation failed");
     b->n = n;
+    b->lattice = descs[0].lattice;
     b->kmax = kmax;
     b->smax = smax;
     b->T.assign(T, T + n);
@@ -119,7 +122,7 @@ smcx_status smcx_batch_create(int32_t n, const smcx_desc* descs, const uint8_t* 
     size_t total = 0;
     for (int r = 0; r < n; ++r) {
         off[r] = total;
-        total += align256(n_sites(descs[r].L));
+        total += align256(n_sites(descs[r].lattice, descs[r].L));
     }
     smcx_status st = bhip(b, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking), "hipStreamCreate");
     if (!st) st = bhip(b, hipMalloc(&b->d_species, total), "hipMalloc(lattices)");
@@ -136,10 +139,10 @@ smcx_status smcx_batch_create(int32_t n, const smcx_desc* descs, const uint8_t* 
     b->first_static.resize(n);
     for (int r = 0; r < n && !st; ++r) {
         const smcx_desc& d = descs[r];
-        const size_t N = n_sites(d.L);
+        const size_t N = n_sites(d.lattice, d.L);
         st = bhip(b, hipMemcpy(b->d_species + off[r], species[r], N, hipMemcpyHostToDevice), "hipMemcpy(lattice)");
         if (st) break;
-        build_wtab(epi[r], d.n_species, d.n_shells, kmax, smax, w.data());
+        build_wtab(epi[r], d.n_species, d.n_shells, kmax, smax, wtab_bias(d.lattice, kmax), w.data());
         st = bhip(b, hipMemcpy(b->d_wtabs + wsize * r, w.data(), sizeof(int32_t) * wsize, hipMemcpyHostToDevice),
                   "hipMemcpy(weights)");
         if (!st) st = upload_table(b, r);
@@ -261,7 +264,8 @@ smcx_status smcx_batch_run(smcx_batch* b, const int32_t* n_sweeps)
             while (active > 0 && n_sweeps[order[active - 1]] <= t) --active;
             const int n_groups = prefix_end[active - 1];
             for (int c = 0; c < 8 && le == hipSuccess; ++c)
-                le = launch_sweep_phase(b->d_lats, b->d_items_run, n_groups, t, c, b->kmax, b->smax, b->stream);
+                le = launch_sweep_phase(b->lattice, b->d_lats, b->d_items_run, n_groups, t, c, b->kmax, b->smax,
+                                        b->stream);
         }
         hipGraph_t g = nullptr;
         hipError_t ce = hipStreamEndCapture(b->stream, &g);
@@ -287,8 +291,8 @@ smcx_status smcx_batch_run_unbatched(smcx_batch* b, const int32_t* n_sweeps)
     for (int r = 0; r < b->n; ++r)
         for (int t = 0; t < n_sweeps[r]; ++t)
             for (int c = 0; c < 8; ++c) {
-                hipError_t e = launch_sweep_phase(b->d_lats, b->d_items_static + b->first_static[r], b->groups[r], t, c,
-                                                  b->kmax, b->smax, b->stream);
+                hipError_t e = launch_sweep_phase(b->lattice, b->d_lats, b->d_items_static + b->first_static[r],
+                                                  b->groups[r], t, c, b->kmax, b->smax, b->stream);
                 if (e != hipSuccess) return bhip(b, e, "sweep_phase launch");
             }
     finish_run(b, n_sweeps);

@@ -42,7 +42,7 @@ smcx_status fail(smcx_ctx* c, smcx_status st, const char* fmt, ...);
 smcx_status validate_desc(const smcx_desc* d, int32_t block_out[3], bool for_gpu);
 smcx_status validate_epi(const int32_t* epi, int K, int S);
 smcx_status validate_T(double T);
-size_t n_sites(const int32_t L[3]);
+size_t n_sites(int lattice, const int32_t L[3]);
 smcx_status ctx_hip(smcx_ctx* c, hipError_t e, const char* what);
 void fill_geometry(DevLattice& L, const smcx_desc* d, const int32_t B[3]);
 bool geometry_ok(const DevLattice& L);

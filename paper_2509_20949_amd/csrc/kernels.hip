@@ -11,7 +11,7 @@
 //   program order, so no barrier separates the rounds.
 // pair_counts: N_m[p'][p] for energy recomputation and Warren-Cowley SRO
 //   (Eq. (SRO)).
-#include "smcx_internal.h"
+#include "device_common.h"
 
 namespace smcx {
 
@@ -26,18 +26,6 @@ __device__ __forceinline__ uint32_t encode2(uint32_t two_species, int F)
 {
     // two species bytes (v0 | v1 << 8) -> ((F+32) v0) | ((F+32) v1) << 8
     return (two_species << 5) + two_species * (uint32_t)F;
-}
-
-__device__ __forceinline__ uint32_t decode(uint32_t code) { return code >> 5; }
-
-// acc + a * b on the 24-bit multiplier (a, b signed 24-bit), modulo 2^32:
-// one v_mad_i32_i24 (the compiler otherwise splits it into a multiply and a
-// three-input add)
-__device__ __forceinline__ uint32_t mad24(uint32_t a, int32_t b, uint32_t acc)
-{
-    uint32_t r;
-    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(acc));
-    return r;
 }
 
 // LDS layout of one block (see smcx_internal.h): corner array at offset 0,
@@ -150,12 +138,6 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u_dir, uint
         dEsum += dE;
         nacc += 1u;
     }
-}
-
-__device__ __forceinline__ int wrap_add(int v, int L)   // v in [-L, 2L)
-{
-    v = v < 0 ? v + L : v;
-    return v >= L ? v - L : v;
 }
 
 // ---------------------------------------------------------------------------
@@ -411,10 +393,11 @@ static hipError_t launch_k(const DevLattice* d_lat, const WorkItem* d_items, int
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_sweep_phase(const DevLattice* d_lat, const WorkItem* d_items, int n_groups, int t,
+hipError_t launch_sweep_phase(int lattice, const DevLattice* d_lat, const WorkItem* d_items, int n_groups, int t,
                               int colour, int kmax, int smax, hipStream_t stream)
 {
     if (n_groups <= 0) return hipSuccess;
+    if (lattice == 1) return launch_sweep_phase_fcc(d_lat, d_items, n_groups, t, colour, smax, stream);
     switch (kmax) {
     case 2: return launch_k<2>(d_lat, d_items, n_groups, t, colour, smax, stream);
     case 3: return launch_k<3>(d_lat, d_items, n_groups, t, colour, smax, stream);
@@ -483,9 +466,10 @@ void pair_counts_kernel(const uint8_t* __restrict__ g, int Lx, int Ly, int Lz, i
         if (c[k]) atomicAdd(&counts[k], (unsigned long long)c[k]);
 }
 
-hipError_t launch_pair_counts(const uint8_t* species, const int32_t L[3], int K, int S,
+hipError_t launch_pair_counts(int lattice, const uint8_t* species, const int32_t L[3], int K, int S,
                               unsigned long long* d_counts, hipStream_t stream)
 {
+    if (lattice == 1) return launch_pair_counts_fcc(species, L, K, S, d_counts, stream);
     const size_t ncell = (size_t)L[0] * L[1] * L[2];
     size_t groups = (ncell + 255) / 256;
     if (groups > 8192) groups = 8192;

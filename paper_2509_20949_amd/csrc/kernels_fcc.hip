@@ -1,0 +1,406 @@
+// kernels_fcc.hip -- the sweep and pair-count kernels on the FCC lattice
+// (the lattice of the paper's quinary alloy and its L1_2 precipitates).
+//
+// Four sublattices per cubic cell at doubled offsets SUB[b]; 12/6/24
+// neighbours in shells 1/2/3.  One wavefront per block as on BCC; the LDS
+// image holds one 15^3 byte array per sublattice, array b covering local
+// cells -1-SUB[b][a] .. 13-SUB[b][a] along axis a, so every neighbour offset
+// is a compile-time constant for a given (sublattice, displacement).  A
+// round is one (residue class, sublattice) pair: 27 x 4 = 108 rounds.
+//
+// Partner choice: the partner sublattice of all trials of one (sweep,
+// colour, sub-colour) set is drawn once (the same draw on every wave), so a
+// wave's partners all live in one sublattice and the partner's neighbour
+// offsets are selected by a scalar branch; each trial then takes one of the
+// 4 first neighbours in that sublattice from two bits of its draw.
+#include "device_common.h"
+
+namespace smcx {
+namespace fcc {
+
+constexpr int SUB[4][3] = {{0, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
+constexpr int SH1[12][3] = {{+1, +1, 0}, {+1, -1, 0}, {-1, +1, 0}, {-1, -1, 0}, {+1, 0, +1}, {+1, 0, -1},
+                            {-1, 0, +1}, {-1, 0, -1}, {0, +1, +1}, {0, +1, -1}, {0, -1, +1}, {0, -1, -1}};
+constexpr int SH2[6][3] = {{+2, 0, 0}, {-2, 0, 0}, {0, +2, 0}, {0, -2, 0}, {0, 0, +2}, {0, 0, -2}};
+constexpr int SH3[24][3] = {{+2, +1, +1}, {+2, +1, -1}, {+2, -1, +1}, {+2, -1, -1}, {-2, +1, +1}, {-2, +1, -1},
+                            {-2, -1, +1}, {-2, -1, -1}, {+1, +2, +1}, {+1, +2, -1}, {-1, +2, +1}, {-1, +2, -1},
+                            {+1, -2, +1}, {+1, -2, -1}, {-1, -2, +1}, {-1, -2, -1}, {+1, +1, +2}, {+1, -1, +2},
+                            {-1, +1, +2}, {-1, -1, +2}, {+1, +1, -2}, {+1, -1, -2}, {-1, +1, -2}, {-1, -1, -2}};
+constexpr int kArrays = 4;
+constexpr int kBpOff = kArrays * kArr;      // per-wave partner-sublattice table (108 bytes)
+constexpr int kWaveLdsF = kBpOff + 112;
+
+constexpr int origin(int b, int a) { return 1 + SUB[b][a]; }
+constexpr int stride(int a) { return a == 0 ? 1 : (a == 1 ? kP : kPP); }
+constexpr int sub_of_parity(int px, int py, int pz)
+{
+    return (px == 0 && py == 0 && pz == 0) ? 0 : (px && py && !pz) ? 1 : (px && !py && pz) ? 2 : 3;
+}
+constexpr int fdiv2(int t) { return t >= 0 ? t / 2 : -((-t + 1) / 2); }
+constexpr int mod2(int t) { return t & 1; }
+
+// LDS offset from the site (b, cell) to the site at doubled displacement d.
+constexpr int offset(int b, int dx, int dy, int dz)
+{
+    const int d[3] = {dx, dy, dz};
+    int par[3] = {0, 0, 0}, cd[3] = {0, 0, 0};
+    for (int a = 0; a < 3; ++a) {
+        const int t = SUB[b][a] + d[a];
+        par[a] = mod2(t);
+        cd[a] = fdiv2(t);
+    }
+    const int bp = sub_of_parity(par[0], par[1], par[2]);
+    int off = (bp - b) * kArr;
+    for (int a = 0; a < 3; ++a) off += (cd[a] + origin(bp, a) - origin(b, a)) * stride(a);
+    return off;
+}
+
+struct Offsets {
+    int s1[12], s2[6], s3[24];
+};
+
+constexpr Offsets make_offsets(int b)
+{
+    Offsets o{};
+    for (int k = 0; k < 12; ++k) o.s1[k] = offset(b, SH1[k][0], SH1[k][1], SH1[k][2]);
+    for (int k = 0; k < 6; ++k) o.s2[k] = offset(b, SH2[k][0], SH2[k][1], SH2[k][2]);
+    for (int k = 0; k < 24; ++k) o.s3[k] = offset(b, SH3[k][0], SH3[k][1], SH3[k][2]);
+    return o;
+}
+
+template <int B> struct Off { static constexpr Offsets v = make_offsets(B); };
+
+// The two axes on which sublattices B and BP differ.
+constexpr int axis1(int B, int BP) { return SUB[B][0] != SUB[BP][0] ? 0 : 1; }
+constexpr int axis2(int B, int BP) { return SUB[B][2] != SUB[BP][2] ? 2 : 1; }
+
+template <int SMAX, int B>
+__device__ __forceinline__ void histogram(const uint8_t* lat, int a, uint32_t (&h)[kMaxS])
+{
+    constexpr Offsets O = Off<B>::v;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) h[0] += 1u << (lat[a + O.s1[k]] & 31u);
+    if constexpr (SMAX >= 2) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) h[1] += 1u << (lat[a + O.s2[k]] & 31u);
+    }
+    if constexpr (SMAX >= 3) {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) h[2] += 1u << (lat[a + O.s3[k]] & 31u);
+    }
+}
+
+// Species fields: 6 bits each (up to 24 neighbours per shell), 5 species,
+// biased by 32 so that 32 + n_i - n_j never borrows.
+constexpr int F = 6;
+constexpr int KMAXF = 5;
+constexpr uint32_t kBias = 32u * (1u | 1u << 6 | 1u << 12 | 1u << 18 | 1u << 24);
+
+template <int SMAX, int B, int BP>
+__device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u_dir, uint32_t u_acc, bool valid,
+                                      const int32_t* wtab, const double* tab, int64_t& dEsum, uint32_t& nacc)
+{
+    constexpr int WR = wrow(KMAXF, SMAX);
+    constexpr int a1 = axis1(B, BP), a2 = axis2(B, BP);
+    const int bit1 = (int)((u_dir >> 30) & 1u), bit2 = (int)(u_dir >> 31);
+    const int aj = ai + (BP - B) * kArr + (SUB[BP][a1] - 1 + bit1) * stride(a1) + (SUB[BP][a2] - 1 + bit2) * stride(a2);
+    const uint32_t ci = lat[ai];
+    const uint32_t cj = lat[aj];
+    uint32_t hi[kMaxS], hj[kMaxS];
+#pragma unroll
+    for (int s = 0; s < kMaxS; ++s) { hi[s] = kBias; hj[s] = 0u; }
+    histogram<SMAX, B>(lat, ai, hi);
+    histogram<SMAX, BP>(lat, aj, hj);
+    const uint32_t a = min(decode(ci), (uint32_t)(KMAXF - 1)), b = min(decode(cj), (uint32_t)(KMAXF - 1));
+    const int32_t* w = wtab + (a * KMAXF + b) * WR;
+    uint32_t acc = (uint32_t)w[SMAX * KMAXF];
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) {
+        const uint32_t d = hi[s] - hj[s];
+#pragma unroll
+        for (int p = 0; p < KMAXF; ++p) acc = mad24((d >> (F * p)) & 63u, w[s * KMAXF + p], acc);
+    }
+    const int32_t dE = (int32_t)acc;
+    const int e = dE < 1 ? 1 : (dE > (1 << 24) - 1 ? (1 << 24) - 1 : dE);
+    const double thr = (tab[512 + (e >> 16)] * tab[256 + ((e >> 8) & 255)]) * tab[e & 255];
+    const bool up_ok = dE < (1 << 24) && (double)u_acc < thr;
+    if (valid && ci != cj && (dE <= 0 || up_ok)) {
+        lat[ai] = (uint8_t)cj;
+        lat[aj] = (uint8_t)ci;
+        dEsum += dE;
+        nacc += 1u;
+    }
+}
+
+// Partner sublattice BP (a wave-uniform value) selects one instantiation.
+template <int SMAX, int B>
+__device__ __forceinline__ void trial_any(int bp, uint8_t* lat, int ai, uint32_t u_dir, uint32_t u_acc, bool valid,
+                                          const int32_t* wtab, const double* tab, int64_t& dEsum, uint32_t& nacc)
+{
+    if constexpr (B != 0) { if (bp == 0) { trial<SMAX, B, 0>(lat, ai, u_dir, u_acc, valid, wtab, tab, dEsum, nacc); return; } }
+    if constexpr (B != 1) { if (bp == 1) { trial<SMAX, B, 1>(lat, ai, u_dir, u_acc, valid, wtab, tab, dEsum, nacc); return; } }
+    if constexpr (B != 2) { if (bp == 2) { trial<SMAX, B, 2>(lat, ai, u_dir, u_acc, valid, wtab, tab, dEsum, nacc); return; } }
+    if constexpr (B != 3) { if (bp == 3) { trial<SMAX, B, 3>(lat, ai, u_dir, u_acc, valid, wtab, tab, dEsum, nacc); return; } }
+}
+
+template <int B>
+__device__ __forceinline__ int site_addr(int lx, int ly, int lz)
+{
+    return B * kArr + (lz + origin(B, 2)) * kPP + (ly + origin(B, 1)) * kP + (lx + origin(B, 0));
+}
+
+// Site b of cell l is staged when l_a lies in -1-SUB[b][a] .. w_a+1-SUB[b][a]
+// and written back when l_a lies in -SUB[b][a] .. w_a-SUB[b][a] (the block's
+// own cells and the partners its trials can reach).
+__device__ __forceinline__ bool in_halo(int b, int lx, int ly, int lz, int wx, int wy, int wz)
+{
+    const int sx = SUB[b][0], sy = SUB[b][1], sz = SUB[b][2];
+    return lx >= -1 - sx && lx <= wx + 1 - sx && ly >= -1 - sy && ly <= wy + 1 - sy && lz >= -1 - sz &&
+           lz <= wz + 1 - sz;
+}
+
+__device__ __forceinline__ bool in_write_box(int b, int lx, int ly, int lz, int wx, int wy, int wz)
+{
+    const int sx = SUB[b][0], sy = SUB[b][1], sz = SUB[b][2];
+    return lx >= -sx && lx <= wx - sx && ly >= -sy && ly <= wy - sy && lz >= -sz && lz <= wz - sz;
+}
+
+__device__ __forceinline__ int lds_index(int b, int lx, int ly, int lz)
+{
+    return b * kArr + (lz + 1 + SUB[b][2]) * kPP + (ly + 1 + SUB[b][1]) * kP + (lx + 1 + SUB[b][0]);
+}
+
+}  // namespace fcc
+
+template <int SMAX>
+__global__ __launch_bounds__(kWave * kWavesPerGroup)
+void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem* __restrict__ items, int t,
+                            int colour)
+{
+    using namespace fcc;
+    constexpr int WR = wrow(KMAXF, SMAX);
+    __shared__ double s_tab[kTab];
+    __shared__ int32_t s_w[KMAXF * KMAXF * WR];
+    __shared__ __attribute__((aligned(16))) uint8_t s_lat[kWavesPerGroup * kWaveLdsF];
+
+    const int wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    int li = 0, f = blockIdx.x * kWavesPerGroup;
+    if (items) {
+        li = items[blockIdx.x].lattice;
+        f = items[blockIdx.x].first_block;
+    }
+    const DevLattice& D = lats[li];
+    const uint32_t s = D.sweep0 + (uint32_t)t;
+    {
+        int ti = (int)(s - D.tab_s0);
+        ti = ti < 0 ? 0 : (ti >= D.n_tabs ? D.n_tabs - 1 : ti);
+        const double* tab = D.tabs + (size_t)ti * kTab;
+        for (int k = threadIdx.x; k < kTab; k += blockDim.x) s_tab[k] = tab[k];
+        for (int k = threadIdx.x; k < KMAXF * KMAXF * WR; k += blockDim.x) s_w[k] = D.wtab[k];
+    }
+    __syncthreads();
+    f += wave;
+    if (f >= D.blocks_per_colour) return;   // no later barrier
+
+    const int hx = D.nb[0] >> 1, hy = D.nb[1] >> 1;
+    const int kx = 2 * (f % hx) + (colour & 1);
+    const int ky = 2 * ((f / hx) % hy) + ((colour >> 1) & 1);
+    const int kz = 2 * (f / (hx * hy)) + ((colour >> 2) & 1);
+    const int Lx = D.L[0], Ly = D.L[1], Lz = D.L[2];
+    uint32_t sh[4] = {0u, 0u, s, 8u};
+    philox4x32_10(sh, D.key[0], D.key[1]);
+    const int ox = (int)(((uint64_t)sh[0] * (uint32_t)Lx) >> 32);
+    const int oy = (int)(((uint64_t)sh[1] * (uint32_t)Ly) >> 32);
+    const int oz = (int)(((uint64_t)sh[2] * (uint32_t)Lz) >> 32);
+    const int x0 = (int)(((int64_t)kx * Lx) / D.nb[0]);
+    const int y0 = (int)(((int64_t)ky * Ly) / D.nb[1]);
+    const int z0 = (int)(((int64_t)kz * Lz) / D.nb[2]);
+    const int wx = (int)(((int64_t)(kx + 1) * Lx) / D.nb[0]) - x0;
+    const int wy = (int)(((int64_t)(ky + 1) * Ly) / D.nb[1]) - y0;
+    const int wz = (int)(((int64_t)(kz + 1) * Lz) / D.nb[2]) - z0;
+    const int gx0 = wrap_add(x0 + ox, Lx), gy0 = wrap_add(y0 + oy, Ly), gz0 = wrap_add(z0 + oz, Lz);
+    const uint32_t k0 = D.key[0], k1 = D.key[1];
+
+    uint8_t* lat = s_lat + wave * kWaveLdsF;
+    uint8_t* __restrict__ g = D.species;
+
+    // partner sublattice of every (colour, sub-colour) set of this sweep:
+    // k = (t0 * 3) >> 32 for t0 = word 0 of Philox(key, (q, 0, s, c + 64)),
+    // the k-th sublattice other than the set's own
+    for (int q = lane; q < 108; q += kWave) {
+        uint32_t r[4] = {(uint32_t)q, 0u, s, (uint32_t)colour + 64u};
+        philox4x32_10(r, k0, k1);
+        const int b = q & 3, k = (int)(((uint64_t)r[0] * 3u) >> 32);
+        lat[kBpOff + q] = (uint8_t)(k + (k >= b ? 1 : 0));
+    }
+
+    // ---- stage block + halo: one cell (4 sublattice bytes, one dword) per lane ----
+    {
+        const int lx = (lane & 15) - 2;
+        const bool okx = lx <= wx + 1;
+        const int gx = wrap_add(gx0 + lx, Lx);
+        for (int r = lane >> 4; r < 256; r += 4) {
+            const int ly = (r & 15) - 2, lz = (r >> 4) - 2;
+            if (!okx || ly > wy + 1 || lz > wz + 1) continue;
+            const int gy = wrap_add(gy0 + ly, Ly), gz = wrap_add(gz0 + lz, Lz);
+            const size_t cell = ((size_t)gz * Ly + gy) * Lx + gx;
+            uint32_t v = *(const uint32_t*)(g + 4 * cell);
+            v = (v << 5) + (v << 2) + (v << 1);     // (6 + 32) * species, per byte
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (in_halo(b, lx, ly, lz, wx, wy, wz)) lat[lds_index(b, lx, ly, lz)] = (uint8_t)(v >> (8 * b));
+        }
+    }
+
+    // ---- 27 residue classes x 4 sublattices = 108 rounds ----
+    const int ix = lane & 3, iy = (lane >> 2) & 3, iz = lane >> 4;
+    const uint32_t bx = (uint32_t)(gx0 + 3 * ix), by = (uint32_t)(gy0 + 3 * iy), bz = (uint32_t)(gz0 + 3 * iz);
+    const uint32_t LxLy = (uint32_t)Lx * (uint32_t)Ly;
+    const bool narrow = LxLy < (1u << 24) && (uint64_t)LxLy * (uint32_t)Lz < (1ull << 32);
+    int64_t dEsum = 0;
+    uint32_t nacc = 0;
+    for (int m = 0; m < 27; ++m) {
+        const int rx = m % 3, ry = (m / 3) % 3, rz = m / 9;
+        const int lx = rx + 3 * ix, ly = ry + 3 * iy, lz = rz + 3 * iz;
+        const bool valid = lx < wx && ly < wy && lz < wz;
+        uint32_t gx = bx + rx, gy = by + ry, gz = bz + rz;
+        gx = min(gx, gx - (uint32_t)Lx);
+        gy = min(gy, gy - (uint32_t)Ly);
+        gz = min(gz, gz - (uint32_t)Lz);
+        uint64_t cell;
+        if (narrow)
+            cell = __umul24(gz, LxLy) + __umul24(gy, (uint32_t)Lx) + gx;
+        else
+            cell = ((uint64_t)gz * (uint32_t)Ly + gy) * (uint32_t)Lx + gx;
+        uint32_t ra[4] = {(uint32_t)cell, (uint32_t)(cell >> 32), s, (uint32_t)colour};
+        uint32_t rb[4] = {(uint32_t)cell, (uint32_t)(cell >> 32), s, (uint32_t)colour + 16u};
+        philox4x32_10(ra, k0, k1);
+        philox4x32_10(rb, k0, k1);
+        const int q0 = 4 * m;
+        int bp = __builtin_amdgcn_readfirstlane(lat[kBpOff + q0]);
+        trial_any<SMAX, 0>(bp, lat, site_addr<0>(lx, ly, lz), ra[0], ra[1], valid, s_w, s_tab, dEsum, nacc);
+        __builtin_amdgcn_wave_barrier();
+        bp = __builtin_amdgcn_readfirstlane(lat[kBpOff + q0 + 1]);
+        trial_any<SMAX, 1>(bp, lat, site_addr<1>(lx, ly, lz), ra[2], ra[3], valid, s_w, s_tab, dEsum, nacc);
+        __builtin_amdgcn_wave_barrier();
+        bp = __builtin_amdgcn_readfirstlane(lat[kBpOff + q0 + 2]);
+        trial_any<SMAX, 2>(bp, lat, site_addr<2>(lx, ly, lz), rb[0], rb[1], valid, s_w, s_tab, dEsum, nacc);
+        __builtin_amdgcn_wave_barrier();
+        bp = __builtin_amdgcn_readfirstlane(lat[kBpOff + q0 + 3]);
+        trial_any<SMAX, 3>(bp, lat, site_addr<3>(lx, ly, lz), rb[2], rb[3], valid, s_w, s_tab, dEsum, nacc);
+        __builtin_amdgcn_wave_barrier();
+    }
+
+    // ---- write back: sublattice b over cells -SUB[b][a] .. w_a - SUB[b][a] ----
+    {
+        const int lx = (lane & 15) - 1;
+        const bool okx = lx <= wx;
+        const int gx = wrap_add(gx0 + lx, Lx);
+        for (int r = lane >> 4; r < 256; r += 4) {
+            const int ly = (r & 15) - 1, lz = (r >> 4) - 1;
+            if (!okx || ly > wy || lz > wz) continue;
+            bool v[4];
+            uint32_t e = 0u;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                v[b] = in_write_box(b, lx, ly, lz, wx, wy, wz);
+                if (v[b]) e |= decode(lat[lds_index(b, lx, ly, lz)]) << (8 * b);
+            }
+            if (!(v[0] || v[1] || v[2] || v[3])) continue;
+            const int gy = wrap_add(gy0 + ly, Ly), gz = wrap_add(gz0 + lz, Lz);
+            uint8_t* q = g + 4 * (((size_t)gz * Ly + gy) * Lx + gx);
+            if (v[0] && v[1] && v[2] && v[3]) {
+                *(uint32_t*)q = e;
+            } else {
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if (v[b]) q[b] = (uint8_t)(e >> (8 * b));
+            }
+        }
+    }
+
+    uint64_t sum = (uint64_t)dEsum;
+    uint32_t cnt = nacc;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)sum, o, kWave);
+        const uint32_t hi = __shfl_xor((uint32_t)(sum >> 32), o, kWave);
+        sum += (uint64_t)lo | ((uint64_t)hi << 32);
+        cnt += __shfl_xor(cnt, o, kWave);
+    }
+    if (lane == 0) {
+        if (sum) atomicAdd((unsigned long long*)D.energy, (unsigned long long)sum);
+        if (cnt) atomicAdd(D.accepted, (unsigned long long)cnt);
+    }
+}
+
+hipError_t launch_sweep_phase_fcc(const DevLattice* d_lat, const WorkItem* d_items, int n_groups, int t, int colour,
+                                  int smax, hipStream_t stream)
+{
+    if (n_groups <= 0) return hipSuccess;
+    const dim3 grid(n_groups), block(kWave * kWavesPerGroup);
+    switch (smax) {
+    case 1: hipLaunchKernelGGL(sweep_phase_fcc_kernel<1>, grid, block, 0, stream, d_lat, d_items, t, colour); break;
+    case 2: hipLaunchKernelGGL(sweep_phase_fcc_kernel<2>, grid, block, 0, stream, d_lat, d_items, t, colour); break;
+    case 3: hipLaunchKernelGGL(sweep_phase_fcc_kernel<3>, grid, block, 0, stream, d_lat, d_items, t, colour); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FCC pair counts: one thread per cell (4 sites), neighbours read through the
+// caches, 5-bit species fields (up to 24 neighbours per shell).
+__global__ __launch_bounds__(256)
+void pair_counts_fcc_kernel(const uint8_t* __restrict__ g, int Lx, int Ly, int Lz, int K, int S,
+                            unsigned long long* __restrict__ counts)
+{
+    using namespace fcc;
+    __shared__ unsigned int c[kMaxS * kMaxK * kMaxK];
+    for (int k = threadIdx.x; k < kMaxS * kMaxK * kMaxK; k += blockDim.x) c[k] = 0u;
+    __syncthreads();
+    const size_t ncell = (size_t)Lx * Ly * Lz;
+    for (size_t cell = (size_t)blockIdx.x * blockDim.x + threadIdx.x; cell < ncell;
+         cell += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(cell % Lx), y = (int)((cell / Lx) % Ly), z = (int)(cell / ((size_t)Lx * Ly));
+        auto at = [&](int X, int Y, int Z) -> uint32_t {   // doubled coordinates
+            X = X < 0 ? X + 2 * Lx : (X >= 2 * Lx ? X - 2 * Lx : X);
+            Y = Y < 0 ? Y + 2 * Ly : (Y >= 2 * Ly ? Y - 2 * Ly : Y);
+            Z = Z < 0 ? Z + 2 * Lz : (Z >= 2 * Lz ? Z - 2 * Lz : Z);
+            const int b = sub_of_parity(X & 1, Y & 1, Z & 1);
+            return g[4 * (((size_t)(Z >> 1) * Ly + (Y >> 1)) * Lx + (X >> 1)) + b];
+        };
+        for (int b = 0; b < 4; ++b) {
+            const int X = 2 * x + SUB[b][0], Y = 2 * y + SUB[b][1], Z = 2 * z + SUB[b][2];
+            const uint32_t si = g[4 * cell + b];
+            uint32_t h[3] = {0u, 0u, 0u};
+            for (int k = 0; k < 12; ++k) h[0] += 1u << (5 * at(X + SH1[k][0], Y + SH1[k][1], Z + SH1[k][2]));
+            if (S >= 2)
+                for (int k = 0; k < 6; ++k) h[1] += 1u << (5 * at(X + SH2[k][0], Y + SH2[k][1], Z + SH2[k][2]));
+            if (S >= 3)
+                for (int k = 0; k < 24; ++k) h[2] += 1u << (5 * at(X + SH3[k][0], Y + SH3[k][1], Z + SH3[k][2]));
+            for (int m = 0; m < S; ++m)
+                for (int p = 0; p < K; ++p) {
+                    const uint32_t n = (h[m] >> (5 * p)) & 31u;
+                    if (n) atomicAdd(&c[(m * kMaxK + si) * kMaxK + p], n);
+                }
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kMaxS * kMaxK * kMaxK; k += blockDim.x)
+        if (c[k]) atomicAdd(&counts[k], (unsigned long long)c[k]);
+}
+
+hipError_t launch_pair_counts_fcc(const uint8_t* species, const int32_t L[3], int K, int S,
+                                  unsigned long long* d_counts, hipStream_t stream)
+{
+    const size_t ncell = (size_t)L[0] * L[1] * L[2];
+    size_t groups = (ncell + 255) / 256;
+    if (groups > 8192) groups = 8192;
+    hipLaunchKernelGGL(pair_counts_fcc_kernel, dim3((unsigned)groups), dim3(256), 0, stream, species, L[0], L[1], L[2],
+                       K, S, d_counts);
+    return hipGetLastError();
+}
+
+}  // namespace smcx

@@ -53,8 +53,8 @@ struct Request {
 
 size_t footprint_of(const smcx_desc* d)
 {
-    const int kmax = kmax_for(d->n_species), smax = d->n_shells;
-    return align256(n_sites(d->L)) + align256(sizeof(double) * kTab) +
+    const int kmax = kmax_for(d->lattice, d->n_species), smax = d->n_shells;
+    return align256(n_sites(d->lattice, d->L)) + align256(sizeof(double) * kTab) +
            align256(sizeof(int32_t) * (size_t)kmax * kmax * wrow(kmax, smax));
 }
 
@@ -108,8 +108,8 @@ smcx_status initial_energy(smcx_server* s, Request* q, int64_t* E)
 {
     smcx_status st = shipc(s, hipMemsetAsync(s->d_counts, 0, sizeof(unsigned long long) * kMaxS * kMaxK * kMaxK, s->stream),
                            "hipMemsetAsync");
-    if (!st) st = shipc(s, launch_pair_counts(q->lat.species, q->lat.L, q->desc.n_species, q->desc.n_shells, s->d_counts,
-                                              s->stream), "pair_counts launch");
+    if (!st) st = shipc(s, launch_pair_counts(q->desc.lattice, q->lat.species, q->lat.L, q->desc.n_species,
+                                              q->desc.n_shells, s->d_counts, s->stream), "pair_counts launch");
     unsigned long long h[kMaxS * kMaxK * kMaxK];
     if (!st) st = shipc(s, hipMemcpyAsync(h, s->d_counts, sizeof(h), hipMemcpyDeviceToHost, s->stream), "hipMemcpyAsync");
     if (!st) st = shipc(s, hipStreamSynchronize(s->stream), "hipStreamSynchronize");
@@ -126,7 +126,7 @@ smcx_status initial_energy(smcx_server* s, Request* q, int64_t* E)
 smcx_status admit(smcx_server* s, Request* q)
 {
     if (q->id == s->fault_id) return sfail(s, SMCX_E_NOMEM, "admission failure forced by SMCX_FAULT_REQUEST");
-    const size_t N = n_sites(q->desc.L);
+    const size_t N = n_sites(q->desc.lattice, q->desc.L);
     const size_t off_tab = align256(N);
     const size_t off_w = off_tab + align256(sizeof(double) * kTab);
     smcx_status st = shipc(s, hipMalloc(&q->d_mem, q->footprint), "hipMalloc(request)");
@@ -138,7 +138,8 @@ smcx_status admit(smcx_server* s, Request* q)
     double tab[kTab];
     build_thresholds(q->T, tab);
     std::vector<int32_t> w((size_t)q->kmax * q->kmax * wrow(q->kmax, q->smax));
-    build_wtab(q->epi.data(), q->desc.n_species, q->desc.n_shells, q->kmax, q->smax, w.data());
+    build_wtab(q->epi.data(), q->desc.n_species, q->desc.n_shells, q->kmax, q->smax,
+               wtab_bias(q->desc.lattice, q->kmax), w.data());
     st = shipc(s, hipMemcpy(q->d_mem, q->species.data(), N, hipMemcpyHostToDevice), "hipMemcpy(lattice)");
     if (!st) st = shipc(s, hipMemcpy(q->d_mem + off_tab, tab, sizeof(tab), hipMemcpyHostToDevice), "hipMemcpy(table)");
     if (!st) st = shipc(s, hipMemcpy(q->d_mem + off_w, w.data(), sizeof(int32_t) * w.size(), hipMemcpyHostToDevice),
@@ -211,7 +212,7 @@ smcx_status smcx_server_submit(smcx_server* s, const smcx_desc* desc, const uint
     if (!st) st = validate_T(T);
     if (st) return sfail(s, st, smcx_global_error());
     if (!species || n_sweeps < 0) return sfail(s, SMCX_E_INVALID, "species NULL or negative sweep count");
-    const size_t N = n_sites(desc->L);
+    const size_t N = n_sites(desc->lattice, desc->L);
     for (size_t i = 0; i < N; ++i)
         if (species[i] >= desc->n_species) return sfail(s, SMCX_E_INVALID, "species value >= K");
     Request* q = new (std::nothrow) Request();
@@ -223,7 +224,7 @@ smcx_status smcx_server_submit(smcx_server* s, const smcx_desc* desc, const uint
     q->epi.assign(epi, epi + (size_t)desc->n_shells * desc->n_species * desc->n_species);
     q->T = T;
     q->n_sweeps = n_sweeps;
-    q->kmax = kmax_for(desc->n_species);
+    q->kmax = kmax_for(desc->lattice, desc->n_species);
     q->smax = desc->n_shells;
     q->footprint = footprint_of(desc);
     if (q->footprint > s->budget) {
@@ -274,16 +275,18 @@ smcx_status smcx_server_step(smcx_server* s, int32_t* n_resident, int32_t* n_wai
         if (st) return st;
         auto steps_of = [&](Request* q) { return std::min(s->sweeps_per_step, q->n_sweeps - q->done); };
         std::stable_sort(run.begin(), run.end(), [&](Request* x, Request* y) {
+            if (x->desc.lattice != y->desc.lattice) return x->desc.lattice < y->desc.lattice;
             if (x->kmax != y->kmax) return x->kmax < y->kmax;
             if (x->smax != y->smax) return x->smax < y->smax;
             return steps_of(x) > steps_of(y);
         });
         std::vector<WorkItem> items;
-        struct Group { int kmax, smax; size_t begin; std::vector<std::pair<int, size_t>> ends; };
+        struct Group { int lattice, kmax, smax; size_t begin; std::vector<std::pair<int, size_t>> ends; };
         std::vector<Group> groups;
         for (Request* q : run) {
-            if (groups.empty() || groups.back().kmax != q->kmax || groups.back().smax != q->smax)
-                groups.push_back(Group{q->kmax, q->smax, items.size(), {}});
+            if (groups.empty() || groups.back().lattice != q->desc.lattice || groups.back().kmax != q->kmax ||
+                groups.back().smax != q->smax)
+                groups.push_back(Group{q->desc.lattice, q->kmax, q->smax, items.size(), {}});
             for (int g = 0; g < q->groups; ++g) items.push_back(WorkItem{q->slot, g * kWavesPerGroup});
             groups.back().ends.push_back({steps_of(q), items.size()});
         }
@@ -306,8 +309,8 @@ smcx_status smcx_server_step(smcx_server* s, int32_t* n_resident, int32_t* n_wai
                 for (const auto& e : G.ends)
                     if (e.first > t) end = e.second;
                 for (int c = 0; c < 8; ++c) {
-                    hipError_t e = launch_sweep_phase(s->d_lats, s->d_items + G.begin, (int)(end - G.begin), t, c,
-                                                      G.kmax, G.smax, s->stream);
+                    hipError_t e = launch_sweep_phase(G.lattice, s->d_lats, s->d_items + G.begin, (int)(end - G.begin),
+                                                      t, c, G.kmax, G.smax, s->stream);
                     if (e != hipSuccess) return shipc(s, e, "sweep_phase launch");
                 }
             }
@@ -320,7 +323,7 @@ smcx_status smcx_server_step(smcx_server* s, int32_t* n_resident, int32_t* n_wai
     for (auto it = s->resident.begin(); it != s->resident.end();) {
         Request* q = s->reqs[*it];
         if (q->done < q->n_sweeps) { ++it; continue; }
-        const size_t N = n_sites(q->desc.L);
+        const size_t N = n_sites(q->desc.lattice, q->desc.L);
         q->config.resize(N);
         int64_t st2[2];
         smcx_status st = shipc(s, hipMemcpy(q->config.data(), q->lat.species, N, hipMemcpyDeviceToHost), "hipMemcpy");

@@ -46,7 +46,7 @@ struct DevLattice {
     int32_t n_tabs;          // later sweeps reuse the last table
     int32_t K;
     int32_t blocks_per_colour;
-    int32_t pad;
+    int32_t lattice;         // 0 BCC, 1 FCC
 };
 
 // One workgroup's share of a batched phase: kWavesPerGroup consecutive
@@ -100,19 +100,34 @@ __host__ __device__ inline int axis_blocks(int L, int B)
 
 // Host helpers (tables.cpp).
 void build_thresholds(double T, double* out768);
-void build_wtab(const int32_t* epi, int K, int S, int kmax, int smax, int32_t* out);
+// bias: the per-field offset the kernel packs into its histogram words
+// (16 for BCC with K <= 6, 0 for BCC with K <= 8, 32 for FCC).
+void build_wtab(const int32_t* epi, int K, int S, int kmax, int smax, int bias, int32_t* out);
 
 // Launchers (kernels.hip).  Return hipSuccess or the launch error.
-hipError_t launch_sweep_phase(const DevLattice* d_lat, const WorkItem* d_items, int n_groups,
+hipError_t launch_sweep_phase(int lattice, const DevLattice* d_lat, const WorkItem* d_items, int n_groups,
                               int t, int colour, int kmax, int smax, hipStream_t stream);
-hipError_t launch_pair_counts(const uint8_t* species, const int32_t L[3], int K, int S,
+hipError_t launch_pair_counts(int lattice, const uint8_t* species, const int32_t L[3], int K, int S,
                               unsigned long long* d_counts, hipStream_t stream);
+hipError_t launch_sweep_phase_fcc(const DevLattice* d_lat, const WorkItem* d_items, int n_groups, int t,
+                                  int colour, int smax, hipStream_t stream);
+hipError_t launch_pair_counts_fcc(const uint8_t* species, const int32_t L[3], int K, int S,
+                                  unsigned long long* d_counts, hipStream_t stream);
 hipError_t launch_species_max(const uint8_t* species, size_t n, unsigned int* d_max, hipStream_t stream);
 hipError_t launch_thresholds(const double* d_tab, const int32_t* d_dE, int n, double* d_out, hipStream_t stream);
 hipError_t launch_philox(const uint32_t* d_ctr, uint32_t k0, uint32_t k1, int n, uint32_t* d_out,
                          hipStream_t stream);
 
-// Kernel template keys: the smallest instantiated KMAX >= K.
+// Kernel template keys: the smallest instantiated KMAX >= K (BCC); FCC
+// kernels are built for K <= 5.
 int kmax_for(int K);
+inline int kmax_for(int lattice, int K) { return lattice == 1 ? 5 : kmax_for(K); }
+inline int wtab_bias(int lattice, int kmax) { return lattice == 1 ? 32 : (kmax <= 6 ? 16 : 0); }
+inline int sites_per_cell(int lattice) { return lattice == 1 ? 4 : 2; }
+inline int first_shell(int lattice) { return lattice == 1 ? 12 : 8; }
+inline int shell_size(int lattice, int s)
+{
+    return lattice == 1 ? (s == 0 ? 12 : s == 1 ? 6 : 24) : (s == 0 ? 8 : s == 1 ? 6 : 12);
+}
 
 }  // namespace smcx

@@ -27,13 +27,12 @@ void build_thresholds(double T, double* out)
 //   dE = sum_{s,p} (n_i[s][p] - n_j[s][p]) (V_s(b,p) - V_s(a,p))
 //        - (V_1(a,a) + V_1(b,b) - 2 V_1(a,b)),
 // the last term removing the i-j bond that both counts include.  When the
-// kernel packs 16 + n_i - n_j per field (kmax <= 6), the constant also
-// removes 16 * sum W.
-void build_wtab(const int32_t* epi, int K, int S, int kmax, int smax, int32_t* out)
+// kernel packs bias + n_i - n_j per field, the constant also removes
+// bias * sum W.
+void build_wtab(const int32_t* epi, int K, int S, int kmax, int smax, int bias, int32_t* out)
 {
     const int wr = wrow(kmax, smax);
     std::memset(out, 0, sizeof(int32_t) * (size_t)kmax * kmax * wr);
-    const bool biased = kmax <= 6;
     for (int a = 0; a < K; ++a)
         for (int b = 0; b < K; ++b) {
             int32_t* row = out + (size_t)(a * kmax + b) * wr;
@@ -46,7 +45,7 @@ void build_wtab(const int32_t* epi, int K, int S, int kmax, int smax, int32_t* o
                 }
             const int64_t corr = -((int64_t)epi[a * K + a] + epi[b * K + b] - 2 * (int64_t)epi[a * K + b]);
             // stored modulo 2^32; the kernel sums modulo 2^32 as well
-            const int64_t c = (biased ? -16 * sum : 0) + corr;
+            const int64_t c = -(int64_t)bias * sum + corr;
             row[smax * kmax] = (int32_t)(uint32_t)(uint64_t)c;
         }
 }

@@ -19,6 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsmcx.so")
 
 OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_DEVICE, E_RANGE, E_STATE = 0, -1, -2, -3, -4, -5, -6
+LATTICE_BCC, LATTICE_FCC = 0, 1
 MAX_SPECIES, MAX_SHELLS, MAX_BLOCK = 8, 3, 12
 
 
@@ -109,9 +110,9 @@ def _ptr(a, t):
     return a.ctypes.data_as(_P(t))
 
 
-def make_desc(L, K, S, block=(0, 0, 0), seed=0) -> smcx_desc:
+def make_desc(L, K, S, block=(0, 0, 0), seed=0, lattice=LATTICE_BCC) -> smcx_desc:
     d = smcx_desc()
-    d.lattice = 0
+    d.lattice = int(lattice)
     d.L[:] = [int(v) for v in L]
     d.n_species = int(K)
     d.n_shells = int(S)
@@ -342,12 +343,13 @@ def smcx_server_destroy(srv):
 class Lattice:
     """One lattice context (owns its device memory)."""
 
-    def __init__(self, L, epi, sigma, seed, T, block=(0, 0, 0)):
+    def __init__(self, L, epi, sigma, seed, T, block=(0, 0, 0), lattice=LATTICE_BCC):
         epi = np.ascontiguousarray(epi, dtype=np.int32)
         self.S, self.K = int(epi.shape[0]), int(epi.shape[1])
         self.L = tuple(int(v) for v in L)
-        self.N = 2 * self.L[0] * self.L[1] * self.L[2]
-        self.desc = make_desc(self.L, self.K, self.S, block, seed)
+        self.lattice = int(lattice)
+        self.N = (4 if lattice == LATTICE_FCC else 2) * self.L[0] * self.L[1] * self.L[2]
+        self.desc = make_desc(self.L, self.K, self.S, block, seed, lattice)
         self.ctx = smcx_create(self.desc, sigma, epi, T)
 
     def sweep(self, n=1):

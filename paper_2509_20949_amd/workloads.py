@@ -25,9 +25,12 @@ BASE_SEED = 250920949
 FECONIALTI = (0.29, 0.29, 0.28, 0.07, 0.07)
 
 
-def n_sites(L) -> int:
+BCC, FCC = 0, 1
+
+
+def n_sites(L, lattice: int = BCC) -> int:
     Lx, Ly, Lz = (int(v) for v in L)
-    return 2 * Lx * Ly * Lz
+    return (4 if lattice == FCC else 2) * Lx * Ly * Lz
 
 
 def epi_table(S: int, K: int, sigma_meV: float, rng: np.random.Generator) -> np.ndarray:
@@ -92,6 +95,7 @@ class Lattice:
     seed: int                # Philox key
     T: np.ndarray            # per-sweep temperature, length n_sweeps
     name: str = ""
+    lattice: int = BCC
 
     @property
     def S(self) -> int:
@@ -103,7 +107,7 @@ class Lattice:
 
     @property
     def N(self) -> int:
-        return n_sites(self.L)
+        return n_sites(self.L, self.lattice)
 
     @property
     def n_sweeps(self) -> int:
@@ -116,20 +120,30 @@ def _streams(k: int):
 
 
 def lattice_job(L, K: int, S: int, sigma_meV: float, T, comp: Optional[np.ndarray] = None,
-                dirichlet: Optional[float] = None, stream: int = 0, name: str = "") -> Lattice:
+                dirichlet: Optional[float] = None, stream: int = 0, name: str = "",
+                lattice: int = BCC) -> Lattice:
     """Generic seeded lattice: EPI, composition, permutation and kernel seed
     come from four independent child streams of SeedSequence(BASE_SEED+stream)."""
     r_epi, r_comp, r_perm, _r_ladder, r_seed = _streams(stream)
-    N = n_sites(L)
+    N = n_sites(L, lattice)
     epi = epi_table(S, K, sigma_meV, r_epi)
     if comp is None:
         comp = dirichlet_counts(K, N, dirichlet, r_comp) if dirichlet else equiatomic(K, N)
     sigma = configuration(comp, r_perm)
     T = np.atleast_1d(np.asarray(T, dtype=np.float64))
-    return Lattice(tuple(int(v) for v in L), epi, sigma, kernel_seed(r_seed), T, name)
+    return Lattice(tuple(int(v) for v in L), epi, sigma, kernel_seed(r_seed), T, name, lattice)
 
 
 # --- the five workload shapes ------------------------------------------------
+
+def fcc_alloy(L=(64, 64, 64), n_sweeps: int = 100, T: float = 1000.0, stream: int = 6) -> Lattice:
+    """FCC quinary with the paper's alloy composition Fe29Co29Ni28Al7Ti7
+    (fractions), shells 1-3, sigma 30 meV (the paper's production lattice
+    is FCC; its fitted EPI is not available)."""
+    N = n_sites(L, FCC)
+    return lattice_job(L, 5, 3, 30.0, np.full(n_sweeps, T), comp=counts_from_fractions(FECONIALTI, N),
+                       stream=stream, name=f"fcc{L[0]}_feconialti", lattice=FCC)
+
 
 def config1(n_sweeps: int = 100) -> Lattice:
     """8^3 cells (1,024 sites), K=4 equiatomic, shells 1-2, sigma 20 meV, 1000 K."""

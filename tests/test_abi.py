@@ -107,3 +107,22 @@ def test_schedule_block_counts_match_oracle(orc):
             n = orc.axis_blocks(L, B)
             want = max(2, min(2 * -(-L // (2 * B)), 2 * (L // 4)))
             assert n == want
+
+
+def test_fcc_validation(smcx):
+    sigma = np.zeros(4 * 512, np.uint8)
+    d = smcx.make_desc((8, 8, 8), 6, 3, (0, 0, 0), 1, smcx.LATTICE_FCC)
+    with pytest.raises(smcx.SmcxError) as e:
+        smcx.smcx_create(d, sigma, np.zeros((3, 6, 6), np.int32), 800.0)
+    assert e.value.status == smcx.E_UNSUPPORTED
+    d = smcx.make_desc((8, 8, 8), 3, 3, (0, 0, 0), 1, 7)
+    with pytest.raises(smcx.SmcxError) as e:
+        smcx.smcx_create(d, sigma, np.zeros((3, 3, 3), np.int32), 800.0)
+    assert e.value.status == smcx.E_INVALID
+    # a 4-site-per-cell species array is checked against K before any device call
+    d = smcx.make_desc((8, 8, 8), 3, 3, (0, 0, 0), 1, smcx.LATTICE_FCC)
+    bad = sigma.copy()
+    bad[-1] = 3
+    with pytest.raises(smcx.SmcxError) as e:
+        smcx.smcx_create(d, bad, np.zeros((3, 3, 3), np.int32), 800.0)
+    assert e.value.status == smcx.E_INVALID

@@ -1,0 +1,125 @@
+"""GPU parity on the FCC lattice (the paper's alloy lattice): configuration
+and energy after every sweep equal to the oracle's, bit for bit, for single
+contexts, batches and served requests."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2509_20949_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+FCC = 1
+
+
+def note(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def smcx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_20949_amd import smcx as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module", autouse=True)
+def oracle_threads(orc):
+    orc.set_threads(min(16, os.cpu_count() or 1))
+    yield
+    orc.set_threads(1)
+
+
+def run_parity(smcx, orc, job, block, n_sweeps, check_sro=False):
+    note(f"FCC {job.name} L={job.L} K={job.K} S={job.S} B={block} sweeps={n_sweeps}")
+    lat = smcx.Lattice(job.L, job.epi, job.sigma, job.seed, float(job.T[0]), block=block, lattice=FCC)
+    ref = orc.OracleState(job.L, block, job.epi, job.sigma, job.seed, lattice=FCC)
+    try:
+        if len(set(np.asarray(job.T[:n_sweeps]).tolist())) > 1:
+            lat.set_schedule(job.T[:n_sweeps])
+        assert lat.energy() == int(ref.E[0])
+        for t in range(n_sweeps):
+            lat.sweep(1)
+            ref.sweep(job.T[t], 1)
+            got = lat.config()
+            if not np.array_equal(got, ref.sigma):
+                bad = np.nonzero(got != ref.sigma)[0]
+                raise AssertionError(f"config differs after sweep {t + 1}: {bad.size} sites, first {bad[:8]}")
+            assert lat.energy() == int(ref.E[0]), f"energy differs after sweep {t + 1}"
+        if check_sro:
+            alpha, counts = lat.sro()
+            a_ref, c_ref = orc.sro(job.L, job.S, job.K, ref.sigma, FCC)
+            assert np.array_equal(counts, c_ref)
+            assert np.allclose(alpha, a_ref, rtol=0, atol=1e-12, equal_nan=True)
+        st = lat.stats()
+        assert st["accepted"] == int(ref.accepted[0]) and st["accepted"] > 0
+        assert lat.energy_recompute() == int(ref.E[0])
+    finally:
+        lat.close()
+
+
+@pytest.mark.parametrize("L,K,S,block", [((8, 8, 8), 5, 3, (12, 12, 12)), ((12, 12, 12), 5, 3, (12, 12, 12)),
+                                         ((13, 9, 22), 3, 2, (5, 4, 12)), ((4, 4, 4), 2, 1, (2, 2, 2)),
+                                         ((26, 25, 27), 5, 3, (12, 12, 12)), ((10, 11, 9), 4, 3, (3, 4, 5)),
+                                         ((7, 6, 5), 1, 3, (3, 3, 2))])
+def test_fcc_parity_every_sweep(smcx, orc, L, K, S, block):
+    job = W.lattice_job(L, K, S, 30.0, np.full(8, 900.0), stream=200 + K, name=f"K{K}S{S}", lattice=FCC)
+    if K == 1:
+        note("FCC single species")
+        lat = smcx.Lattice(job.L, job.epi, job.sigma, job.seed, 900.0, block=block, lattice=FCC)
+        try:
+            E0 = lat.energy()
+            lat.sweep(3)
+            assert lat.energy() == E0 and np.array_equal(lat.config(), job.sigma)
+        finally:
+            lat.close()
+        return
+    run_parity(smcx, orc, job, block, 8)
+
+
+def test_fcc_alloy_composition_anneal_and_sro(smcx, orc):
+    """FCC quinary at the paper's Fe29Co29Ni28Al7Ti7 composition, annealed
+    1600 K -> 900 K, SRO compared after the run."""
+    job = W.fcc_alloy((16, 16, 16), n_sweeps=12)
+    job.T = W.linear_anneal(1600.0, 900.0, 12)
+    run_parity(smcx, orc, job, (12, 12, 12), 12, check_sro=True)
+
+
+def test_fcc_batch_and_server_equal_oracle(smcx, orc):
+    jobs = [W.lattice_job(L, 5, 3, 30.0, np.full(1, T), stream=210 + k, name=f"fb{k}", lattice=FCC)
+            for k, (L, T) in enumerate([((8, 8, 8), 700.0), ((14, 12, 10), 1200.0), ((20, 20, 20), 900.0)])]
+    note("FCC batch")
+    descs = [smcx.make_desc(j.L, j.K, j.S, (0, 0, 0), j.seed, FCC) for j in jobs]
+    b = smcx.smcx_batch_create(descs, [j.sigma for j in jobs], [j.epi for j in jobs], [float(j.T[0]) for j in jobs])
+    counts = [4, 2, 3]
+    try:
+        smcx.smcx_batch_run(b, counts)
+        smcx.smcx_batch_synchronize(b)
+        for r, j in enumerate(jobs):
+            ref = orc.OracleState(j.L, (12, 12, 12), j.epi, j.sigma, j.seed, lattice=FCC)
+            ref.sweep(float(j.T[0]), counts[r])
+            v = smcx.smcx_batch_ctx(b, r)
+            assert np.array_equal(smcx.smcx_get_config(v, j.N), ref.sigma)
+            assert smcx.smcx_energy(v) == int(ref.E[0])
+    finally:
+        smcx.smcx_batch_destroy(b)
+    note("FCC server")
+    srv = smcx.smcx_server_create(1 << 30, 4, 2)
+    try:
+        ids = [smcx.smcx_server_submit(srv, d, j.sigma, j.epi, float(j.T[0]), n)
+               for d, j, n in zip(descs, jobs, counts)]
+        for _ in range(10):
+            smcx.smcx_server_step(srv)
+        for rid, j, n in zip(ids, jobs, counts):
+            assert smcx.smcx_server_poll(srv, rid) == 2
+            E, acc, cfg = smcx.smcx_server_result(srv, rid, j.N)
+            ref = orc.OracleState(j.L, (12, 12, 12), j.epi, j.sigma, j.seed, lattice=FCC)
+            ref.sweep(float(j.T[0]), n)
+            assert np.array_equal(cfg, ref.sigma) and E == int(ref.E[0])
+    finally:
+        smcx.smcx_server_destroy(srv)
