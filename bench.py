@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--L", type=int, default=512, help="cells per axis (512 = the benchmark workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0 = all host cores)")
+    ap.add_argument("--no-slab", action="store_true",
+                    help="skip the 512x512x64 leg (one GPU's share of an 8-way z-slab split)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-replica batched leg")
     ap.add_argument("--batched-sweeps", type=int, default=500)
     ap.add_argument("--unbatched-sweeps", type=int, default=20,
@@ -85,6 +87,29 @@ def copy_calibration():
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}), flush=True)
+
+
+def slab_leg(args, smcx, W, sweeps=50):
+    """One GPU's share of the 512^3 lattice split into 8 z-slabs: a
+    512 x 512 x 64 lattice (periodic here; the slab form would take its
+    halo planes from the neighbouring GPUs)."""
+    import torch
+    job = W.lattice_job((512, 512, 64), 5, 3, 30.0, np.full(1, 800.0), dirichlet=5.0, stream=3,
+                        name="slab512x512x64")
+    lat = smcx.Lattice(job.L, job.epi, job.sigma, job.seed, 800.0)
+    try:
+        lat.sweep(2)
+        smcx.smcx_synchronize(lat.ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.sweep(sweeps)
+        smcx.smcx_synchronize(lat.ctx)
+        dt = time.perf_counter() - t0
+        ok = lat.energy() == lat.energy_recompute()
+    finally:
+        lat.close()
+    return {"L": list(job.L), "sites": job.N, "sweeps": sweeps, "value": job.N * sweeps / dt,
+            "unit": "swaps/s", "energy_check_ok": ok}
 
 
 def batched_leg(args, smcx, W):
@@ -285,6 +310,9 @@ def main():
         "context": {"paper_h800_atom_steps_per_s": 3.5e9, "paper_lattice": "FCC HEA, size not stated",
                     "input_generation_s": t_gen},
     }
+    if not args.no_slab:
+        progress("slab leg: 512 x 512 x 64")
+        out["slab_share"] = slab_leg(args, smcx, W)
     if not args.no_batched:
         progress("batched leg: 256 replicas")
         out["batched"] = batched_leg(args, smcx, W)

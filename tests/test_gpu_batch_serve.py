@@ -249,7 +249,8 @@ def test_server_forced_admission_failure_isolated(smcx, orc, monkeypatch):
 def test_server_rejects_oversized_request(smcx):
     srv = smcx.smcx_server_create(1 << 20, 2, 2)
     try:
-        j = W.lattice_job((80, 80, 80), 5, 3, 30.0, np.full(2, 800.0), stream=150)
+        # 2 * 100^3 = 2,000,000 bytes: larger than the 1 MiB budget
+        j = W.lattice_job((100, 100, 100), 5, 3, 30.0, np.full(2, 800.0), stream=150)
         with pytest.raises(smcx.SmcxError) as e:
             smcx.smcx_server_submit(srv, smcx.make_desc(j.L, 5, 3), j.sigma, j.epi, 800.0, 2)
         assert e.value.status == smcx.E_NOMEM
