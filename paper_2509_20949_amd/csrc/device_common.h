@@ -10,14 +10,21 @@ namespace smcx {
 // its histogram field; the top 3 bits give v back.
 __device__ __forceinline__ uint32_t decode(uint32_t code) { return code >> 5; }
 
-// acc + a * b on the 24-bit multiplier (a, b signed 24-bit), modulo 2^32:
-// one v_mad_i32_i24 (the compiler otherwise splits it into a multiply and a
-// three-input add)
+// acc + a * b on the 24-bit multiplier (a, b signed 24-bit), modulo 2^32
 __device__ __forceinline__ uint32_t mad24(uint32_t a, int32_t b, uint32_t acc)
 {
-    uint32_t r;
-    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(acc));
-    return r;
+    return (uint32_t)__mul24((int32_t)a, b) + acc;
+}
+
+// Cell (3 ix, 3 iy, 3 iz) of a 4 x 4 x 4 sub-colour round taken by `lane`:
+// lane bits 0 and 5 give ix, bits 1-2 iy, bits 3-4 iz.  Each half-wave then
+// covers two x columns, which with the 231-byte plane pitch puts its 32 byte
+// reads at any common offset into distinct LDS banks.
+__device__ __forceinline__ void lane_cell(int lane, int& ix, int& iy, int& iz)
+{
+    ix = (lane & 1) | ((lane >> 4) & 2);
+    iy = (lane >> 1) & 3;
+    iz = (lane >> 3) & 3;
 }
 
 __device__ __forceinline__ int wrap_add(int v, int L)   // v in [-L, 2L)

@@ -255,7 +255,8 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
     // ---- 27 residue classes x 2 sublattices = 54 rounds ----
     // Lane (ix, iy, iz) takes local cell (rx + 3 ix, ry + 3 iy, rz + 3 iz) of
     // residue class (rx, ry, rz); lanes past the block edge only compute.
-    const int ix = lane & 3, iy = (lane >> 2) & 3, iz = lane >> 4;
+    int ix, iy, iz;
+    lane_cell(lane, ix, iy, iz);
     const int lane_c = (3 * iz + 1) * kPP + (3 * iy + 1) * kP + (3 * ix + 1);
     constexpr int kBodyFromCorner = kArr + kPP + kP + 1;
     // global coordinates of the lane's cell in class (0,0,0); below 2L, and

@@ -254,7 +254,8 @@ void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem*
     }
 
     // ---- 27 residue classes x 4 sublattices = 108 rounds ----
-    const int ix = lane & 3, iy = (lane >> 2) & 3, iz = lane >> 4;
+    int ix, iy, iz;
+    lane_cell(lane, ix, iy, iz);
     const uint32_t bx = (uint32_t)(gx0 + 3 * ix), by = (uint32_t)(gy0 + 3 * iy), bz = (uint32_t)(gz0 + 3 * iz);
     const uint32_t LxLy = (uint32_t)Lx * (uint32_t)Ly;
     const bool narrow = LxLy < (1u << 24) && (uint64_t)LxLy * (uint32_t)Lz < (1ull << 32);

@@ -19,10 +19,15 @@ constexpr int kMaxS = 3;
 // LDS image of one block: two byte arrays (corner and body sublattice) of
 // 15 x 15 x 15 cells.  Corner array covers local cells -1..13, body array
 // -2..12, so a block of width <= 12 plus its interaction halo fits.
+// The plane pitch is padded from 225 to 231 bytes: with the lane-to-cell map
+// of lane_cell() (device_common.h), the 64 bytes a wave reads at one common
+// offset then lie in distinct 4-byte LDS banks of each half-wave (or share a
+// dword), for every offset a trial uses; at 225 they collide 3-way.
 constexpr int kP = 15;               // row pitch (cells)
-constexpr int kPP = kP * kP;         // plane pitch
-constexpr int kArr = 3376;           // bytes per sublattice array (15^3 = 3375, padded)
+constexpr int kPP = 231;             // plane pitch (15 rows + 6 bytes of padding)
+constexpr int kArr = 3460;           // bytes per sublattice array (last byte 14*231 + 14*15 + 14)
 constexpr int kWaveLds = 2 * kArr;   // bytes per wave
+static_assert(kPP >= 15 * kP && kArr > 14 * kPP + 14 * kP + 14, "LDS array too small");
 
 // Threshold tables: T0 | T1 | T2, 256 doubles each.
 constexpr int kTab = 768;
