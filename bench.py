@@ -37,11 +37,11 @@ HBM_PEAK = 8.0e12                 # bytes/s
 # Algorithmic integer work of one trial (K = 5 species, S = 3 shells), counted
 # in VALU issue slots of one lane (quarter-rate 32x32->64 multiplies = 4,
 # FP64 multiply/convert/compare = 2), the minimum the method needs:
-#   Philox4x32-10, one call per two trials: 10 x (2 x 4 + 2) / 2   = 50
+#   Philox4x32-10, one call per four trials: 10 x (2 x 4 + 2) / 4  = 25
 #   species counts of the 2 x 26 neighbours, one op each           = 52
 #   dE from the counts: 3 shell differences + 15 x (extract + mad) = 33
 #   Metropolis test: 2 FP64 mul + convert + compare                =  8
-OPS_PER_TRIAL = 50 + 52 + 33 + 8          # = 143
+OPS_PER_TRIAL = 25 + 52 + 33 + 8          # = 118
 # Algorithmic HBM bytes of one trial: each site is read once and written
 # once per sweep (uint8 species).
 BYTES_PER_TRIAL = 2

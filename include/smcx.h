@@ -32,16 +32,25 @@
  *   6 at (+-a, 0, 0), 24 at (+-a, +-a/2, +-a/2) (and permutations).  The EPI table
  *   is int32 micro-eV, layout epi[s][p][q] (S*K*K entries), symmetric in
  *   (p, q), |V| < 2^22.  Energies are exact int64 micro-eV.
- * Trial.  Sweep s, colour phase c: site b of a cell draws Philox4x32-10
- *   with key = (seed & 0xffffffff, seed >> 32) and counter = (cell &
- *   0xffffffff, cell >> 32, s, c + 16*(b >> 1)), using output words
- *   2*(b & 1) and 2*(b & 1) + 1.  BCC: the first word's top 3 bits pick the
- *   partner among the 8 first neighbours (bit a set = +a/2 along axis a).
- *   FCC: all trials of one (sweep, colour, sub-colour q) set take their
- *   partner in one sublattice b' = the k-th sublattice other than b, k =
- *   (t * 3) >> 32, t = word 0 of Philox4x32-10(key, (q, 0, s, c + 64)); bits
- *   30 and 31 of the first word give the signs (+a/2 when set) on the two
- *   axes where b and b' differ.  The second word u accepts an uphill swap iff dE < 2^24 and
+ * Trial.  Sweep s, colour phase c; key = (seed & 0xffffffff, seed >> 32).
+ *   BCC: a site (cell, b) with local cell l in its block and residue class
+ *   m = ((l_z%3)*3 + l_y%3)*3 + l_x%3 (sub-colour q = 2m + b) takes the
+ *   32-bit word w = word 2*(m & 1) + b of Philox4x32-10(key, (g & 0xffffffff,
+ *   g >> 32, s, c + 256*(m >> 1))), g = the cell at local coordinates
+ *   3*floor(l/3) of the same block.  Its partner is the first neighbour
+ *   with +a/2 along x iff bit 31 of w is set, along y iff bit 2q and along
+ *   z iff bit 2q+1 of R is set (-a/2 otherwise), R = the 128 bits of
+ *   Philox4x32-10(key, (0, 0, s, 32 + c)) (bit t = bit t%32 of word t/32);
+ *   its acceptance draw is u = w << 1 (mod 2^32).
+ *   FCC: site b of a cell draws Philox4x32-10(key, (cell & 0xffffffff,
+ *   cell >> 32, s, c + 16*(b >> 1))) and uses words 2*(b & 1) (direction)
+ *   and u = word 2*(b & 1) + 1 (acceptance); all trials of one (sweep,
+ *   colour, sub-colour q) set take their partner in one sublattice b' = the
+ *   k-th sublattice other than b, k = (t * 3) >> 32, t = word 0 of
+ *   Philox4x32-10(key, (q, 0, s, c + 64)); bits 30 and 31 of the direction
+ *   word give the signs (+a/2 when set) on the two axes where b and b'
+ *   differ.
+ *   Both lattices accept an uphill swap iff dE < 2^24 and
  *   (double)u < (T2[dE>>16] * T1[(dE>>8)&255]) * T0[dE&255], with
  *   beta = 1 / (86.17333262 * T) per micro-eV and
  *   T0[l] = exp(-l beta), T1[m] = exp(-256 m beta),
@@ -194,7 +203,8 @@ smcx_status smcx_batch_set_temperature(smcx_batch* batch, int32_t r, double T_ke
 /* Replica exchange (equations for P_swap and Delta): for each listed pair
  * (a[k], b[k]) in order, exchange the temperatures of replicas a and b with
  * probability min(1, exp((1/kB)(1/T_a - 1/T_b)(E_a - E_b))), deciding with
- * Philox4x32-10(key = (seed lo, seed hi), counter = (k, round, 0, 9)) word 0
+ * Philox4x32-10(key = (seed lo, seed hi), counter = (k, round lo, round hi, 9))
+ * word 0
  * as u: accept iff (double)u < 2^32 * min(1, exp(Delta)).  Replicas must
  * share L and K.  accepted[k] (nullable) receives the decisions. */
 smcx_status smcx_batch_exchange(smcx_batch* batch, const int32_t* a, const int32_t* b, int32_t n_pairs,

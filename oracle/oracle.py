@@ -52,6 +52,9 @@ def lib():
         L.or_schedule.argtypes = [C.c_int, p(C.c_int32), p(C.c_int32), C.c_uint64, C.c_uint32,
                                   p(C.c_uint8), p(C.c_uint8), p(C.c_int64)]
         L.or_neighbour.argtypes = [C.c_int, p(C.c_int32), C.c_int64, C.c_int]
+        L.or_bcc_draws.argtypes = [p(C.c_int32), p(C.c_int32), C.c_uint64, C.c_uint32, p(C.c_uint32),
+                                   p(C.c_uint8), p(C.c_uint8), p(C.c_uint32)]
+        L.or_bcc_draws.restype = C.c_int
         L.or_shell_size.argtypes = [C.c_int, C.c_int]
         L.or_n_sub.argtypes = [C.c_int]
         L.or_neighbour.restype = C.c_int64
@@ -163,6 +166,22 @@ def schedule(L, B, seed, s, lattice=BCC):
                       C.c_uint32(s), _ptr(col, C.c_uint8), _ptr(sub, C.c_uint8),
                       _ptr(blk, C.c_int64))
     return col, sub, blk
+
+
+def bcc_draws(L, B, seed, s):
+    """Per-site BCC trial draws of sweep s: (counters [N, 4], word, dir, u_acc)."""
+    Lv = _L(L)
+    N = n_sites(Lv, BCC)
+    ctr = np.zeros((N, 4), np.uint32)
+    word = np.zeros(N, np.uint8)
+    dirs = np.zeros(N, np.uint8)
+    u = np.zeros(N, np.uint32)
+    rc = lib().or_bcc_draws(_ptr(Lv, C.c_int32), _ptr(_L(B), C.c_int32), C.c_uint64(seed), C.c_uint32(s),
+                            _ptr(ctr, C.c_uint32), _ptr(word, C.c_uint8), _ptr(dirs, C.c_uint8),
+                            _ptr(u, C.c_uint32))
+    if rc != 0:
+        raise ValueError("invalid arguments")
+    return ctr, word, dirs, u
 
 
 def neighbour(L, i, k, lattice=BCC):

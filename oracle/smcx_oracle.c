@@ -370,8 +370,11 @@ void or_sweep_shift(const int32_t L[3], uint64_t seed, uint32_t s, int32_t shift
     for (int a = 0; a < 3; ++a) shift[a] = (int32_t)(((uint64_t)r[a] * (uint64_t)L[a]) >> 32);
 }
 
-void or_schedule(int lat, const int32_t L[3], const int32_t B[3], uint64_t seed, uint32_t s,
-                 uint8_t* colour, uint8_t* subcolour, int64_t* block)
+/* base (nullable, one entry per cell): the cell whose local coordinates are
+ * 3 * floor(l / 3) on every axis, in the same block (the cell of residue 0
+ * in the cell's group of 3 x 3 x 3 residues). */
+static void schedule_full(int lat, const int32_t L[3], const int32_t B[3], uint64_t seed, uint32_t s,
+                          uint8_t* colour, uint8_t* subcolour, int64_t* block, int64_t* base)
 {
     const int nsub = or_n_sub(lat);
     int32_t shift[3];
@@ -408,8 +411,86 @@ void or_schedule(int lat, const int32_t L[3], const int32_t B[3], uint64_t seed,
                     subcolour[nsub * cell + b] = (uint8_t)(q + b);
                     if (block) block[nsub * cell + b] = ((int64_t)kz * n[1] + ky) * n[0] + kx;
                 }
+                if (base) {
+                    int64_t bx = wrap(x - lx % 3, L[0]), by = wrap(y - ly % 3, L[1]), bz = wrap(z - lz % 3, L[2]);
+                    base[cell] = (bz * L[1] + by) * L[0] + bx;
+                }
             }
     for (int a = 0; a < 3; ++a) { free(kof[a]); free(lof[a]); }
+}
+
+void or_schedule(int lat, const int32_t L[3], const int32_t B[3], uint64_t seed, uint32_t s,
+                 uint8_t* colour, uint8_t* subcolour, int64_t* block)
+{
+    schedule_full(lat, L, B, seed, s, colour, subcolour, block, NULL);
+}
+
+/* BCC trial draws (reading; the paper fixes neither the random numbers nor
+ * how a swap partner is picked beyond its being a nearest neighbour).
+ *   A trial at site (cell, b) with residue m = ((l_z%3)*3 + l_y%3)*3 + l_x%3
+ *   (sub-colour q = 2m + b) takes the 32-bit word 2*(m & 1) + b of
+ *   Philox4x32-10(key = seed, counter = (g lo, g hi, s, c + 256*(m >> 1))),
+ *   g = the cell's base cell (see schedule_full): one call serves the four
+ *   trials of residues 2k and 2k+1 of one base cell.
+ *   Partner: first-neighbour vector number dir (bit a set = +1 on axis a).
+ *   Bit 0 (x) is the word's top bit; bits 1 (y) and 2 (z) are shared by all
+ *   trials of one (sweep, colour, sub-colour) set: bits 2q and 2q+1 of the
+ *   128-bit string R_c = Philox4x32-10(key, (0, 0, s, 32 + c)), bit t being
+ *   bit t%32 of word t/32.  Every trial still proposes the swap of one
+ *   fixed pair, chosen without looking at the configuration, so each trial
+ *   is a Metropolis step reversible with respect to Eq. (1); over the set
+ *   draw and the word, dir is uniform on 0..7.
+ *   Acceptance draw: the word shifted left by one (its low 31 bits, times
+ *   two), compared as in or_accept. */
+static int set_bit(const uint32_t R[4], int t) { return (int)((R[t >> 5] >> (t & 31)) & 1u); }
+
+static void bcc_draw(const uint32_t key[2], uint32_t s, int c, int q, int64_t g, const uint32_t R[4],
+                     uint32_t ctr[4], int* word, int* dir, uint32_t* u_acc)
+{
+    int m = q >> 1, b = q & 1;
+    ctr[0] = (uint32_t)g;
+    ctr[1] = (uint32_t)((uint64_t)g >> 32);
+    ctr[2] = s;
+    ctr[3] = (uint32_t)c + 256u * (uint32_t)(m >> 1);
+    uint32_t r[4];
+    or_philox4x32_10(ctr, key, r);
+    *word = 2 * (m & 1) + b;
+    uint32_t u = r[*word];
+    *dir = (int)(u >> 31) | set_bit(R, 2 * q) << 1 | set_bit(R, 2 * q + 1) << 2;
+    *u_acc = u << 1;
+}
+
+static void bcc_set_bits(const uint32_t key[2], uint32_t s, int c, uint32_t R[4])
+{
+    uint32_t ctr[4] = {0u, 0u, s, 32u + (uint32_t)c};
+    or_philox4x32_10(ctr, key, R);
+}
+
+int or_bcc_draws(const int32_t L[3], const int32_t B[3], uint64_t seed, uint32_t s, uint32_t* ctr,
+                 uint8_t* word, uint8_t* dir, uint32_t* u_acc)
+{
+    for (int a = 0; a < 3; ++a)
+        if (L[a] < 2 || B[a] < 2) return -1;
+    int64_t N = n_sites(0, L), ncell = N / 2;
+    uint8_t* colour = (uint8_t*)malloc(N);
+    uint8_t* sub = (uint8_t*)malloc(N);
+    int64_t* base = (int64_t*)malloc(sizeof(int64_t) * ncell);
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t R[8][4];
+    schedule_full(0, L, B, seed, s, colour, sub, NULL, base);
+    for (int c = 0; c < 8; ++c) bcc_set_bits(key, s, c, R[c]);
+    for (int64_t i = 0; i < N; ++i) {
+        int w, d;
+        uint32_t u;
+        bcc_draw(key, s, colour[i], sub[i], base[i / 2], R[colour[i]], ctr + 4 * i, &w, &d, &u);
+        word[i] = (uint8_t)w;
+        dir[i] = (uint8_t)d;
+        u_acc[i] = u;
+    }
+    free(colour);
+    free(sub);
+    free(base);
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -474,7 +555,9 @@ int or_sweep(int lat, const int32_t L[3], const int32_t B[3], int S, int K, cons
         if (sigma[i] >= K) return -1;
     uint8_t* colour = (uint8_t*)malloc(N);
     uint8_t* sub = (uint8_t*)malloc(N);
+    int64_t* base = lat == 0 ? (int64_t*)malloc(sizeof(int64_t) * (N / 2)) : NULL;
     int64_t* order = (int64_t*)malloc(sizeof(int64_t) * N);
+    uint32_t R[8][4];
     int64_t start[8 * 27 * 4 + 1];
     int partner_sub[8 * 27 * 4];
     double tab[768];
@@ -483,7 +566,9 @@ int or_sweep(int lat, const int32_t L[3], const int32_t B[3], int S, int K, cons
     for (int32_t t = 0; t < n; ++t) {
         uint32_t s = s0 + (uint32_t)t;
         or_thresholds(T[t], tab);
-        or_schedule(lat, L, B, seed, s, colour, sub, NULL);
+        schedule_full(lat, L, B, seed, s, colour, sub, NULL, base);
+        if (lat == 0)
+            for (int c = 0; c < 8; ++c) bcc_set_bits(key, s, c, R[c]);
         /* order: counting sort on (colour, sub-colour), stable in site id */
         memset(start, 0, sizeof(start));
         for (int64_t i = 0; i < N; ++i) start[colour[i] * 27 * nsub + sub[i] + 1] += 1;
@@ -504,15 +589,23 @@ int or_sweep(int lat, const int32_t L[3], const int32_t B[3], int S, int K, cons
                 int64_t i = order[r];
                 int64_t cell = i / nsub;
                 int b = (int)(i % nsub);
-                /* sites 0, 1 of a cell share one Philox call, sites 2, 3 (FCC)
-                 * another one with counter word 3 raised by 16 */
-                uint32_t ctr[4] = {(uint32_t)cell, (uint32_t)(cell >> 32), s,
-                                   (uint32_t)colour[i] + 16u * (uint32_t)(b >> 1)};
-                uint32_t rnd[4];
-                or_philox4x32_10(ctr, key, rnd);
-                uint32_t u_dir = rnd[2 * (b & 1)], u_acc = rnd[2 * (b & 1) + 1];
-                int64_t j = lat == 1 ? fcc_partner(L, i, partner_sub[g], u_dir)
-                                     : or_neighbour(lat, L, i, (int)(u_dir >> 29));
+                int64_t j;
+                uint32_t u_acc;
+                if (lat == 0) {
+                    uint32_t ctr[4];
+                    int word, dir;
+                    bcc_draw(key, s, colour[i], sub[i], base[cell], R[colour[i]], ctr, &word, &dir, &u_acc);
+                    j = or_neighbour(0, L, i, dir);
+                } else {
+                    /* FCC: sites 0, 1 of a cell share one Philox call, sites
+                     * 2, 3 another one with counter word 3 raised by 16 */
+                    uint32_t ctr[4] = {(uint32_t)cell, (uint32_t)(cell >> 32), s,
+                                       (uint32_t)colour[i] + 16u * (uint32_t)(b >> 1)};
+                    uint32_t rnd[4];
+                    or_philox4x32_10(ctr, key, rnd);
+                    u_acc = rnd[2 * (b & 1) + 1];
+                    j = fcc_partner(L, i, partner_sub[g], rnd[2 * (b & 1)]);
+                }
                 if (sigma[i] == sigma[j]) continue;
                 int64_t dE = or_delta_energy(lat, L, S, K, epi, sigma, i, j);
                 if (or_accept(dE, u_acc, tab)) {
@@ -531,6 +624,7 @@ int or_sweep(int lat, const int32_t L[3], const int32_t B[3], int S, int K, cons
     }
     free(colour);
     free(sub);
+    free(base);
     free(order);
     return 0;
 }

@@ -77,6 +77,12 @@ void or_sweep_shift(const int32_t L[3], uint64_t seed, uint32_t s, int32_t shift
 void or_schedule(int lat, const int32_t L[3], const int32_t B[3], uint64_t seed, uint32_t s,
                  uint8_t* colour, uint8_t* subcolour, int64_t* block);
 
+/* BCC trial draws of sweep s for every site i: Philox counter ctr[4i..4i+3],
+ * the word used, the first-neighbour vector number (bit a set = +1 on axis
+ * a) and the acceptance draw.  Returns 0, or -1 on invalid arguments. */
+int or_bcc_draws(const int32_t L[3], const int32_t B[3], uint64_t seed, uint32_t s, uint32_t* ctr,
+                 uint8_t* word, uint8_t* dir, uint32_t* u_acc);
+
 /* Site index of neighbour `k` of site i, k indexing the displacement set of
  * shells 1..S in the order documented in smcx_oracle.c. */
 int64_t or_neighbour(int lat, const int32_t L[3], int64_t i, int k);

@@ -79,18 +79,20 @@ __device__ __forceinline__ void histogram(const uint8_t* lat, int a, uint32_t (&
     }
 }
 
-// One trial: site at LDS byte ai (sublattice SUB), draws (u_dir, u_acc).
-// Returns through dEsum / nacc; updates the LDS image in place.
+// One trial: site at LDS byte ai (sublattice SUB) with its 32-bit draw u.
+// The partner is the first neighbour whose x step is the top bit of u and
+// whose y and z steps (shared by the whole round) give yz = ey*kP + ez*kPP;
+// the acceptance draw is u << 1.  Returns through dEsum / nacc; updates the
+// LDS image in place.
 template <int KMAX, int SMAX, int SUB>
-__device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u_dir, uint32_t u_acc, bool valid,
+__device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int yz, bool valid,
                                       const int32_t* wtab, const double* tab, int64_t& dEsum,
                                       uint32_t& nacc)
 {
     constexpr int F = Field<KMAX>::F;
     constexpr int WR = wrow(KMAX, SMAX);
-    const uint32_t dir = u_dir >> 29;
-    const int aj = ai + s1base<SUB>() + (int)(dir & 1u) + (int)((dir >> 1) & 1u) * kP +
-                   (int)((dir >> 2) & 1u) * kPP;
+    const uint32_t u_acc = u << 1;
+    const int aj = ai + s1base<SUB>() + (int)(u >> 31) + yz;
     const uint32_t ci = lat[ai];
     const uint32_t cj = lat[aj];
 
@@ -130,14 +132,15 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u_dir, uint
     // Metropolis decision, Eq. (3), on the FP64 byte tables.
     const int e = dE < 1 ? 1 : (dE > (1 << 24) - 1 ? (1 << 24) - 1 : dE);
     const double thr = (tab[512 + (e >> 16)] * tab[256 + ((e >> 8) & 255)]) * tab[e & 255];
-    const bool up_ok = dE < (1 << 24) && (double)u_acc < thr;
-    const bool accept = valid && ci != cj && (dE <= 0 || up_ok);
-    if (accept) {
-        lat[ai] = (uint8_t)cj;
-        lat[aj] = (uint8_t)ci;
-        dEsum += dE;
-        nacc += 1u;
-    }
+    const bool up_ok = (dE < (1 << 24)) & ((double)u_acc < thr);
+    const bool accept = valid & (ci != cj) & ((dE <= 0) | up_ok);
+    // Both bytes are stored by every lane (unchanged unless accepted): no
+    // two lanes of a round touch the same byte, and a branch-free trial
+    // keeps the whole round in one basic block for the scheduler.
+    lat[ai] = (uint8_t)(accept ? cj : ci);
+    lat[aj] = (uint8_t)(accept ? ci : cj);
+    dEsum += accept ? (int64_t)dE : 0;
+    nacc += accept ? 1u : 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -208,24 +211,41 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
     // ---- stage block + halo: local cells -2..w+1 on each axis ----
     // Fast path (the block's x-range does not cross the periodic boundary):
     // 8 lanes per row, each reading two cells (corner, body, corner, body
-    // bytes) as one aligned dword, or two when the cells start 2 bytes into
-    // a dword (rows of an odd-length lattice alternate).  The lattice base is
-    // 4-byte aligned.
+    // bytes) from the dword at byte `at & ~3` and the one at `(at + 2) & ~3`
+    // (the same dword when the cells start on a dword boundary; rows of an
+    // odd-length lattice alternate).  All 32 rows of a lane are loaded
+    // before any is written to LDS, so the loads are in flight together.
+    // Lanes and rows outside the halo load a clamped in-range address and
+    // store nothing.  The lattice base is 4-byte aligned.
     if (gx0 >= 3 && gx0 + wx + 4 <= Lx) {
         const int lx0 = 2 * (lane & 7) - 2;       // cells lx0, lx0 + 1
         const bool lane_ok = lx0 <= wx + 1;
         const bool c0 = lx0 >= -1, c1 = lx0 + 1 <= wx + 1, b0 = lx0 <= wx, b1 = lx0 + 1 <= wx;
-        for (int r = lane >> 3; r < 256; r += 8) {
-            const int ly = (r & 15) - 2, lz = (r >> 4) - 2;
-            if (!lane_ok || ly > wy + 1 || lz > wz + 1) continue;
-            const uint32_t gy = (uint32_t)wrap_add(gy0 + ly, Ly), gz = (uint32_t)wrap_add(gz0 + lz, Lz);
+        const int lxa = lane_ok ? lx0 : -2;        // an in-range address for every lane
+        // row r = (lane >> 3) + 8 it: ly = (lane >> 3) - 2 + 8 (it & 1), lz = (it >> 1) - 2
+        uint32_t gyrow[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int ly = min((lane >> 3) - 2 + 8 * h, wy + 1);
+            gyrow[h] = (uint32_t)wrap_add(gy0 + ly, Ly);
+        }
+        uint32_t q0[32], q1[32], al[32];
+#pragma unroll
+        for (int it = 0; it < 32; ++it) {
+            const int lz = min((it >> 1) - 2, wz + 1);
+            const uint32_t gz = (uint32_t)wrap_add(gz0 + lz, Lz), gy = gyrow[it & 1];
             const size_t row = narrow ? (size_t)(__umul24(gz, LxLy) + __umul24(gy, (uint32_t)Lx))
                                       : ((size_t)gz * (uint32_t)Ly + gy) * (uint32_t)Lx;
-            const size_t at = 2 * (row + (size_t)(gx0 + lx0));      // byte of corner(lx0)
-            const uint32_t* q = (const uint32_t*)(g + (at & ~(size_t)3));
-            uint32_t v = q[0];
-            if (at & 2) v = __builtin_amdgcn_alignbyte(q[1], v, 2);
-            v = encode2(v, F);
+            const size_t at = 2 * (row + (size_t)(gx0 + lxa));     // byte of corner(lxa)
+            q0[it] = *(const uint32_t*)(g + (at & ~(size_t)3));
+            q1[it] = *(const uint32_t*)(g + ((at + 2) & ~(size_t)3));
+            al[it] = (uint32_t)at & 2u;
+        }
+#pragma unroll
+        for (int it = 0; it < 32; ++it) {
+            const int ly = (lane >> 3) - 2 + 8 * (it & 1), lz = (it >> 1) - 2;
+            if (!lane_ok || ly > wy + 1 || lz > wz + 1) continue;
+            const uint32_t v = encode2(__builtin_amdgcn_alignbyte(q1[it], q0[it], al[it]), F);
             const int crow = (lz + 1) * kPP + (ly + 1) * kP + (lx0 + 1);
             const int brow = kArr + (lz + 2) * kPP + (ly + 2) * kP + (lx0 + 2);
             const bool cy = ly >= -1 && lz >= -1, by = ly <= wy && lz <= wz;
@@ -254,73 +274,124 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
 
     // ---- 27 residue classes x 2 sublattices = 54 rounds ----
     // Lane (ix, iy, iz) takes local cell (rx + 3 ix, ry + 3 iy, rz + 3 iz) of
-    // residue class (rx, ry, rz); lanes past the block edge only compute.
+    // residue class m = (rz*3 + ry)*3 + rx; lanes past the block edge only
+    // compute.  Random words: one Philox call per lane and residue pair
+    // (2k, 2k+1), counter (base cell, s, colour + 256 k), the base cell being
+    // the lane's cell of class 0; class 2k takes words 0 (corner) and 1
+    // (body), class 2k+1 words 2 and 3.  The y and z steps of every partner
+    // of sub-colour q = 2m + b are bits 2q and 2q+1 of one Philox call
+    // (0, 0, s, 32 + colour), the same for all blocks of the colour.
     int ix, iy, iz;
     lane_cell(lane, ix, iy, iz);
     const int lane_c = (3 * iz + 1) * kPP + (3 * iy + 1) * kP + (3 * ix + 1);
     constexpr int kBodyFromCorner = kArr + kPP + kP + 1;
-    // global coordinates of the lane's cell in class (0,0,0); below 2L, and
-    // below 2L after adding r < 3 for every lane that holds a site
-    const uint32_t bx = (uint32_t)(gx0 + 3 * ix), by = (uint32_t)(gy0 + 3 * iy), bz = (uint32_t)(gz0 + 3 * iz);
+    const uint32_t k0 = D.key[0], k1 = D.key[1];
+    uint32_t base_lo, base_hi;
+    {
+        // a lane that holds a site has gx0 + 3 ix < 2 Lx: one conditional
+        // subtraction wraps it (other lanes only feed their draws to no trial)
+        uint32_t bx = (uint32_t)(gx0 + 3 * ix), by = (uint32_t)(gy0 + 3 * iy), bz = (uint32_t)(gz0 + 3 * iz);
+        bx = min(bx, bx - (uint32_t)Lx);
+        by = min(by, by - (uint32_t)Ly);
+        bz = min(bz, bz - (uint32_t)Lz);
+        const uint64_t cell = narrow ? (uint64_t)(__umul24(bz, LxLy) + __umul24(by, (uint32_t)Lx) + bx)
+                                     : ((uint64_t)bz * (uint32_t)Ly + by) * (uint32_t)Lx + bx;
+        base_lo = (uint32_t)cell;
+        base_hi = (uint32_t)(cell >> 32);
+    }
+    uint64_t yz_lo, yz_hi;   // the 128 partner bits, wave-uniform
+    {
+        uint32_t R[4] = {0u, 0u, s, 32u + (uint32_t)colour};
+        philox4x32_10(R, k0, k1);
+        // (readfirstlane returns int: widen through uint32_t, not by sign)
+        yz_lo = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(R[0]) |
+                (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(R[1]) << 32;
+        yz_hi = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(R[2]) |
+                (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(R[3]) << 32;
+    }
     int64_t dEsum = 0;
     uint32_t nacc = 0;
-    const uint32_t k0 = D.key[0], k1 = D.key[1];
-    for (int m = 0; m < 27; ++m) {
+    // rounds of residue class m (corner then body) with draws uc, ub and the
+    // four partner bits of sub-colours 2m, 2m+1 in b4
+    auto rounds = [&](int m, uint32_t uc, uint32_t ub, uint32_t b4) {
         const int rx = m % 3, ry = (m / 3) % 3, rz = m / 9;
-        const bool valid = 3 * ix < wx - rx && 3 * iy < wy - ry && 3 * iz < wz - rz;
-        uint32_t gx = bx + rx, gy = by + ry, gz = bz + rz;
-        gx = min(gx, gx - (uint32_t)Lx);   // periodic wrap of [0, 2L)
-        gy = min(gy, gy - (uint32_t)Ly);
-        gz = min(gz, gz - (uint32_t)Lz);
-        uint64_t cell;
-        if (narrow)
-            cell = __umul24(gz, LxLy) + __umul24(gy, (uint32_t)Lx) + gx;
-        else
-            cell = ((uint64_t)gz * (uint32_t)Ly + gy) * (uint32_t)Lx + gx;
-        uint32_t r[4] = {(uint32_t)cell, (uint32_t)(cell >> 32), s, (uint32_t)colour};
-        philox4x32_10(r, k0, k1);
+        const bool valid = (3 * ix < wx - rx) & (3 * iy < wy - ry) & (3 * iz < wz - rz);
         const int ac = lane_c + (rz * kPP + ry * kP + rx);
-        trial<KMAX, SMAX, 0>(lat, ac, r[0], r[1], valid, s_w, s_tab, dEsum, nacc);
+        const int yz0 = (int)(b4 & 1u) * kP + (int)((b4 >> 1) & 1u) * kPP;
+        const int yz1 = (int)((b4 >> 2) & 1u) * kP + (int)((b4 >> 3) & 1u) * kPP;
+        trial<KMAX, SMAX, 0>(lat, ac, uc, yz0, valid, s_w, s_tab, dEsum, nacc);
         __builtin_amdgcn_wave_barrier();
-        trial<KMAX, SMAX, 1>(lat, ac + kBodyFromCorner, r[2], r[3], valid, s_w, s_tab, dEsum, nacc);
+        trial<KMAX, SMAX, 1>(lat, ac + kBodyFromCorner, ub, yz1, valid, s_w, s_tab, dEsum, nacc);
         __builtin_amdgcn_wave_barrier();
+    };
+    uint32_t w[4] = {base_lo, base_hi, s, (uint32_t)colour};
+    philox4x32_10(w, k0, k1);
+    for (int k = 0; k < 13; ++k) {
+        const uint32_t u0 = w[0], u1 = w[1], u2 = w[2], u3 = w[3];
+        // the next pair's call, issued ahead of this pair's LDS traffic (same
+        // basic block, so the scheduler can interleave the two)
+        w[0] = base_lo; w[1] = base_hi; w[2] = s; w[3] = (uint32_t)colour + 256u * (uint32_t)(k + 1);
+        philox4x32_10(w, k0, k1);
+        // partner bits of sub-colours 4k .. 4k+3: bits 8k .. 8k+7
+        const uint32_t bits = (uint32_t)(8 * k < 64 ? yz_lo >> (8 * k) : yz_hi >> (8 * k - 64));
+        rounds(2 * k, u0, u1, bits);
+        rounds(2 * k + 1, u2, u3, bits >> 4);
     }
+    rounds(26, w[0], w[1], (uint32_t)(yz_hi >> 40));   // bits 104 .. 107
 
     // ---- write back: corner cells 0..w, body cells -1..w-1 ----
     // Fast path (no periodic wrap along x): 8 lanes per row, each owning one
     // aligned dword of the row's span (corner(-1) .. body(w)); it stores the
     // dword whole, or only its bytes that belong to the corner box [0, w]^3
-    // or the body box [-1, w-1]^3 where the span or a box ends.
+    // or the body box [-1, w-1]^3 where the span or a box ends.  Rows go in
+    // batches of four per lane: the 16 LDS reads of a batch are issued
+    // before any is used.  Rows and cells outside the boxes read clamped
+    // in-image LDS bytes and store nothing.
     if (gx0 >= 1 && gx0 + wx < Lx) {
-        for (int r = lane >> 3; r < 256; r += 8) {
-            const int ly = (r & 15) - 1, lz = (r >> 4) - 1;
-            if (ly > wy || lz > wz) continue;
-            const uint32_t gy = (uint32_t)wrap_add(gy0 + ly, Ly), gz = (uint32_t)wrap_add(gz0 + lz, Lz);
-            const size_t row = narrow ? (size_t)(__umul24(gz, LxLy) + __umul24(gy, (uint32_t)Lx))
-                                      : ((size_t)gz * (uint32_t)Ly + gy) * (uint32_t)Lx;
-            const size_t at0 = 2 * (row + (size_t)gx0);             // byte of corner(0)
-            const size_t d = ((at0 - 2) & ~(size_t)3) + 4u * (uint32_t)(lane & 7);
-            const int lxa = (int)((int64_t)(d - at0) / 2);          // cells lxa, lxa + 1
-            const bool cy = ly >= 0 && lz >= 0, by = ly < wy && lz < wz;
-            const bool v0 = cy && lxa >= 0 && lxa <= wx;              // corner(lxa)
-            const bool v1 = by && lxa >= -1 && lxa < wx;              // body(lxa)
-            const bool v2 = cy && lxa + 1 >= 0 && lxa + 1 <= wx;      // corner(lxa + 1)
-            const bool v3 = by && lxa + 1 >= -1 && lxa + 1 < wx;      // body(lxa + 1)
-            if (!(v0 || v1 || v2 || v3)) continue;
-            const int crow = (lz + 1) * kPP + (ly + 1) * kP + (lxa + 1);
-            const int brow = kArr + (lz + 2) * kPP + (ly + 2) * kP + (lxa + 2);
-            const uint32_t e0 = v0 ? decode(lat[crow]) : 0u;
-            const uint32_t e1 = v1 ? decode(lat[brow]) : 0u;
-            const uint32_t e2 = v2 ? decode(lat[crow + 1]) : 0u;
-            const uint32_t e3 = v3 ? decode(lat[brow + 1]) : 0u;
-            uint8_t* q = g + d;
-            if (v0 && v1 && v2 && v3) {
-                *(uint32_t*)q = e0 | e1 << 8 | e2 << 16 | e3 << 24;
-            } else {
-                if (v0) q[0] = (uint8_t)e0;
-                if (v1) q[1] = (uint8_t)e1;
-                if (v2) q[2] = (uint8_t)e2;
-                if (v3) q[3] = (uint8_t)e3;
+        const int lrow = lane >> 3;                 // rows lrow + 8 it: ly = lrow - 1 + 8 (it & 1), lz = (it >> 1) - 1
+        const int nit = 2 * (wz + 2);               // rows with lz <= wz
+        for (int it0 = 0; it0 < nit; it0 += 4) {
+            uint32_t e[4][4];
+            uint8_t* dst[4];
+            uint32_t msk[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int it = it0 + u;
+                const int ly = lrow - 1 + 8 * (it & 1), lz = (it >> 1) - 1;
+                const bool ok = ly <= wy && lz <= wz;
+                const int lyc = min(ly, wy), lzc = min(lz, wz);
+                const uint32_t gy = (uint32_t)wrap_add(gy0 + lyc, Ly), gz = (uint32_t)wrap_add(gz0 + lzc, Lz);
+                const size_t row = narrow ? (size_t)(__umul24(gz, LxLy) + __umul24(gy, (uint32_t)Lx))
+                                          : ((size_t)gz * (uint32_t)Ly + gy) * (uint32_t)Lx;
+                const size_t at0 = 2 * (row + (size_t)gx0);           // byte of corner(0)
+                const size_t d = ((at0 - 2) & ~(size_t)3) + 4u * (uint32_t)(lane & 7);
+                const int lxa = (int)((int64_t)(d - at0) / 2);        // cells lxa, lxa + 1; lxa in -2..13
+                const bool cy = ok && ly >= 0 && lz >= 0, by = ok && ly < wy && lz < wz;
+                msk[u] = (uint32_t)(cy && lxa >= 0 && lxa <= wx)                // corner(lxa)
+                       | (uint32_t)(by && lxa >= -1 && lxa < wx) << 1          // body(lxa)
+                       | (uint32_t)(cy && lxa + 1 >= 0 && lxa + 1 <= wx) << 2  // corner(lxa + 1)
+                       | (uint32_t)(by && lxa + 1 >= -1 && lxa + 1 < wx) << 3; // body(lxa + 1)
+                const int crow = (lzc + 1) * kPP + (lyc + 1) * kP + (max(lxa, -1) + 1);
+                const int brow = kArr + (lzc + 2) * kPP + (lyc + 2) * kP + (lxa + 2);
+                e[u][0] = lat[crow];
+                e[u][1] = lat[brow];
+                e[u][2] = lat[crow + 1];
+                e[u][3] = lat[brow + 1];
+                dst[u] = g + d;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t m = msk[u];
+                if (!m) continue;
+                uint8_t* q = dst[u];
+                if (m == 15u) {
+                    *(uint32_t*)q = decode(e[u][0]) | decode(e[u][1]) << 8 | decode(e[u][2]) << 16 |
+                                    decode(e[u][3]) << 24;
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (m >> k & 1u) q[k] = (uint8_t)decode(e[u][k]);
+                }
             }
         }
     } else {
