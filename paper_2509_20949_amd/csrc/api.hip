@@ -153,6 +153,25 @@ smcx_status upload_tables(smcx_ctx* c, const double* T, int n, uint64_t s0)
                    "hipMemcpy(lattice descriptor)");
 }
 
+smcx_status read_state(smcx_ctx* c, int64_t* E, uint64_t* accepted)
+{
+    std::vector<int64_t> h(kStateWords);
+    smcx_status st = ctx_hip(c, hipMemcpyAsync(h.data(), c->d_state, sizeof(int64_t) * kStateWords,
+                                               hipMemcpyDeviceToHost, c->stream), "hipMemcpyAsync(state)");
+    if (!st) st = ctx_hip(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    if (st) return st;
+    state_sum(h.data(), E, accepted);
+    return SMCX_OK;
+}
+
+smcx_status write_state(smcx_ctx* c, int64_t E, uint64_t accepted)
+{
+    std::vector<int64_t> h(kStateWords);
+    state_init(h.data(), E, accepted);
+    return ctx_hip(c, hipMemcpy(c->d_state, h.data(), sizeof(int64_t) * kStateWords, hipMemcpyHostToDevice),
+                   "hipMemcpy(state)");
+}
+
 smcx_status recompute_energy(smcx_ctx* c, int64_t* E)
 {
     smcx_status st = ctx_hip(c, hipMemsetAsync(c->d_counts, 0, sizeof(unsigned long long) * kMaxS * kMaxK * kMaxK,
@@ -193,20 +212,20 @@ static smcx_status ctx_init(smcx_ctx* c, const smcx_desc* d, const int32_t B[3],
     smcx_status st;
     st = ctx_hip(c, hipMalloc(&c->d_lat, sizeof(DevLattice)), "hipMalloc(descriptor)");
     if (st) return st;
-    st = ctx_hip(c, hipMalloc(&c->d_state, sizeof(int64_t) + sizeof(unsigned long long)), "hipMalloc(state)");
+    st = ctx_hip(c, hipMalloc(&c->d_state, sizeof(int64_t) * kStateWords), "hipMalloc(state)");
     if (st) return st;
     st = ctx_hip(c, hipMalloc(&c->d_counts, sizeof(unsigned long long) * kMaxS * kMaxK * kMaxK), "hipMalloc(counts)");
     if (st) return st;
     const int wr = wrow(c->kmax, c->smax);
     std::vector<int32_t> w((size_t)c->kmax * c->kmax * wr);
-    build_wtab(epi, c->K, c->S, c->kmax, c->smax, wtab_bias(d->lattice, c->kmax), w.data());
+    const int drop = build_wtab(epi, c->K, c->S, c->kmax, c->smax, wtab_bias(d->lattice, c->kmax), w.data());
     st = ctx_hip(c, hipMalloc(&c->d_wtab, sizeof(int32_t) * w.size()), "hipMalloc(weights)");
     if (st) return st;
     st = ctx_hip(c, hipMemcpy(c->d_wtab, w.data(), sizeof(int32_t) * w.size(), hipMemcpyHostToDevice), "hipMemcpy(weights)");
     if (st) return st;
     c->h_lat.wtab = c->d_wtab;
-    c->h_lat.energy = (int64_t*)c->d_state;
-    c->h_lat.accepted = (unsigned long long*)((char*)c->d_state + sizeof(int64_t));
+    c->h_lat.drop_last = drop;
+    c->h_lat.state = (int64_t*)c->d_state;
     c->h_lat.species = c->d_species;
     c->h_lat.sweep0 = 0;   // single lattice: launch step t is the sweep index
     c->T_default = T;
@@ -215,8 +234,7 @@ static smcx_status ctx_init(smcx_ctx* c, const smcx_desc* d, const int32_t B[3],
     int64_t E0 = 0;
     st = recompute_energy(c, &E0);
     if (st) return st;
-    int64_t init[2] = {E0, 0};
-    return ctx_hip(c, hipMemcpy(c->d_state, init, sizeof(init), hipMemcpyHostToDevice), "hipMemcpy(state)");
+    return write_state(c, E0, 0);
 }
 
 void ctx_release(smcx_ctx* c)
@@ -422,13 +440,7 @@ smcx_status smcx_sweep(smcx_ctx* c, int32_t n)
 smcx_status smcx_energy(smcx_ctx* c, int64_t* E)
 {
     if (!c || !E) return fail(c, SMCX_E_INVALID, "NULL argument");
-    int64_t h[2];
-    smcx_status st = ctx_hip(c, hipMemcpyAsync(h, c->d_state, sizeof(h), hipMemcpyDeviceToHost, c->stream),
-                             "hipMemcpyAsync");
-    if (!st) st = ctx_hip(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
-    if (st) return st;
-    *E = h[0];
-    return SMCX_OK;
+    return read_state(c, E, nullptr);
 }
 
 smcx_status smcx_energy_recompute(smcx_ctx* c, int64_t* E)
@@ -476,14 +488,12 @@ smcx_status smcx_get_config(smcx_ctx* c, uint8_t* out, size_t n)
 smcx_status smcx_get_stats(smcx_ctx* c, uint64_t* sweeps, uint64_t* attempted, uint64_t* accepted, int32_t block[3])
 {
     if (!c) return fail_global(SMCX_E_INVALID, "ctx is NULL");
-    int64_t h[2];
-    smcx_status st = ctx_hip(c, hipMemcpyAsync(h, c->d_state, sizeof(h), hipMemcpyDeviceToHost, c->stream),
-                             "hipMemcpyAsync");
-    if (!st) st = ctx_hip(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    uint64_t acc = 0;
+    smcx_status st = read_state(c, nullptr, &acc);
     if (st) return st;
     if (sweeps) *sweeps = c->sweeps;
     if (attempted) *attempted = c->attempted;
-    if (accepted) *accepted = (uint64_t)h[1];
+    if (accepted) *accepted = acc;
     if (block)
         for (int a = 0; a < 3; ++a) block[a] = c->B[a];
     return SMCX_OK;
@@ -504,8 +514,7 @@ smcx_status smcx_set_state(smcx_ctx* c, const uint8_t* species, uint64_t sweep_i
     int64_t E = 0;
     st = recompute_energy(c, &E);
     if (st) return st;
-    int64_t init[2] = {E, 0};
-    return ctx_hip(c, hipMemcpy(c->d_state, init, sizeof(init), hipMemcpyHostToDevice), "hipMemcpy(state)");
+    return write_state(c, E, 0);
 }
 
 smcx_status smcx_synchronize(smcx_ctx* c)

@@ -26,7 +26,7 @@ struct smcx_batch {
     uint8_t* d_species = nullptr;               // all lattices, 256-byte aligned slices
     DevLattice* d_lats = nullptr;
     std::vector<DevLattice> h_lats;
-    int64_t* d_states = nullptr;                // [n][2]: running energy, accepted
+    int64_t* d_states = nullptr;                // [n][kStateWords]: running energy, accepted (slots)
     double* d_tabs = nullptr;                   // [n][768]
     int32_t* d_wtabs = nullptr;                 // [n][kmax*kmax*wrow]
     unsigned long long* d_counts = nullptr;     // pair-count scratch shared by the views
@@ -127,7 +127,7 @@ smcx_status smcx_batch_create(int32_t n, const smcx_desc* descs, const uint8_t* 
     smcx_status st = bhip(b, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking), "hipStreamCreate");
     if (!st) st = bhip(b, hipMalloc(&b->d_species, total), "hipMalloc(lattices)");
     if (!st) st = bhip(b, hipMalloc(&b->d_lats, sizeof(DevLattice) * n), "hipMalloc(descriptors)");
-    if (!st) st = bhip(b, hipMalloc(&b->d_states, sizeof(int64_t) * 2 * n), "hipMalloc(states)");
+    if (!st) st = bhip(b, hipMalloc(&b->d_states, sizeof(int64_t) * kStateWords * n), "hipMalloc(states)");
     if (!st) st = bhip(b, hipMalloc(&b->d_tabs, sizeof(double) * kTab * n), "hipMalloc(tables)");
     if (!st) st = bhip(b, hipMalloc(&b->d_wtabs, sizeof(int32_t) * wsize * n), "hipMalloc(weights)");
     if (!st) st = bhip(b, hipMalloc(&b->d_counts, sizeof(unsigned long long) * kMaxS * kMaxK * kMaxK), "hipMalloc");
@@ -142,7 +142,7 @@ smcx_status smcx_batch_create(int32_t n, const smcx_desc* descs, const uint8_t* 
         const size_t N = n_sites(d.lattice, d.L);
         st = bhip(b, hipMemcpy(b->d_species + off[r], species[r], N, hipMemcpyHostToDevice), "hipMemcpy(lattice)");
         if (st) break;
-        build_wtab(epi[r], d.n_species, d.n_shells, kmax, smax, wtab_bias(d.lattice, kmax), w.data());
+        const int drop = build_wtab(epi[r], d.n_species, d.n_shells, kmax, smax, wtab_bias(d.lattice, kmax), w.data());
         st = bhip(b, hipMemcpy(b->d_wtabs + wsize * r, w.data(), sizeof(int32_t) * wsize, hipMemcpyHostToDevice),
                   "hipMemcpy(weights)");
         if (!st) st = upload_table(b, r);
@@ -153,8 +153,8 @@ smcx_status smcx_batch_create(int32_t n, const smcx_desc* descs, const uint8_t* 
         L.species = b->d_species + off[r];
         L.tabs = b->d_tabs + (size_t)r * kTab;
         L.wtab = b->d_wtabs + wsize * r;
-        L.energy = b->d_states + 2 * r;
-        L.accepted = (unsigned long long*)(b->d_states + 2 * r + 1);
+        L.drop_last = drop;
+        L.state = b->d_states + (size_t)kStateWords * r;
         L.sweep0 = 0;
         L.tab_s0 = 0;
         L.n_tabs = 1;
@@ -178,7 +178,7 @@ smcx_status smcx_batch_create(int32_t n, const smcx_desc* descs, const uint8_t* 
         v->stream = b->stream;
         v->h_lat = L;
         v->d_lat = b->d_lats + r;
-        v->d_state = b->d_states + 2 * r;
+        v->d_state = b->d_states + (size_t)kStateWords * r;
         v->d_counts = b->d_counts;
         v->d_wtab = nullptr;   // owned by the batch
         v->T_default = T[r];
@@ -198,8 +198,8 @@ smcx_status smcx_batch_create(int32_t n, const smcx_desc* descs, const uint8_t* 
         int64_t E0 = 0;
         st = recompute_energy(b->views[r], &E0);
         if (st) { b->err = b->views[r]->err; break; }
-        int64_t init[2] = {E0, 0};
-        st = bhip(b, hipMemcpy(b->d_states + 2 * r, init, sizeof(init), hipMemcpyHostToDevice), "hipMemcpy(state)");
+        st = write_state(b->views[r], E0, 0);
+        if (st) { b->err = b->views[r]->err; break; }
     }
     if (st) { batch_free(b); delete b; return st; }
     *out = b;
@@ -335,10 +335,14 @@ smcx_status smcx_batch_exchange(smcx_batch* b, const int32_t* a, const int32_t* 
     }
     smcx_status st = bhip(b, hipStreamSynchronize(b->stream), "hipStreamSynchronize");
     if (st) return st;
-    std::vector<int64_t> states(2 * (size_t)b->n);
-    st = bhip(b, hipMemcpy(states.data(), b->d_states, sizeof(int64_t) * states.size(), hipMemcpyDeviceToHost),
+    std::vector<int64_t> image((size_t)kStateWords * b->n), states(2 * (size_t)b->n);
+    st = bhip(b, hipMemcpy(image.data(), b->d_states, sizeof(int64_t) * image.size(), hipMemcpyDeviceToHost),
               "hipMemcpy(states)");
     if (st) return st;
+    for (int r = 0; r < b->n; ++r) {
+        uint64_t acc = 0;
+        state_sum(image.data() + (size_t)kStateWords * r, &states[2 * (size_t)r], &acc);
+    }
     const double kB = 86.17333262;   // micro-eV / K
     for (int k = 0; k < n_pairs; ++k) {
         const int x = a[k], y = bb[k];

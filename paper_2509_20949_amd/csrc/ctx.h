@@ -47,5 +47,8 @@ smcx_status ctx_hip(smcx_ctx* c, hipError_t e, const char* what);
 void fill_geometry(DevLattice& L, const smcx_desc* d, const int32_t B[3]);
 bool geometry_ok(const DevLattice& L);
 smcx_status recompute_energy(smcx_ctx* c, int64_t* E);
+// Running energy / accepted count of a context (sums over the state slots).
+smcx_status read_state(smcx_ctx* c, int64_t* E, uint64_t* accepted);
+smcx_status write_state(smcx_ctx* c, int64_t E, uint64_t accepted);
 void ctx_release(smcx_ctx* c);
 }  // namespace smcx

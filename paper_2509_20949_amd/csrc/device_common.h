@@ -27,6 +27,31 @@ __device__ __forceinline__ void lane_cell(int lane, int& ix, int& iy, int& iz)
     iz = (lane >> 3) & 3;
 }
 
+// An empty asm on the accumulator keeps the counting chain sequential:
+// otherwise the adds are reassociated into a tree, and each shift then needs
+// its own mask and instruction instead of one shift-add.
+__device__ __forceinline__ void keep(uint32_t& h) { asm("" : "+v"(h)); }
+
+// LDS form of the pair-weight table: entry f of row (a, b) (f = s*KMAX + p
+// for a weight, SMAX*KMAX for the constant) sits in plane f at position
+// a*KMAX + b, planes wplane(KMAX) dwords apart.  The lanes of a wave read one
+// plane per instruction, each at its own row: distinct rows fall in distinct
+// 4-byte banks, equal rows broadcast (a row-per-lane layout made most lanes
+// collide, its rows all starting on the same few banks).
+constexpr int wplane(int kmax) { return ((kmax * kmax + 31) / 32) * 32; }
+constexpr int wplanes(int kmax, int smax) { return smax * kmax + 1; }
+
+// Fill the LDS planes from the row-major table of wrow(KMAX, SMAX) ints per row.
+template <int KMAX, int SMAX>
+__device__ __forceinline__ void load_wplanes(int32_t* s_w, const int32_t* wtab)
+{
+    constexpr int PS = wplane(KMAX), WR = wrow(KMAX, SMAX);
+    for (int k = threadIdx.x; k < wplanes(KMAX, SMAX) * PS; k += blockDim.x) {
+        const int f = k / PS, row = k - f * PS;
+        s_w[k] = row < KMAX * KMAX ? wtab[row * WR + f] : 0;
+    }
+}
+
 __device__ __forceinline__ int wrap_add(int v, int L)   // v in [-L, 2L)
 {
     v = v < 0 ? v + L : v;

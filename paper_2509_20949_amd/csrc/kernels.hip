@@ -11,6 +11,8 @@
 //   program order, so no barrier separates the rounds.
 // pair_counts: N_m[p'][p] for energy recomputation and Warren-Cowley SRO
 //   (Eq. (SRO)).
+#include <type_traits>
+
 #include "device_common.h"
 
 namespace smcx {
@@ -53,29 +55,44 @@ __device__ __forceinline__ constexpr int s3off(int k)
 }
 
 // Packed species histogram of the neighbours of the site at LDS byte `a`
-// with sublattice SUB, one 32-bit word per shell.
+// with sublattice SUB, one 32-bit word per shell, added to h.  Each shell is
+// summed in a few short chains of shift-adds (kept apart by keep(), so each
+// step stays one v_lshl_add) that are joined at the end: short dependency
+// chains for latency, one instruction per neighbour for throughput.
 template <int SMAX, int SUB>
 __device__ __forceinline__ void histogram(const uint8_t* lat, int a, uint32_t (&h)[kMaxS])
 {
     const int b1 = a + s1base<SUB>();
+    uint32_t p0 = h[0], p1 = 0u;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const uint32_t c = lat[b1 + (e & 1) + ((e >> 1) & 1) * kP + ((e >> 2) & 1) * kPP];
-        h[0] += 1u << (c & 31);
+        uint32_t& acc = (e & 1) ? p1 : p0;
+        acc += 1u << (c & 31);
+        keep(acc);
     }
+    h[0] = p0 + p1;
     if constexpr (SMAX >= 2) {
+        uint32_t q0 = h[1], q1 = 0u;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             const uint32_t c = lat[a + s2off(k)];
-            h[1] += 1u << (c & 31);
+            uint32_t& acc = (k & 1) ? q1 : q0;
+            acc += 1u << (c & 31);
+            keep(acc);
         }
+        h[1] = q0 + q1;
     }
     if constexpr (SMAX >= 3) {
+        uint32_t r0 = h[2], r1 = 0u, r2 = 0u;
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             const uint32_t c = lat[a + s3off(k)];
-            h[2] += 1u << (c & 31);
+            uint32_t& acc = (k % 3 == 0) ? r0 : ((k % 3 == 1) ? r1 : r2);
+            acc += 1u << (c & 31);
+            keep(acc);
         }
+        h[2] = r0 + r1 + r2;
     }
 }
 
@@ -84,13 +101,39 @@ __device__ __forceinline__ void histogram(const uint8_t* lat, int a, uint32_t (&
 // whose y and z steps (shared by the whole round) give yz = ey*kP + ez*kPP;
 // the acceptance draw is u << 1.  Returns through dEsum / nacc; updates the
 // LDS image in place.
-template <int KMAX, int SMAX, int SUB>
+// acc + sum over shells s < SMAX and fields p < NF of field(s, p) * w[s*KMAX + p],
+// modulo 2^32: field = bias + n_i - n_j read from the packed difference
+// (F = 5), or n_i - n_j from the two 4-bit fields (F = 4).  The constant may
+// leave the int32 range for extreme tables while the true dE (|dE| < 2^29)
+// never does: the 32-bit multiply-adds wrap, and the wrapped sum is exact.
+template <int KMAX, int SMAX, int NF>
+__device__ __forceinline__ uint32_t weigh(const uint32_t (&hi)[kMaxS], const uint32_t (&hj)[kMaxS],
+                                          const int32_t* w, uint32_t acc)
+{
+    constexpr int PS = wplane(KMAX);
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) {
+        if constexpr (Field<KMAX>::F == 5) {
+            const uint32_t d = hi[s] - hj[s];   // fields 16 + n_i - n_j, no borrows
+#pragma unroll
+            for (int p = 0; p < NF; ++p)
+                acc = mad24((d >> (5 * p)) & 31u, w[(s * KMAX + p) * PS], acc);
+        } else {
+#pragma unroll
+            for (int p = 0; p < NF; ++p)
+                acc = mad24((uint32_t)((int32_t)((hi[s] >> (4 * p)) & 15u) - (int32_t)((hj[s] >> (4 * p)) & 15u)),
+                            w[(s * KMAX + p) * PS], acc);
+        }
+    }
+    return acc;
+}
+
+template <int KMAX, int SMAX, int SUB, bool DROP>
 __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int yz, bool valid,
                                       const int32_t* wtab, const double* tab, int64_t& dEsum,
                                       uint32_t& nacc)
 {
     constexpr int F = Field<KMAX>::F;
-    constexpr int WR = wrow(KMAX, SMAX);
     const uint32_t u_acc = u << 1;
     const int aj = ai + s1base<SUB>() + (int)(u >> 31) + yz;
     const uint32_t ci = lat[ai];
@@ -108,25 +151,11 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int yz, 
     // lanes without a site in this round may decode stale halo bytes: clamp
     // the row index into the table (their result is discarded)
     const uint32_t a = min(decode(ci), (uint32_t)(KMAX - 1)), b = min(decode(cj), (uint32_t)(KMAX - 1));
-    const int32_t* w = wtab + (a * KMAX + b) * WR;
-    // The constant may leave the int32 range for extreme tables while the
-    // true dE (|dE| < 2^29) never does: the 32-bit multiply-adds wrap, and
-    // the wrapped sum is exact.
-    uint32_t acc = (uint32_t)w[SMAX * KMAX];
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s) {
-        if constexpr (F == 5) {
-            const uint32_t d = hi[s] - hj[s];   // fields 16 + n_i - n_j, no borrows
-#pragma unroll
-            for (int p = 0; p < KMAX; ++p)
-                acc = mad24((d >> (5 * p)) & 31u, w[s * KMAX + p], acc);
-        } else {
-#pragma unroll
-            for (int p = 0; p < KMAX; ++p)
-                acc = mad24((uint32_t)((int32_t)((hi[s] >> (4 * p)) & 15u) - (int32_t)((hj[s] >> (4 * p)) & 15u)),
-                            w[s * KMAX + p], acc);
-        }
-    }
+    const int32_t* w = wtab + (a * KMAX + b);   // row (a, b) of the weight planes
+    // With DROP the rows fold in the last species, whose count differences
+    // follow from the others (both sites have the same number of neighbours
+    // per shell): only fields 0 .. KMAX-2 are read.
+    const uint32_t acc = weigh<KMAX, SMAX, DROP ? KMAX - 1 : KMAX>(hi, hj, w, (uint32_t)w[SMAX * KMAX * wplane(KMAX)]);
     const int32_t dE = (int32_t)acc;
 
     // Metropolis decision, Eq. (3), on the FP64 byte tables.
@@ -150,9 +179,8 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
                         int t, int colour)
 {
     constexpr int F = Field<KMAX>::F;
-    constexpr int WR = wrow(KMAX, SMAX);
     __shared__ double s_tab[kTab];
-    __shared__ int32_t s_w[KMAX * KMAX * WR];
+    __shared__ int32_t s_w[wplanes(KMAX, SMAX) * wplane(KMAX)];
     __shared__ __attribute__((aligned(16))) uint8_t s_lat[kWavesPerGroup * kWaveLds];
 
     const int wave = threadIdx.x / kWave;
@@ -171,7 +199,7 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
         ti = ti < 0 ? 0 : (ti >= D.n_tabs ? D.n_tabs - 1 : ti);
         const double* tab = D.tabs + (size_t)ti * kTab;
         for (int k = threadIdx.x; k < kTab; k += blockDim.x) s_tab[k] = tab[k];
-        for (int k = threadIdx.x; k < KMAX * KMAX * WR; k += blockDim.x) s_w[k] = D.wtab[k];
+        load_wplanes<KMAX, SMAX>(s_w, D.wtab);
     }
     __syncthreads();
 
@@ -311,33 +339,42 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
     }
     int64_t dEsum = 0;
     uint32_t nacc = 0;
-    // rounds of residue class m (corner then body) with draws uc, ub and the
-    // four partner bits of sub-colours 2m, 2m+1 in b4
-    auto rounds = [&](int m, uint32_t uc, uint32_t ub, uint32_t b4) {
-        const int rx = m % 3, ry = (m / 3) % 3, rz = m / 9;
-        const bool valid = (3 * ix < wx - rx) & (3 * iy < wy - ry) & (3 * iz < wz - rz);
-        const int ac = lane_c + (rz * kPP + ry * kP + rx);
-        const int yz0 = (int)(b4 & 1u) * kP + (int)((b4 >> 1) & 1u) * kPP;
-        const int yz1 = (int)((b4 >> 2) & 1u) * kP + (int)((b4 >> 3) & 1u) * kPP;
-        trial<KMAX, SMAX, 0>(lat, ac, uc, yz0, valid, s_w, s_tab, dEsum, nacc);
-        __builtin_amdgcn_wave_barrier();
-        trial<KMAX, SMAX, 1>(lat, ac + kBodyFromCorner, ub, yz1, valid, s_w, s_tab, dEsum, nacc);
-        __builtin_amdgcn_wave_barrier();
-    };
-    uint32_t w[4] = {base_lo, base_hi, s, (uint32_t)colour};
-    philox4x32_10(w, k0, k1);
-    for (int k = 0; k < 13; ++k) {
-        const uint32_t u0 = w[0], u1 = w[1], u2 = w[2], u3 = w[3];
-        // the next pair's call, issued ahead of this pair's LDS traffic (same
-        // basic block, so the scheduler can interleave the two)
-        w[0] = base_lo; w[1] = base_hi; w[2] = s; w[3] = (uint32_t)colour + 256u * (uint32_t)(k + 1);
+    // The rounds, instantiated for folded (DROP) or full weight rows: the
+    // choice is per lattice, so each instance stays branch-free.
+    auto all_rounds = [&](auto drop_tag) {
+        constexpr bool DROP = decltype(drop_tag)::value;
+        // rounds of residue class m (corner then body) with draws uc, ub and
+        // the four partner bits of sub-colours 2m, 2m+1 in b4
+        auto rounds = [&](int m, uint32_t uc, uint32_t ub, uint32_t b4) {
+            const int rx = m % 3, ry = (m / 3) % 3, rz = m / 9;
+            const bool valid = (3 * ix < wx - rx) & (3 * iy < wy - ry) & (3 * iz < wz - rz);
+            const int ac = lane_c + (rz * kPP + ry * kP + rx);
+            const int yz0 = (int)(b4 & 1u) * kP + (int)((b4 >> 1) & 1u) * kPP;
+            const int yz1 = (int)((b4 >> 2) & 1u) * kP + (int)((b4 >> 3) & 1u) * kPP;
+            trial<KMAX, SMAX, 0, DROP>(lat, ac, uc, yz0, valid, s_w, s_tab, dEsum, nacc);
+            __builtin_amdgcn_wave_barrier();
+            trial<KMAX, SMAX, 1, DROP>(lat, ac + kBodyFromCorner, ub, yz1, valid, s_w, s_tab, dEsum, nacc);
+            __builtin_amdgcn_wave_barrier();
+        };
+        uint32_t w[4] = {base_lo, base_hi, s, (uint32_t)colour};
         philox4x32_10(w, k0, k1);
-        // partner bits of sub-colours 4k .. 4k+3: bits 8k .. 8k+7
-        const uint32_t bits = (uint32_t)(8 * k < 64 ? yz_lo >> (8 * k) : yz_hi >> (8 * k - 64));
-        rounds(2 * k, u0, u1, bits);
-        rounds(2 * k + 1, u2, u3, bits >> 4);
-    }
-    rounds(26, w[0], w[1], (uint32_t)(yz_hi >> 40));   // bits 104 .. 107
+        for (int k = 0; k < 13; ++k) {
+            const uint32_t u0 = w[0], u1 = w[1], u2 = w[2], u3 = w[3];
+            // the next pair's call, issued ahead of this pair's LDS traffic
+            // (same basic block, so the scheduler can interleave the two)
+            w[0] = base_lo; w[1] = base_hi; w[2] = s; w[3] = (uint32_t)colour + 256u * (uint32_t)(k + 1);
+            philox4x32_10(w, k0, k1);
+            // partner bits of sub-colours 4k .. 4k+3: bits 8k .. 8k+7
+            const uint32_t bits = (uint32_t)(8 * k < 64 ? yz_lo >> (8 * k) : yz_hi >> (8 * k - 64));
+            rounds(2 * k, u0, u1, bits);
+            rounds(2 * k + 1, u2, u3, bits >> 4);
+        }
+        rounds(26, w[0], w[1], (uint32_t)(yz_hi >> 40));   // bits 104 .. 107
+    };
+    if (D.drop_last)
+        all_rounds(std::integral_constant<bool, true>{});
+    else
+        all_rounds(std::integral_constant<bool, false>{});
 
     // ---- write back: corner cells 0..w, body cells -1..w-1 ----
     // Fast path (no periodic wrap along x): 8 lanes per row, each owning one
@@ -429,8 +466,9 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
         cnt += __shfl_xor(cnt, o, kWave);
     }
     if (lane == 0) {
-        if (sum) atomicAdd((unsigned long long*)D.energy, (unsigned long long)sum);
-        if (cnt) atomicAdd(D.accepted, (unsigned long long)cnt);
+        unsigned long long* slot = (unsigned long long*)(D.state + (f % kSpread) * kSlotWords);
+        if (sum) atomicAdd(slot, (unsigned long long)sum);
+        if (cnt) atomicAdd(slot + 1, (unsigned long long)cnt);
     }
 }
 

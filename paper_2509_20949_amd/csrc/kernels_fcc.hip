@@ -79,14 +79,14 @@ __device__ __forceinline__ void histogram(const uint8_t* lat, int a, uint32_t (&
 {
     constexpr Offsets O = Off<B>::v;
 #pragma unroll
-    for (int k = 0; k < 12; ++k) h[0] += 1u << (lat[a + O.s1[k]] & 31u);
+    for (int k = 0; k < 12; ++k) { h[0] += 1u << (lat[a + O.s1[k]] & 31u); keep(h[0]); }
     if constexpr (SMAX >= 2) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) h[1] += 1u << (lat[a + O.s2[k]] & 31u);
+        for (int k = 0; k < 6; ++k) { h[1] += 1u << (lat[a + O.s2[k]] & 31u); keep(h[1]); }
     }
     if constexpr (SMAX >= 3) {
 #pragma unroll
-        for (int k = 0; k < 24; ++k) h[2] += 1u << (lat[a + O.s3[k]] & 31u);
+        for (int k = 0; k < 24; ++k) { h[2] += 1u << (lat[a + O.s3[k]] & 31u); keep(h[2]); }
     }
 }
 
@@ -97,10 +97,10 @@ constexpr int KMAXF = 5;
 constexpr uint32_t kBias = 32u * (1u | 1u << 6 | 1u << 12 | 1u << 18 | 1u << 24);
 
 template <int SMAX, int B, int BP>
-__device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u_dir, uint32_t u_acc, bool valid,
+__device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u_dir, uint32_t u_acc, bool valid, bool drop,
                                       const int32_t* wtab, const double* tab, int64_t& dEsum, uint32_t& nacc)
 {
-    constexpr int WR = wrow(KMAXF, SMAX);
+    constexpr int PS = wplane(KMAXF);
     constexpr int a1 = axis1(B, BP), a2 = axis2(B, BP);
     const int bit1 = (int)((u_dir >> 30) & 1u), bit2 = (int)(u_dir >> 31);
     const int aj = ai + (BP - B) * kArr + (SUB[BP][a1] - 1 + bit1) * stride(a1) + (SUB[BP][a2] - 1 + bit2) * stride(a2);
@@ -112,13 +112,24 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u_dir, uint
     histogram<SMAX, B>(lat, ai, hi);
     histogram<SMAX, BP>(lat, aj, hj);
     const uint32_t a = min(decode(ci), (uint32_t)(KMAXF - 1)), b = min(decode(cj), (uint32_t)(KMAXF - 1));
-    const int32_t* w = wtab + (a * KMAXF + b) * WR;
-    uint32_t acc = (uint32_t)w[SMAX * KMAXF];
+    const int32_t* w = wtab + (a * KMAXF + b);   // row (a, b) of the weight planes
+    // drop (wave-uniform): the rows fold in the last species, whose count
+    // differences follow from the others; only fields 0 .. KMAXF-2 are read
+    uint32_t acc = (uint32_t)w[SMAX * KMAXF * PS];
+    if (drop) {
 #pragma unroll
-    for (int s = 0; s < SMAX; ++s) {
-        const uint32_t d = hi[s] - hj[s];
+        for (int s = 0; s < SMAX; ++s) {
+            const uint32_t d = hi[s] - hj[s];
 #pragma unroll
-        for (int p = 0; p < KMAXF; ++p) acc = mad24((d >> (F * p)) & 63u, w[s * KMAXF + p], acc);
+            for (int p = 0; p < KMAXF - 1; ++p) acc = mad24((d >> (F * p)) & 63u, w[(s * KMAXF + p) * PS], acc);
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) {
+            const uint32_t d = hi[s] - hj[s];
+#pragma unroll
+            for (int p = 0; p < KMAXF; ++p) acc = mad24((d >> (F * p)) & 63u, w[(s * KMAXF + p) * PS], acc);
+        }
     }
     const int32_t dE = (int32_t)acc;
     const int e = dE < 1 ? 1 : (dE > (1 << 24) - 1 ? (1 << 24) - 1 : dE);
@@ -134,13 +145,13 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u_dir, uint
 
 // Partner sublattice BP (a wave-uniform value) selects one instantiation.
 template <int SMAX, int B>
-__device__ __forceinline__ void trial_any(int bp, uint8_t* lat, int ai, uint32_t u_dir, uint32_t u_acc, bool valid,
+__device__ __forceinline__ void trial_any(int bp, uint8_t* lat, int ai, uint32_t u_dir, uint32_t u_acc, bool valid, bool drop,
                                           const int32_t* wtab, const double* tab, int64_t& dEsum, uint32_t& nacc)
 {
-    if constexpr (B != 0) { if (bp == 0) { trial<SMAX, B, 0>(lat, ai, u_dir, u_acc, valid, wtab, tab, dEsum, nacc); return; } }
-    if constexpr (B != 1) { if (bp == 1) { trial<SMAX, B, 1>(lat, ai, u_dir, u_acc, valid, wtab, tab, dEsum, nacc); return; } }
-    if constexpr (B != 2) { if (bp == 2) { trial<SMAX, B, 2>(lat, ai, u_dir, u_acc, valid, wtab, tab, dEsum, nacc); return; } }
-    if constexpr (B != 3) { if (bp == 3) { trial<SMAX, B, 3>(lat, ai, u_dir, u_acc, valid, wtab, tab, dEsum, nacc); return; } }
+    if constexpr (B != 0) { if (bp == 0) { trial<SMAX, B, 0>(lat, ai, u_dir, u_acc, valid, drop, wtab, tab, dEsum, nacc); return; } }
+    if constexpr (B != 1) { if (bp == 1) { trial<SMAX, B, 1>(lat, ai, u_dir, u_acc, valid, drop, wtab, tab, dEsum, nacc); return; } }
+    if constexpr (B != 2) { if (bp == 2) { trial<SMAX, B, 2>(lat, ai, u_dir, u_acc, valid, drop, wtab, tab, dEsum, nacc); return; } }
+    if constexpr (B != 3) { if (bp == 3) { trial<SMAX, B, 3>(lat, ai, u_dir, u_acc, valid, drop, wtab, tab, dEsum, nacc); return; } }
 }
 
 template <int B>
@@ -178,9 +189,8 @@ void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem*
                             int colour)
 {
     using namespace fcc;
-    constexpr int WR = wrow(KMAXF, SMAX);
     __shared__ double s_tab[kTab];
-    __shared__ int32_t s_w[KMAXF * KMAXF * WR];
+    __shared__ int32_t s_w[wplanes(KMAXF, SMAX) * wplane(KMAXF)];
     __shared__ __attribute__((aligned(16))) uint8_t s_lat[kWavesPerGroup * kWaveLdsF];
 
     const int wave = threadIdx.x / kWave;
@@ -197,7 +207,7 @@ void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem*
         ti = ti < 0 ? 0 : (ti >= D.n_tabs ? D.n_tabs - 1 : ti);
         const double* tab = D.tabs + (size_t)ti * kTab;
         for (int k = threadIdx.x; k < kTab; k += blockDim.x) s_tab[k] = tab[k];
-        for (int k = threadIdx.x; k < KMAXF * KMAXF * WR; k += blockDim.x) s_w[k] = D.wtab[k];
+        load_wplanes<KMAXF, SMAX>(s_w, D.wtab);
     }
     __syncthreads();
     f += wave;
@@ -261,6 +271,7 @@ void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem*
     const bool narrow = LxLy < (1u << 24) && (uint64_t)LxLy * (uint32_t)Lz < (1ull << 32);
     int64_t dEsum = 0;
     uint32_t nacc = 0;
+    const bool drop = D.drop_last != 0;
     for (int m = 0; m < 27; ++m) {
         const int rx = m % 3, ry = (m / 3) % 3, rz = m / 9;
         const int lx = rx + 3 * ix, ly = ry + 3 * iy, lz = rz + 3 * iz;
@@ -280,16 +291,16 @@ void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem*
         philox4x32_10(rb, k0, k1);
         const int q0 = 4 * m;
         int bp = __builtin_amdgcn_readfirstlane(lat[kBpOff + q0]);
-        trial_any<SMAX, 0>(bp, lat, site_addr<0>(lx, ly, lz), ra[0], ra[1], valid, s_w, s_tab, dEsum, nacc);
+        trial_any<SMAX, 0>(bp, lat, site_addr<0>(lx, ly, lz), ra[0], ra[1], valid, drop, s_w, s_tab, dEsum, nacc);
         __builtin_amdgcn_wave_barrier();
         bp = __builtin_amdgcn_readfirstlane(lat[kBpOff + q0 + 1]);
-        trial_any<SMAX, 1>(bp, lat, site_addr<1>(lx, ly, lz), ra[2], ra[3], valid, s_w, s_tab, dEsum, nacc);
+        trial_any<SMAX, 1>(bp, lat, site_addr<1>(lx, ly, lz), ra[2], ra[3], valid, drop, s_w, s_tab, dEsum, nacc);
         __builtin_amdgcn_wave_barrier();
         bp = __builtin_amdgcn_readfirstlane(lat[kBpOff + q0 + 2]);
-        trial_any<SMAX, 2>(bp, lat, site_addr<2>(lx, ly, lz), rb[0], rb[1], valid, s_w, s_tab, dEsum, nacc);
+        trial_any<SMAX, 2>(bp, lat, site_addr<2>(lx, ly, lz), rb[0], rb[1], valid, drop, s_w, s_tab, dEsum, nacc);
         __builtin_amdgcn_wave_barrier();
         bp = __builtin_amdgcn_readfirstlane(lat[kBpOff + q0 + 3]);
-        trial_any<SMAX, 3>(bp, lat, site_addr<3>(lx, ly, lz), rb[2], rb[3], valid, s_w, s_tab, dEsum, nacc);
+        trial_any<SMAX, 3>(bp, lat, site_addr<3>(lx, ly, lz), rb[2], rb[3], valid, drop, s_w, s_tab, dEsum, nacc);
         __builtin_amdgcn_wave_barrier();
     }
 
@@ -331,8 +342,9 @@ void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem*
         cnt += __shfl_xor(cnt, o, kWave);
     }
     if (lane == 0) {
-        if (sum) atomicAdd((unsigned long long*)D.energy, (unsigned long long)sum);
-        if (cnt) atomicAdd(D.accepted, (unsigned long long)cnt);
+        unsigned long long* slot = (unsigned long long*)(D.state + (f % kSpread) * kSlotWords);
+        if (sum) atomicAdd(slot, (unsigned long long)sum);
+        if (cnt) atomicAdd(slot + 1, (unsigned long long)cnt);
     }
 }
 

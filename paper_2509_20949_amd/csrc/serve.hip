@@ -65,7 +65,7 @@ struct smcx_server {
     int max_slots = 0, sweeps_per_step = 1;
     hipStream_t stream = nullptr;
     DevLattice* d_lats = nullptr;            // one entry per slot
-    int64_t* d_states = nullptr;             // [slot][2]
+    int64_t* d_states = nullptr;             // [slot][kStateWords]
     unsigned long long* d_counts = nullptr;
     WorkItem* d_items = nullptr;
     size_t items_cap = 0;
@@ -138,8 +138,8 @@ smcx_status admit(smcx_server* s, Request* q)
     double tab[kTab];
     build_thresholds(q->T, tab);
     std::vector<int32_t> w((size_t)q->kmax * q->kmax * wrow(q->kmax, q->smax));
-    build_wtab(q->epi.data(), q->desc.n_species, q->desc.n_shells, q->kmax, q->smax,
-               wtab_bias(q->desc.lattice, q->kmax), w.data());
+    const int drop = build_wtab(q->epi.data(), q->desc.n_species, q->desc.n_shells, q->kmax, q->smax,
+                                wtab_bias(q->desc.lattice, q->kmax), w.data());
     st = shipc(s, hipMemcpy(q->d_mem, q->species.data(), N, hipMemcpyHostToDevice), "hipMemcpy(lattice)");
     if (!st) st = shipc(s, hipMemcpy(q->d_mem + off_tab, tab, sizeof(tab), hipMemcpyHostToDevice), "hipMemcpy(table)");
     if (!st) st = shipc(s, hipMemcpy(q->d_mem + off_w, w.data(), sizeof(int32_t) * w.size(), hipMemcpyHostToDevice),
@@ -151,15 +151,17 @@ smcx_status admit(smcx_server* s, Request* q)
     L.species = q->d_mem;
     L.tabs = (const double*)(q->d_mem + off_tab);
     L.wtab = (const int32_t*)(q->d_mem + off_w);
-    L.energy = s->d_states + 2 * q->slot;
-    L.accepted = (unsigned long long*)(s->d_states + 2 * q->slot + 1);
+    L.drop_last = drop;
+    L.state = s->d_states + (size_t)kStateWords * q->slot;
     L.n_tabs = 1;
     q->groups = (L.blocks_per_colour + kWavesPerGroup - 1) / kWavesPerGroup;
     int64_t E0 = 0;
     st = initial_energy(s, q, &E0);
     if (st) return st;
-    int64_t init[2] = {E0, 0};
-    st = shipc(s, hipMemcpy(s->d_states + 2 * q->slot, init, sizeof(init), hipMemcpyHostToDevice), "hipMemcpy(state)");
+    std::vector<int64_t> init(kStateWords);
+    state_init(init.data(), E0, 0);
+    st = shipc(s, hipMemcpy(s->d_states + (size_t)kStateWords * q->slot, init.data(), sizeof(int64_t) * kStateWords,
+                            hipMemcpyHostToDevice), "hipMemcpy(state)");
     if (st) return st;
     q->species.clear();
     q->species.shrink_to_fit();
@@ -192,7 +194,7 @@ smcx_status smcx_server_create(size_t budget, int32_t max_slots, int32_t sweeps_
     if (const char* f = std::getenv("SMCX_FAULT_REQUEST")) s->fault_id = std::strtoull(f, nullptr, 10);
     smcx_status st = shipc(s, hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), "hipStreamCreate");
     if (!st) st = shipc(s, hipMalloc(&s->d_lats, sizeof(DevLattice) * max_slots), "hipMalloc(descriptors)");
-    if (!st) st = shipc(s, hipMalloc(&s->d_states, sizeof(int64_t) * 2 * max_slots), "hipMalloc(states)");
+    if (!st) st = shipc(s, hipMalloc(&s->d_states, sizeof(int64_t) * kStateWords * max_slots), "hipMalloc(states)");
     if (!st) st = shipc(s, hipMalloc(&s->d_counts, sizeof(unsigned long long) * kMaxS * kMaxK * kMaxK), "hipMalloc");
     if (st) {
         smcx_server_destroy(s);
@@ -325,15 +327,15 @@ smcx_status smcx_server_step(smcx_server* s, int32_t* n_resident, int32_t* n_wai
         if (q->done < q->n_sweeps) { ++it; continue; }
         const size_t N = n_sites(q->desc.lattice, q->desc.L);
         q->config.resize(N);
-        int64_t st2[2];
+        std::vector<int64_t> st2(kStateWords);
         smcx_status st = shipc(s, hipMemcpy(q->config.data(), q->lat.species, N, hipMemcpyDeviceToHost), "hipMemcpy");
-        if (!st) st = shipc(s, hipMemcpy(st2, s->d_states + 2 * q->slot, sizeof(st2), hipMemcpyDeviceToHost), "hipMemcpy");
+        if (!st) st = shipc(s, hipMemcpy(st2.data(), s->d_states + (size_t)kStateWords * q->slot,
+                                         sizeof(int64_t) * kStateWords, hipMemcpyDeviceToHost), "hipMemcpy");
         if (st) {
             q->state = FAILED;
             q->err = s->err;
         } else {
-            q->E = st2[0];
-            q->accepted = (uint64_t)st2[1];
+            state_sum(st2.data(), &q->E, &q->accepted);
             q->state = FINISHED;
             ++finished_now;
         }

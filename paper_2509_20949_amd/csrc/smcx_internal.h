@@ -36,13 +36,24 @@ constexpr int kTab = 768;
 // W[s][p] = V_s(b, p) - V_s(a, p) for s < SMAX, p < KMAX, then a constant.
 __host__ __device__ constexpr int wrow(int kmax, int smax) { return ((smax * kmax + 1) + 3) & ~3; }
 
+// Running energy (micro-eV, int64) and accepted-swap count (uint64) of one
+// lattice, spread over kSpread slots one cache line apart: the wave of block
+// f adds its totals to slot f % kSpread, so one launch's thousands of
+// device-scope atomics do not all meet on a single address (they serialise
+// there).  The values are the sums over the slots; state_init/state_sum
+// (tables.cpp) write and read the host image.
+constexpr int kSpread = 128;
+constexpr int kSlotWords = 8;                        // 64 bytes per slot: energy, accepted, padding
+constexpr int kStateWords = kSpread * kSlotWords;    // int64 words per lattice
+void state_init(int64_t* h /* kStateWords */, int64_t E, uint64_t accepted);
+void state_sum(const int64_t* h /* kStateWords */, int64_t* E, uint64_t* accepted);
+
 // Per-lattice state the kernels read (device memory).
 struct DevLattice {
     uint8_t* species;        // 2*Lx*Ly*Lz bytes, canonical order
     const double* tabs;      // n_tabs x 768 thresholds
     const int32_t* wtab;     // KMAX*KMAX rows of wrow(KMAX, SMAX) ints
-    int64_t* energy;         // running energy (micro-eV)
-    unsigned long long* accepted;
+    int64_t* state;          // running energy and accepted count, kStateWords words (see below)
     int32_t L[3];
     int32_t nb[3];           // blocks per axis (even)
     uint32_t key[2];
@@ -52,6 +63,7 @@ struct DevLattice {
     int32_t K;
     int32_t blocks_per_colour;
     int32_t lattice;         // 0 BCC, 1 FCC
+    int32_t drop_last;       // 1: weight rows fold in the last species (fields 0..KMAX-2 read)
 };
 
 // One workgroup's share of a batched phase: kWavesPerGroup consecutive
@@ -106,8 +118,9 @@ __host__ __device__ inline int axis_blocks(int L, int B)
 // Host helpers (tables.cpp).
 void build_thresholds(double T, double* out768);
 // bias: the per-field offset the kernel packs into its histogram words
-// (16 for BCC with K <= 6, 0 for BCC with K <= 8, 32 for FCC).
-void build_wtab(const int32_t* epi, int K, int S, int kmax, int smax, int bias, int32_t* out);
+// (16 for BCC with K <= 6, 0 for BCC with K <= 8, 32 for FCC).  Returns the
+// value of DevLattice::drop_last the rows are built for.
+int build_wtab(const int32_t* epi, int K, int S, int kmax, int smax, int bias, int32_t* out);
 
 // Launchers (kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_sweep_phase(int lattice, const DevLattice* d_lat, const WorkItem* d_items, int n_groups,
