@@ -46,6 +46,25 @@ OPS_PER_TRIAL = 25 + 52 + 33 + 8          # = 118
 # once per sweep (uint8 species).
 BYTES_PER_TRIAL = 2
 
+# HBM traffic of one colour launch on the 512^3 lattice, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE scaled by the same counters on a 1 GiB copy
+# (profiles/sweep_phase_bcc512_k5s3_hbm_counters.md).  It describes the
+# kernel built from the sources with this SHA-256 only; for other sources
+# the bench reports traffic as null.
+MEASURED_TRAFFIC = {"sources_sha256": "6f5a91e7dc3fc8852dd7fb73e6051c892e4fa8a3041d1241ee8ba4ba0d91ee15",
+                    "bytes_per_launch": 307851198}
+KERNEL_SOURCES = ("paper_2509_20949_amd/csrc/kernels.hip", "paper_2509_20949_amd/csrc/device_common.h",
+                  "paper_2509_20949_amd/csrc/smcx_internal.h")
+
+
+def kernel_sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
 
 def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -282,6 +301,9 @@ def main():
     comp_ok = bool(np.array_equal(np.bincount(cfg, minlength=job.K), np.bincount(job.sigma, minlength=job.K)))
     lat.close()
 
+    traffic = None
+    if args.L == 512 and kernel_sources_digest() == MEASURED_TRAFFIC["sources_sha256"]:
+        traffic = MEASURED_TRAFFIC["bytes_per_launch"]
     out = {
         "metric": "attempted swaps/s on 1 MI355X (268M-site BCC); batched p50/p99 latency",
         "value": value,
@@ -299,7 +321,7 @@ def main():
                    "shells": job.S, "T_K": 800.0, "composition": "Dirichlet(5)", "block": 12,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved_ops / 1e12, "peak": VALU_PEAK / 1e12,
-                     "unit": "Tops/s", "frac": achieved_ops / VALU_PEAK, "traffic": None,
+                     "unit": "Tops/s", "frac": achieved_ops / VALU_PEAK, "traffic": traffic,
                      "kernel": "sweep_phase_kernel<5,3>", "avg_launch_ms": avg_launch_s * 1e3,
                      "launches": launches, "ops_per_trial": OPS_PER_TRIAL},
         "hbm": {"achieved": hbm_bytes / avg_launch_s / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
