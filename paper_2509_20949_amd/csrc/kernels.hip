@@ -283,20 +283,33 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
             if (by && b1) lat[brow + 1] = (uint8_t)(v >> 24);
         }
     } else {
-        // a periodic wrap along x: one cell (two bytes) per lane
+        // a periodic wrap along x: one cell (two bytes) per lane, rows
+        // r = (lane >> 4) + 4 it; the loads of 16 rows are issued together
+        // (lanes and rows outside the halo load a clamped in-range cell)
         const int lx = (lane & 15) - 2;
         const bool okx = lx <= wx + 1;
-        const int gx = wrap_add(gx0 + lx, Lx);
-        for (int r = lane >> 4; r < 256; r += 4) {
-            const int ly = (r & 15) - 2, lz = (r >> 4) - 2;
-            if (!okx || ly > wy + 1 || lz > wz + 1) continue;
-            const int gy = wrap_add(gy0 + ly, Ly), gz = wrap_add(gz0 + lz, Lz);
-            const size_t cell = ((size_t)gz * Ly + gy) * Lx + gx;
-            const uint32_t v = encode2(*(const uint16_t*)(g + 2 * cell), F);
-            if (lx >= -1 && ly >= -1 && lz >= -1)
-                lat[(lz + 1) * kPP + (ly + 1) * kP + (lx + 1)] = (uint8_t)v;
-            if (lx <= wx && ly <= wy && lz <= wz)
-                lat[kArr + (lz + 2) * kPP + (ly + 2) * kP + (lx + 2)] = (uint8_t)(v >> 8);
+        const int gx = wrap_add(gx0 + (okx ? lx : -2), Lx);
+        for (int it0 = 0; it0 < 64; it0 += 16) {
+            uint32_t v16[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int it = it0 + u;
+                const int ly = min((lane >> 4) + 4 * (it & 3) - 2, wy + 1), lz = min((it >> 2) - 2, wz + 1);
+                const int gy = wrap_add(gy0 + ly, Ly), gz = wrap_add(gz0 + lz, Lz);
+                const size_t cell = ((size_t)gz * Ly + gy) * Lx + gx;
+                v16[u] = *(const uint16_t*)(g + 2 * cell);
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int it = it0 + u;
+                const int ly = (lane >> 4) + 4 * (it & 3) - 2, lz = (it >> 2) - 2;
+                if (!okx || ly > wy + 1 || lz > wz + 1) continue;
+                const uint32_t v = encode2(v16[u], F);
+                if (lx >= -1 && ly >= -1 && lz >= -1)
+                    lat[(lz + 1) * kPP + (ly + 1) * kP + (lx + 1)] = (uint8_t)v;
+                if (lx <= wx && ly <= wy && lz <= wz)
+                    lat[kArr + (lz + 2) * kPP + (ly + 2) * kP + (lx + 2)] = (uint8_t)(v >> 8);
+            }
         }
     }
 
@@ -432,26 +445,41 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
             }
         }
     } else {
-        // a periodic wrap along x: one cell (two bytes) per lane
+        // a periodic wrap along x: one cell (two bytes) per lane, rows
+        // r = (lane >> 4) + 4 it; the LDS reads of 8 rows are issued
+        // together (rows and cells outside the boxes read clamped in-image
+        // bytes and store nothing)
         const int lx = (lane & 15) - 1;
         const bool okx = lx <= wx;
-        const int gx = wrap_add(gx0 + lx, Lx);
-        for (int r = lane >> 4; r < 256; r += 4) {
-            const int ly = (r & 15) - 1, lz = (r >> 4) - 1;
-            if (!okx || ly > wy || lz > wz) continue;
-            const bool corner = lx >= 0 && ly >= 0 && lz >= 0;
-            const bool body = lx < wx && ly < wy && lz < wz;
-            if (!corner && !body) continue;
-            const int gy = wrap_add(gy0 + ly, Ly), gz = wrap_add(gz0 + lz, Lz);
-            const size_t cell = ((size_t)gz * Ly + gy) * Lx + gx;
-            const uint32_t vc = corner ? decode(lat[(lz + 1) * kPP + (ly + 1) * kP + (lx + 1)]) : 0u;
-            const uint32_t vb = body ? decode(lat[kArr + (lz + 2) * kPP + (ly + 2) * kP + (lx + 2)]) : 0u;
-            if (corner && body)
-                *(uint16_t*)(g + 2 * cell) = (uint16_t)(vc | vb << 8);
-            else if (corner)
-                g[2 * cell] = (uint8_t)vc;
-            else
-                g[2 * cell + 1] = (uint8_t)vb;
+        const int lxc = okx ? lx : wx;
+        const int gx = wrap_add(gx0 + lxc, Lx);
+        const int nit = 4 * (wz + 2);               // rows with lz <= wz
+        for (int it0 = 0; it0 < nit; it0 += 8) {
+            uint32_t vc[8], vb[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int it = it0 + u;
+                const int lyc = min((lane >> 4) + 4 * (it & 3) - 1, wy), lzc = min((it >> 2) - 1, wz);
+                vc[u] = lat[(lzc + 1) * kPP + (lyc + 1) * kP + (lxc + 1)];
+                vb[u] = lat[kArr + (lzc + 2) * kPP + (lyc + 2) * kP + (lxc + 2)];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int it = it0 + u;
+                const int ly = (lane >> 4) + 4 * (it & 3) - 1, lz = (it >> 2) - 1;
+                if (!okx || ly > wy || lz > wz) continue;
+                const bool corner = lx >= 0 && ly >= 0 && lz >= 0;
+                const bool body = lx < wx && ly < wy && lz < wz;
+                if (!corner && !body) continue;
+                const int gy = wrap_add(gy0 + ly, Ly), gz = wrap_add(gz0 + lz, Lz);
+                const size_t cell = ((size_t)gz * Ly + gy) * Lx + gx;
+                if (corner && body)
+                    *(uint16_t*)(g + 2 * cell) = (uint16_t)(decode(vc[u]) | decode(vb[u]) << 8);
+                else if (corner)
+                    g[2 * cell] = (uint8_t)decode(vc[u]);
+                else
+                    g[2 * cell + 1] = (uint8_t)decode(vb[u]);
+            }
         }
     }
 

@@ -246,20 +246,32 @@ void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem*
     }
 
     // ---- stage block + halo: one cell (4 sublattice bytes, one dword) per lane ----
+    // Rows r = (lane >> 4) + 4 it; the loads of 16 rows are issued together
+    // (lanes and rows outside the halo load a clamped in-range cell).
     {
         const int lx = (lane & 15) - 2;
         const bool okx = lx <= wx + 1;
-        const int gx = wrap_add(gx0 + lx, Lx);
-        for (int r = lane >> 4; r < 256; r += 4) {
-            const int ly = (r & 15) - 2, lz = (r >> 4) - 2;
-            if (!okx || ly > wy + 1 || lz > wz + 1) continue;
-            const int gy = wrap_add(gy0 + ly, Ly), gz = wrap_add(gz0 + lz, Lz);
-            const size_t cell = ((size_t)gz * Ly + gy) * Lx + gx;
-            uint32_t v = *(const uint32_t*)(g + 4 * cell);
-            v = (v << 5) + (v << 2) + (v << 1);     // (6 + 32) * species, per byte
+        const int gx = wrap_add(gx0 + (okx ? lx : -2), Lx);
+        for (int it0 = 0; it0 < 64; it0 += 16) {
+            uint32_t v16[16];
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
-                if (in_halo(b, lx, ly, lz, wx, wy, wz)) lat[lds_index(b, lx, ly, lz)] = (uint8_t)(v >> (8 * b));
+            for (int u = 0; u < 16; ++u) {
+                const int it = it0 + u;
+                const int ly = min((lane >> 4) + 4 * (it & 3) - 2, wy + 1), lz = min((it >> 2) - 2, wz + 1);
+                const int gy = wrap_add(gy0 + ly, Ly), gz = wrap_add(gz0 + lz, Lz);
+                v16[u] = *(const uint32_t*)(g + 4 * (((size_t)gz * Ly + gy) * Lx + gx));
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int it = it0 + u;
+                const int ly = (lane >> 4) + 4 * (it & 3) - 2, lz = (it >> 2) - 2;
+                if (!okx || ly > wy + 1 || lz > wz + 1) continue;
+                uint32_t v = v16[u];
+                v = (v << 5) + (v << 2) + (v << 1);     // (6 + 32) * species, per byte
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if (in_halo(b, lx, ly, lz, wx, wy, wz)) lat[lds_index(b, lx, ly, lz)] = (uint8_t)(v >> (8 * b));
+            }
         }
     }
 
@@ -305,29 +317,46 @@ void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem*
     }
 
     // ---- write back: sublattice b over cells -SUB[b][a] .. w_a - SUB[b][a] ----
+    // Rows r = (lane >> 4) + 4 it; the 16 LDS reads of four rows are issued
+    // together (rows and cells outside the boxes read clamped in-image bytes
+    // and store nothing).
     {
         const int lx = (lane & 15) - 1;
         const bool okx = lx <= wx;
+        const int lxc = okx ? lx : 0;
         const int gx = wrap_add(gx0 + lx, Lx);
-        for (int r = lane >> 4; r < 256; r += 4) {
-            const int ly = (r & 15) - 1, lz = (r >> 4) - 1;
-            if (!okx || ly > wy || lz > wz) continue;
-            bool v[4];
-            uint32_t e = 0u;
+        const int nit = 4 * (wz + 2);               // rows with lz <= wz
+        for (int it0 = 0; it0 < nit; it0 += 4) {
+            uint32_t c[4][4];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                v[b] = in_write_box(b, lx, ly, lz, wx, wy, wz);
-                if (v[b]) e |= decode(lat[lds_index(b, lx, ly, lz)]) << (8 * b);
+            for (int u = 0; u < 4; ++u) {
+                const int it = it0 + u;
+                const int lyc = min((lane >> 4) + 4 * (it & 3) - 1, wy), lzc = min((it >> 2) - 1, wz);
+#pragma unroll
+                for (int b = 0; b < 4; ++b) c[u][b] = lat[lds_index(b, lxc, lyc, lzc)];
             }
-            if (!(v[0] || v[1] || v[2] || v[3])) continue;
-            const int gy = wrap_add(gy0 + ly, Ly), gz = wrap_add(gz0 + lz, Lz);
-            uint8_t* q = g + 4 * (((size_t)gz * Ly + gy) * Lx + gx);
-            if (v[0] && v[1] && v[2] && v[3]) {
-                *(uint32_t*)q = e;
-            } else {
 #pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    if (v[b]) q[b] = (uint8_t)(e >> (8 * b));
+            for (int u = 0; u < 4; ++u) {
+                const int it = it0 + u;
+                const int ly = (lane >> 4) + 4 * (it & 3) - 1, lz = (it >> 2) - 1;
+                if (!okx || ly > wy || lz > wz) continue;
+                bool v[4];
+                uint32_t e = 0u;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    v[b] = in_write_box(b, lx, ly, lz, wx, wy, wz);
+                    e |= decode(c[u][b]) << (8 * b);
+                }
+                if (!(v[0] || v[1] || v[2] || v[3])) continue;
+                const int gy = wrap_add(gy0 + ly, Ly), gz = wrap_add(gz0 + lz, Lz);
+                uint8_t* q = g + 4 * (((size_t)gz * Ly + gy) * Lx + gx);
+                if (v[0] && v[1] && v[2] && v[3]) {
+                    *(uint32_t*)q = e;
+                } else {
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        if (v[b]) q[b] = (uint8_t)(e >> (8 * b));
+                }
             }
         }
     }
