@@ -55,6 +55,8 @@ def lib():
         L.or_bcc_draws.argtypes = [p(C.c_int32), p(C.c_int32), C.c_uint64, C.c_uint32, p(C.c_uint32),
                                    p(C.c_uint8), p(C.c_uint8), p(C.c_uint32)]
         L.or_bcc_draws.restype = C.c_int
+        L.or_fcc_draws.argtypes = [p(C.c_int32), p(C.c_int32), C.c_uint64, C.c_uint32, p(C.c_int64), p(C.c_uint32)]
+        L.or_fcc_draws.restype = C.c_int
         L.or_shell_size.argtypes = [C.c_int, C.c_int]
         L.or_n_sub.argtypes = [C.c_int]
         L.or_neighbour.restype = C.c_int64
@@ -182,6 +184,19 @@ def bcc_draws(L, B, seed, s):
     if rc != 0:
         raise ValueError("invalid arguments")
     return ctr, word, dirs, u
+
+
+def fcc_draws(L, B, seed, s):
+    """Per-site FCC trial draws of sweep s: (partner site index, u_acc)."""
+    Lv = _L(L)
+    N = n_sites(Lv, FCC)
+    partner = np.zeros(N, np.int64)
+    u = np.zeros(N, np.uint32)
+    rc = lib().or_fcc_draws(_ptr(Lv, C.c_int32), _ptr(_L(B), C.c_int32), C.c_uint64(seed), C.c_uint32(s),
+                            _ptr(partner, C.c_int64), _ptr(u, C.c_uint32))
+    if rc != 0:
+        raise ValueError("invalid arguments")
+    return partner, u
 
 
 def neighbour(L, i, k, lattice=BCC):

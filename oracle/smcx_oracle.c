@@ -510,18 +510,21 @@ static int valid_inputs(const int32_t L[3], const int32_t B[3], int S, int K, co
 
 /* FCC partner choice (reading; the paper states none).  A site of
  * sublattice b has 12 first neighbours, 4 in each other sublattice.  The
- * partner sublattice b' of every trial of one (sweep s, colour c,
- * sub-colour q) set is drawn once: k = (t * 3) >> 32 with t = word 0 of
- * Philox4x32-10(key, (q, 0, s, c + 64)), b' = the k-th sublattice other
- * than b in increasing order.  The trial then takes the neighbour
- * (+-1, +-1) on the two axes where b and b' differ, the top two bits of its
- * direction word giving the signs (bit 30: first axis, bit 31: second,
- * set = +1).  Marginally each trial's partner is uniform over the 12. */
-static int fcc_partner_sublattice(const uint32_t key[2], uint32_t s, int c, int q)
+ * partner of every trial of one (sweep s, colour c, sub-colour q) set is
+ * drawn once, from r = Philox4x32-10(key, (q, 0, s, c + 64)): the partner
+ * sublattice b' = the k-th sublattice other than b in increasing order,
+ * k = (r0 * 3) >> 32, and on the two axes where b and b' differ the
+ * neighbour (+-1, +-1) with the signs given by bits 30 (first axis) and 31
+ * (second axis) of r1, set = +1.  Every trial still swaps one fixed pair
+ * chosen without looking at the configuration (a reversible Metropolis
+ * step of Eq. (1)); over the set draw the partner is uniform over the 12.
+ * The trial's own draw is only its acceptance word (see or_sweep). */
+static int fcc_partner_sublattice(const uint32_t key[2], uint32_t s, int c, int q, uint32_t* signs)
 {
     uint32_t ctr[4] = {(uint32_t)q, 0u, s, (uint32_t)c + 64u};
     uint32_t r[4];
     or_philox4x32_10(ctr, key, r);
+    *signs = r[1];
     int b = q % 4, k = (int)(((uint64_t)r[0] * 3u) >> 32);
     for (int bp = 0; bp < 4; ++bp) {
         if (bp == b) continue;
@@ -530,17 +533,44 @@ static int fcc_partner_sublattice(const uint32_t key[2], uint32_t s, int c, int 
     return -1;
 }
 
-static int64_t fcc_partner(const int32_t L[3], int64_t i, int bp, uint32_t u_dir)
+static int64_t fcc_partner(const int32_t L[3], int64_t i, int bp, uint32_t signs)
 {
     int b = (int)(i % 4);
     int d[3] = {0, 0, 0};
     int bit = 30;
     for (int a = 0; a < 3; ++a)
         if (SUB_FCC[b][a] != SUB_FCC[bp][a]) {
-            d[a] = ((u_dir >> bit) & 1u) ? +1 : -1;
+            d[a] = ((signs >> bit) & 1u) ? +1 : -1;
             ++bit;
         }
     return site_at(1, L, decode_site(1, L, i), d);
+}
+
+int or_fcc_draws(const int32_t L[3], const int32_t B[3], uint64_t seed, uint32_t s, int64_t* partner,
+                 uint32_t* u_acc)
+{
+    for (int a = 0; a < 3; ++a)
+        if (L[a] < 2 || B[a] < 2) return -1;
+    int64_t N = n_sites(1, L);
+    uint8_t* colour = (uint8_t*)malloc(N);
+    uint8_t* sub = (uint8_t*)malloc(N);
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    int psub[8 * 108];
+    uint32_t psign[8 * 108];
+    schedule_full(1, L, B, seed, s, colour, sub, NULL, NULL);
+    for (int g = 0; g < 8 * 108; ++g) psub[g] = fcc_partner_sublattice(key, s, g / 108, g % 108, &psign[g]);
+    for (int64_t i = 0; i < N; ++i) {
+        int64_t cell = i / 4;
+        int g = colour[i] * 108 + sub[i];
+        uint32_t ctr[4] = {(uint32_t)cell, (uint32_t)(cell >> 32), s, (uint32_t)colour[i]};
+        uint32_t rnd[4];
+        or_philox4x32_10(ctr, key, rnd);
+        u_acc[i] = rnd[i % 4];
+        partner[i] = fcc_partner(L, i, psub[g], psign[g]);
+    }
+    free(colour);
+    free(sub);
+    return 0;
 }
 
 int or_sweep(int lat, const int32_t L[3], const int32_t B[3], int S, int K, const int32_t* epi,
@@ -560,6 +590,7 @@ int or_sweep(int lat, const int32_t L[3], const int32_t B[3], int S, int K, cons
     uint32_t R[8][4];
     int64_t start[8 * 27 * 4 + 1];
     int partner_sub[8 * 27 * 4];
+    uint32_t partner_signs[8 * 27 * 4];
     double tab[768];
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
 
@@ -578,7 +609,7 @@ int or_sweep(int lat, const int32_t L[3], const int32_t B[3], int S, int K, cons
         /* FCC: one partner sublattice per (colour, sub-colour) set */
         if (lat == 1)
             for (int g = 0; g < ngroups; ++g)
-                partner_sub[g] = fcc_partner_sublattice(key, s, g / (27 * nsub), g % (27 * nsub));
+                partner_sub[g] = fcc_partner_sublattice(key, s, g / (27 * nsub), g % (27 * nsub), &partner_signs[g]);
         for (int g = 0; g < ngroups; ++g) {
             int64_t lo = g == 0 ? 0 : start[g - 1], hi = start[g];
             int64_t dE_set = 0;
@@ -597,14 +628,13 @@ int or_sweep(int lat, const int32_t L[3], const int32_t B[3], int S, int K, cons
                     bcc_draw(key, s, colour[i], sub[i], base[cell], R[colour[i]], ctr, &word, &dir, &u_acc);
                     j = or_neighbour(0, L, i, dir);
                 } else {
-                    /* FCC: sites 0, 1 of a cell share one Philox call, sites
-                     * 2, 3 another one with counter word 3 raised by 16 */
-                    uint32_t ctr[4] = {(uint32_t)cell, (uint32_t)(cell >> 32), s,
-                                       (uint32_t)colour[i] + 16u * (uint32_t)(b >> 1)};
+                    /* FCC: the four sites of a cell share one Philox call,
+                     * site b taking word b as its acceptance draw */
+                    uint32_t ctr[4] = {(uint32_t)cell, (uint32_t)(cell >> 32), s, (uint32_t)colour[i]};
                     uint32_t rnd[4];
                     or_philox4x32_10(ctr, key, rnd);
-                    u_acc = rnd[2 * (b & 1) + 1];
-                    j = fcc_partner(L, i, partner_sub[g], rnd[2 * (b & 1)]);
+                    u_acc = rnd[b];
+                    j = fcc_partner(L, i, partner_sub[g], partner_signs[g]);
                 }
                 if (sigma[i] == sigma[j]) continue;
                 int64_t dE = or_delta_energy(lat, L, S, K, epi, sigma, i, j);

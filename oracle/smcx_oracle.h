@@ -83,6 +83,11 @@ void or_schedule(int lat, const int32_t L[3], const int32_t B[3], uint64_t seed,
 int or_bcc_draws(const int32_t L[3], const int32_t B[3], uint64_t seed, uint32_t s, uint32_t* ctr,
                  uint8_t* word, uint8_t* dir, uint32_t* u_acc);
 
+/* FCC trial draws of sweep s for every site i: the partner's site index
+ * and the acceptance draw.  Returns 0, or -1 on invalid arguments. */
+int or_fcc_draws(const int32_t L[3], const int32_t B[3], uint64_t seed, uint32_t s, int64_t* partner,
+                 uint32_t* u_acc);
+
 /* Site index of neighbour `k` of site i, k indexing the displacement set of
  * shells 1..S in the order documented in smcx_oracle.c. */
 int64_t or_neighbour(int lat, const int32_t L[3], int64_t i, int k);

@@ -8,11 +8,13 @@
 // is a compile-time constant for a given (sublattice, displacement).  A
 // round is one (residue class, sublattice) pair: 27 x 4 = 108 rounds.
 //
-// Partner choice: the partner sublattice of all trials of one (sweep,
-// colour, sub-colour) set is drawn once (the same draw on every wave), so a
-// wave's partners all live in one sublattice and the partner's neighbour
-// offsets are selected by a scalar branch; each trial then takes one of the
-// 4 first neighbours in that sublattice from two bits of its draw.
+// Partner choice: the partner of all trials of one (sweep, colour,
+// sub-colour) set -- its sublattice and the signs of the step on the two
+// axes where the sublattices differ -- is drawn once (the same draw on
+// every wave), so the partner's neighbour offsets are selected by a scalar
+// branch and every partner read of a wave is at one common offset.  A
+// trial's own draw is its acceptance word: one Philox call per cell serves
+// the cell's four sites.
 #include "device_common.h"
 
 namespace smcx {
@@ -96,13 +98,16 @@ constexpr int F = 6;
 constexpr int KMAXF = 5;
 constexpr uint32_t kBias = 32u * (1u | 1u << 6 | 1u << 12 | 1u << 18 | 1u << 24);
 
+// One trial: site at LDS byte ai (sublattice B), partner in sublattice BP
+// with the wave-uniform signs (bit 0: first differing axis, bit 1: second;
+// set = +1), acceptance draw u_acc.
 template <int SMAX, int B, int BP>
-__device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u_dir, uint32_t u_acc, bool valid, bool drop,
+__device__ __forceinline__ void trial(uint8_t* lat, int ai, int signs, uint32_t u_acc, bool valid, bool drop,
                                       const int32_t* wtab, const double* tab, int64_t& dEsum, uint32_t& nacc)
 {
     constexpr int PS = wplane(KMAXF);
     constexpr int a1 = axis1(B, BP), a2 = axis2(B, BP);
-    const int bit1 = (int)((u_dir >> 30) & 1u), bit2 = (int)(u_dir >> 31);
+    const int bit1 = signs & 1, bit2 = (signs >> 1) & 1;
     const int aj = ai + (BP - B) * kArr + (SUB[BP][a1] - 1 + bit1) * stride(a1) + (SUB[BP][a2] - 1 + bit2) * stride(a2);
     const uint32_t ci = lat[ai];
     const uint32_t cj = lat[aj];
@@ -134,24 +139,25 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u_dir, uint
     const int32_t dE = (int32_t)acc;
     const int e = dE < 1 ? 1 : (dE > (1 << 24) - 1 ? (1 << 24) - 1 : dE);
     const double thr = (tab[512 + (e >> 16)] * tab[256 + ((e >> 8) & 255)]) * tab[e & 255];
-    const bool up_ok = dE < (1 << 24) && (double)u_acc < thr;
-    if (valid && ci != cj && (dE <= 0 || up_ok)) {
-        lat[ai] = (uint8_t)cj;
-        lat[aj] = (uint8_t)ci;
-        dEsum += dE;
-        nacc += 1u;
-    }
+    const bool up_ok = (dE < (1 << 24)) & ((double)u_acc < thr);
+    const bool accept = valid & (ci != cj) & ((dE <= 0) | up_ok);
+    // both bytes stored by every lane (unchanged unless accepted): no two
+    // lanes of a round touch the same byte
+    lat[ai] = (uint8_t)(accept ? cj : ci);
+    lat[aj] = (uint8_t)(accept ? ci : cj);
+    dEsum += accept ? (int64_t)dE : 0;
+    nacc += accept ? 1u : 0u;
 }
 
 // Partner sublattice BP (a wave-uniform value) selects one instantiation.
 template <int SMAX, int B>
-__device__ __forceinline__ void trial_any(int bp, uint8_t* lat, int ai, uint32_t u_dir, uint32_t u_acc, bool valid, bool drop,
+__device__ __forceinline__ void trial_any(int bp, uint8_t* lat, int ai, int signs, uint32_t u_acc, bool valid, bool drop,
                                           const int32_t* wtab, const double* tab, int64_t& dEsum, uint32_t& nacc)
 {
-    if constexpr (B != 0) { if (bp == 0) { trial<SMAX, B, 0>(lat, ai, u_dir, u_acc, valid, drop, wtab, tab, dEsum, nacc); return; } }
-    if constexpr (B != 1) { if (bp == 1) { trial<SMAX, B, 1>(lat, ai, u_dir, u_acc, valid, drop, wtab, tab, dEsum, nacc); return; } }
-    if constexpr (B != 2) { if (bp == 2) { trial<SMAX, B, 2>(lat, ai, u_dir, u_acc, valid, drop, wtab, tab, dEsum, nacc); return; } }
-    if constexpr (B != 3) { if (bp == 3) { trial<SMAX, B, 3>(lat, ai, u_dir, u_acc, valid, drop, wtab, tab, dEsum, nacc); return; } }
+    if constexpr (B != 0) { if (bp == 0) { trial<SMAX, B, 0>(lat, ai, signs, u_acc, valid, drop, wtab, tab, dEsum, nacc); return; } }
+    if constexpr (B != 1) { if (bp == 1) { trial<SMAX, B, 1>(lat, ai, signs, u_acc, valid, drop, wtab, tab, dEsum, nacc); return; } }
+    if constexpr (B != 2) { if (bp == 2) { trial<SMAX, B, 2>(lat, ai, signs, u_acc, valid, drop, wtab, tab, dEsum, nacc); return; } }
+    if constexpr (B != 3) { if (bp == 3) { trial<SMAX, B, 3>(lat, ai, signs, u_acc, valid, drop, wtab, tab, dEsum, nacc); return; } }
 }
 
 template <int B>
@@ -235,14 +241,15 @@ void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem*
     uint8_t* lat = s_lat + wave * kWaveLdsF;
     uint8_t* __restrict__ g = D.species;
 
-    // partner sublattice of every (colour, sub-colour) set of this sweep:
-    // k = (t0 * 3) >> 32 for t0 = word 0 of Philox(key, (q, 0, s, c + 64)),
-    // the k-th sublattice other than the set's own
+    // partner of every (colour, sub-colour q) set of this sweep, from
+    // r = Philox(key, (q, 0, s, c + 64)): sublattice = the k-th other than
+    // the set's own, k = (r0 * 3) >> 32 (low 2 bits of the byte), signs =
+    // bits 30 and 31 of r1 (bits 2 and 3)
     for (int q = lane; q < 108; q += kWave) {
         uint32_t r[4] = {(uint32_t)q, 0u, s, (uint32_t)colour + 64u};
         philox4x32_10(r, k0, k1);
         const int b = q & 3, k = (int)(((uint64_t)r[0] * 3u) >> 32);
-        lat[kBpOff + q] = (uint8_t)(k + (k >= b ? 1 : 0));
+        lat[kBpOff + q] = (uint8_t)((k + (k >= b ? 1 : 0)) | (int)(r[1] >> 30) << 2);
     }
 
     // ---- stage block + halo: one cell (4 sublattice bytes, one dword) per lane ----
@@ -287,7 +294,7 @@ void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem*
     for (int m = 0; m < 27; ++m) {
         const int rx = m % 3, ry = (m / 3) % 3, rz = m / 9;
         const int lx = rx + 3 * ix, ly = ry + 3 * iy, lz = rz + 3 * iz;
-        const bool valid = lx < wx && ly < wy && lz < wz;
+        const bool valid = (lx < wx) & (ly < wy) & (lz < wz);
         uint32_t gx = bx + rx, gy = by + ry, gz = bz + rz;
         gx = min(gx, gx - (uint32_t)Lx);
         gy = min(gy, gy - (uint32_t)Ly);
@@ -297,22 +304,21 @@ void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem*
             cell = __umul24(gz, LxLy) + __umul24(gy, (uint32_t)Lx) + gx;
         else
             cell = ((uint64_t)gz * (uint32_t)Ly + gy) * (uint32_t)Lx + gx;
+        // one Philox call per cell: site b accepts with word b
         uint32_t ra[4] = {(uint32_t)cell, (uint32_t)(cell >> 32), s, (uint32_t)colour};
-        uint32_t rb[4] = {(uint32_t)cell, (uint32_t)(cell >> 32), s, (uint32_t)colour + 16u};
         philox4x32_10(ra, k0, k1);
-        philox4x32_10(rb, k0, k1);
         const int q0 = 4 * m;
-        int bp = __builtin_amdgcn_readfirstlane(lat[kBpOff + q0]);
-        trial_any<SMAX, 0>(bp, lat, site_addr<0>(lx, ly, lz), ra[0], ra[1], valid, drop, s_w, s_tab, dEsum, nacc);
+        int pb = __builtin_amdgcn_readfirstlane(lat[kBpOff + q0]);
+        trial_any<SMAX, 0>(pb & 3, lat, site_addr<0>(lx, ly, lz), pb >> 2, ra[0], valid, drop, s_w, s_tab, dEsum, nacc);
         __builtin_amdgcn_wave_barrier();
-        bp = __builtin_amdgcn_readfirstlane(lat[kBpOff + q0 + 1]);
-        trial_any<SMAX, 1>(bp, lat, site_addr<1>(lx, ly, lz), ra[2], ra[3], valid, drop, s_w, s_tab, dEsum, nacc);
+        pb = __builtin_amdgcn_readfirstlane(lat[kBpOff + q0 + 1]);
+        trial_any<SMAX, 1>(pb & 3, lat, site_addr<1>(lx, ly, lz), pb >> 2, ra[1], valid, drop, s_w, s_tab, dEsum, nacc);
         __builtin_amdgcn_wave_barrier();
-        bp = __builtin_amdgcn_readfirstlane(lat[kBpOff + q0 + 2]);
-        trial_any<SMAX, 2>(bp, lat, site_addr<2>(lx, ly, lz), rb[0], rb[1], valid, drop, s_w, s_tab, dEsum, nacc);
+        pb = __builtin_amdgcn_readfirstlane(lat[kBpOff + q0 + 2]);
+        trial_any<SMAX, 2>(pb & 3, lat, site_addr<2>(lx, ly, lz), pb >> 2, ra[2], valid, drop, s_w, s_tab, dEsum, nacc);
         __builtin_amdgcn_wave_barrier();
-        bp = __builtin_amdgcn_readfirstlane(lat[kBpOff + q0 + 3]);
-        trial_any<SMAX, 3>(bp, lat, site_addr<3>(lx, ly, lz), rb[2], rb[3], valid, drop, s_w, s_tab, dEsum, nacc);
+        pb = __builtin_amdgcn_readfirstlane(lat[kBpOff + q0 + 3]);
+        trial_any<SMAX, 3>(pb & 3, lat, site_addr<3>(lx, ly, lz), pb >> 2, ra[3], valid, drop, s_w, s_tab, dEsum, nacc);
         __builtin_amdgcn_wave_barrier();
     }
 

@@ -97,3 +97,52 @@ def test_partner_is_a_first_neighbour(orc):
     # sign of each component follows the direction bits
     want = np.stack([(dirs.astype(np.int64) >> a) & 1 for a in range(3)], axis=-1) * 2 - 1
     assert np.array_equal(d, want)
+
+
+# ---- FCC (the partner of every trial of a set is drawn once per set) ----
+
+def fcc_pos(L, k):
+    sub = np.array([(0, 0, 0), (1, 1, 0), (1, 0, 1), (0, 1, 1)])
+    b, c = k % 4, k // 4
+    x, y, z = c % L[0], (c // L[0]) % L[1], c // (L[0] * L[1])
+    return np.stack([2 * x, 2 * y, 2 * z], axis=-1) + sub[b]
+
+
+def fcc_disp(L, i, j):
+    d = (fcc_pos(L, j) - fcc_pos(L, i)) % (2 * np.asarray(L))
+    return np.where(d > np.asarray(L), d - 2 * np.asarray(L), d)
+
+
+def test_fcc_partner_is_first_neighbour_and_shared_per_set(orc):
+    L, B = (7, 6, 5), (12, 12, 12)
+    N = 4 * int(np.prod(L))
+    i = np.arange(N)
+    for s in (0, 4):
+        j, u = orc.fcc_draws(L, B, 21, s)
+        d = fcc_disp(L, i, j)
+        assert np.all((d * d).sum(-1) == 2)          # first shell: (+-1, +-1, 0) and permutations
+        col, sub, _ = orc.schedule(L, B, 21, s, lattice=orc.FCC)
+        key = col.astype(np.int64) * 108 + sub
+        for k in np.unique(key):
+            assert np.unique(d[key == k], axis=0).shape[0] == 1, (s, k)
+        # acceptance words: one Philox call per cell, a different word per site
+        assert np.unique(u).size > 0.99 * N
+
+
+def test_fcc_partner_uniform_over_the_twelve(orc):
+    """One displacement per (colour, sub-colour) set, counted once per set."""
+    L, B = (6, 6, 6), (12, 12, 12)
+    N = 4 * int(np.prod(L))
+    i = np.arange(N)
+    counts = {}
+    for s in range(200):
+        j, _ = orc.fcc_draws(L, B, 5, s)
+        d = fcc_disp(L, i, j)
+        col, sub, _ = orc.schedule(L, B, 5, s, lattice=orc.FCC)
+        key = col.astype(np.int64) * 108 + sub
+        _, first = np.unique(key, return_index=True)   # one draw per set
+        for v, c in zip(*np.unique(d[first], axis=0, return_counts=True)):
+            counts[tuple(v)] = counts.get(tuple(v), 0) + c
+    assert len(counts) == 12
+    chi2, dof = chi2_uniform(list(counts.values()))
+    assert chi2 < dof + 6 * np.sqrt(2 * dof), counts
