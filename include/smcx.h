@@ -42,14 +42,12 @@
  *   z iff bit 2q+1 of R is set (-a/2 otherwise), R = the 128 bits of
  *   Philox4x32-10(key, (0, 0, s, 32 + c)) (bit t = bit t%32 of word t/32);
  *   its acceptance draw is u = w << 1 (mod 2^32).
- *   FCC: site b of a cell draws Philox4x32-10(key, (cell & 0xffffffff,
- *   cell >> 32, s, c + 16*(b >> 1))) and uses words 2*(b & 1) (direction)
- *   and u = word 2*(b & 1) + 1 (acceptance); all trials of one (sweep,
- *   colour, sub-colour q) set take their partner in one sublattice b' = the
- *   k-th sublattice other than b, k = (t * 3) >> 32, t = word 0 of
- *   Philox4x32-10(key, (q, 0, s, c + 64)); bits 30 and 31 of the direction
- *   word give the signs (+a/2 when set) on the two axes where b and b'
- *   differ.
+ *   FCC: site b of a cell takes u = word b of Philox4x32-10(key, (cell &
+ *   0xffffffff, cell >> 32, s, c)) as its acceptance draw.  The partner of
+ *   every trial of one (sweep, colour, sub-colour q) set is drawn once from
+ *   r = Philox4x32-10(key, (q, 0, s, c + 64)): its sublattice b' = the k-th
+ *   sublattice other than b, k = (r0 * 3) >> 32, and bits 30 and 31 of r1
+ *   give the signs (+a/2 when set) on the two axes where b and b' differ.
  *   Both lattices accept an uphill swap iff dE < 2^24 and
  *   (double)u < (T2[dE>>16] * T1[(dE>>8)&255]) * T0[dE&255], with
  *   beta = 1 / (86.17333262 * T) per micro-eV and
