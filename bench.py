@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--L", type=int, default=512, help="cells per axis (512 = the benchmark workload)")
+    ap.add_argument("--block", type=int, default=12,
+                    help="schedule block-width parameter B (12: one wavefront-sized block, the fewest blocks)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0 = all host cores)")
     ap.add_argument("--no-slab", action="store_true",
@@ -308,7 +310,7 @@ def main():
     t_gen = time.perf_counter() - t_gen
     progress(f"input ready in {t_gen:.1f} s; warmup {args.warmup} sweeps")
 
-    lat = smcx.Lattice(job.L, job.epi, job.sigma, job.seed, 800.0)   # block 12: one wave per block
+    lat = smcx.Lattice(job.L, job.epi, job.sigma, job.seed, 800.0, block=(args.block,) * 3)
     E0 = lat.energy()
     lat.sweep(args.warmup)
     smcx.smcx_synchronize(lat.ctx)
@@ -356,7 +358,7 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": f"bcc{job.L[0]}^3 quinary EPI sweep", "sites": job.N, "species": job.K,
-                   "shells": job.S, "T_K": 800.0, "composition": "Dirichlet(5)", "block": 12,
+                   "shells": job.S, "T_K": 800.0, "composition": "Dirichlet(5)", "block": args.block,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved_ops / 1e12, "peak": VALU_PEAK / 1e12,
                      "unit": "Tops/s", "frac": achieved_ops / VALU_PEAK, "traffic": traffic,
