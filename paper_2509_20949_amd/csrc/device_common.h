@@ -52,6 +52,33 @@ __device__ __forceinline__ void load_wplanes(int32_t* s_w, const int32_t* wtab)
     }
 }
 
+// Lower bound floor(k L / n) of block k of n along an axis of L cells
+// (0 <= k <= n <= L).  k L <= L^2 < 2^32 whenever L <= 65535; wider axes
+// divide in 64 bits.  Called with wave-uniform arguments, so it runs on the scalar unit.
+__device__ __forceinline__ int block_lo(int k, int L, int n)
+{
+    return L <= 65535 ? (int)(((uint32_t)k * (uint32_t)L) / (uint32_t)n) : (int)(((int64_t)k * L) / n);
+}
+
+// The index of the calling lane's wavefront in its workgroup, as a value the
+// compiler knows to be the same for all lanes: everything derived from it
+// (block coordinates, row bases) is then computed once per wave in scalar
+// registers rather than per lane.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)); }
+
+// Accesses to the lattice in HBM.  A pointer loaded from a struct is generic
+// to the compiler, and generic (flat) accesses also count against the LDS
+// wait counter; through an address-space-1 pointer they are global loads
+// and stores.
+template <class T> __device__ __forceinline__ T gload(const uint8_t* p)
+{
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+template <class T> __device__ __forceinline__ void gstore(uint8_t* p, T v)
+{
+    *(__attribute__((address_space(1))) T*)p = v;
+}
+
 __device__ __forceinline__ int wrap_add(int v, int L)   // v in [-L, 2L)
 {
     v = v < 0 ? v + L : v;

@@ -24,10 +24,12 @@ namespace smcx {
 // v.  One shift-add per neighbour then counts species into packed fields.
 template <int KMAX> struct Field { static constexpr int F = KMAX <= 6 ? 5 : 4; };
 
-__device__ __forceinline__ uint32_t encode2(uint32_t two_species, int F)
+__device__ __forceinline__ uint32_t encode4(uint32_t species, int F)
 {
-    // two species bytes (v0 | v1 << 8) -> ((F+32) v0) | ((F+32) v1) << 8
-    return (two_species << 5) + two_species * (uint32_t)F;
+    // up to four species bytes v_k -> bytes (F+32) v_k: no carries, as
+    // (F+32) v <= 255 for every species the field width admits (all four
+    // bytes are used, so no 24-bit multiply)
+    return (species << 5) + species * (uint32_t)F;
 }
 
 // LDS layout of one block (see smcx_internal.h): corner array at offset 0,
@@ -183,7 +185,7 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
     __shared__ int32_t s_w[wplanes(KMAX, SMAX) * wplane(KMAX)];
     __shared__ __attribute__((aligned(16))) uint8_t s_lat[kWavesPerGroup * kWaveLds];
 
-    const int wave = threadIdx.x / kWave;
+    const int wave = wave_id();
     const int lane = threadIdx.x % kWave;
     int li = 0, f = blockIdx.x * kWavesPerGroup;
     if (items) {
@@ -220,12 +222,9 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
     const int oy = (int)(((uint64_t)sh[1] * (uint32_t)Ly) >> 32);
     const int oz = (int)(((uint64_t)sh[2] * (uint32_t)Lz) >> 32);
 
-    const int x0 = (int)(((int64_t)kx * Lx) / D.nb[0]);
-    const int y0 = (int)(((int64_t)ky * Ly) / D.nb[1]);
-    const int z0 = (int)(((int64_t)kz * Lz) / D.nb[2]);
-    const int wx = (int)(((int64_t)(kx + 1) * Lx) / D.nb[0]) - x0;
-    const int wy = (int)(((int64_t)(ky + 1) * Ly) / D.nb[1]) - y0;
-    const int wz = (int)(((int64_t)(kz + 1) * Lz) / D.nb[2]) - z0;
+    const int x0 = block_lo(kx, Lx, D.nb[0]), wx = block_lo(kx + 1, Lx, D.nb[0]) - x0;
+    const int y0 = block_lo(ky, Ly, D.nb[1]), wy = block_lo(ky + 1, Ly, D.nb[1]) - y0;
+    const int z0 = block_lo(kz, Lz, D.nb[2]), wz = block_lo(kz + 1, Lz, D.nb[2]) - z0;
     // global coordinate of local cell 0
     const int gx0 = wrap_add(x0 + ox, Lx), gy0 = wrap_add(y0 + oy, Ly), gz0 = wrap_add(z0 + oz, Lz);
 
@@ -265,15 +264,15 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
             const size_t row = narrow ? (size_t)(__umul24(gz, LxLy) + __umul24(gy, (uint32_t)Lx))
                                       : ((size_t)gz * (uint32_t)Ly + gy) * (uint32_t)Lx;
             const size_t at = 2 * (row + (size_t)(gx0 + lxa));     // byte of corner(lxa)
-            q0[it] = *(const uint32_t*)(g + (at & ~(size_t)3));
-            q1[it] = *(const uint32_t*)(g + ((at + 2) & ~(size_t)3));
+            q0[it] = gload<uint32_t>(g + (at & ~(size_t)3));
+            q1[it] = gload<uint32_t>(g + ((at + 2) & ~(size_t)3));
             al[it] = (uint32_t)at & 2u;
         }
 #pragma unroll
         for (int it = 0; it < 32; ++it) {
             const int ly = (lane >> 3) - 2 + 8 * (it & 1), lz = (it >> 1) - 2;
             if (!lane_ok || ly > wy + 1 || lz > wz + 1) continue;
-            const uint32_t v = encode2(__builtin_amdgcn_alignbyte(q1[it], q0[it], al[it]), F);
+            const uint32_t v = encode4(__builtin_amdgcn_alignbyte(q1[it], q0[it], al[it]), F);
             const int crow = (lz + 1) * kPP + (ly + 1) * kP + (lx0 + 1);
             const int brow = kArr + (lz + 2) * kPP + (ly + 2) * kP + (lx0 + 2);
             const bool cy = ly >= -1 && lz >= -1, by = ly <= wy && lz <= wz;
@@ -297,14 +296,14 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
                 const int ly = min((lane >> 4) + 4 * (it & 3) - 2, wy + 1), lz = min((it >> 2) - 2, wz + 1);
                 const int gy = wrap_add(gy0 + ly, Ly), gz = wrap_add(gz0 + lz, Lz);
                 const size_t cell = ((size_t)gz * Ly + gy) * Lx + gx;
-                v16[u] = *(const uint16_t*)(g + 2 * cell);
+                v16[u] = gload<uint16_t>(g + 2 * cell);
             }
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 const int it = it0 + u;
                 const int ly = (lane >> 4) + 4 * (it & 3) - 2, lz = (it >> 2) - 2;
                 if (!okx || ly > wy + 1 || lz > wz + 1) continue;
-                const uint32_t v = encode2(v16[u], F);
+                const uint32_t v = encode4(v16[u], F);
                 if (lx >= -1 && ly >= -1 && lz >= -1)
                     lat[(lz + 1) * kPP + (ly + 1) * kP + (lx + 1)] = (uint8_t)v;
                 if (lx <= wx && ly <= wy && lz <= wz)
@@ -435,12 +434,12 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
                 if (!m) continue;
                 uint8_t* q = dst[u];
                 if (m == 15u) {
-                    *(uint32_t*)q = decode(e[u][0]) | decode(e[u][1]) << 8 | decode(e[u][2]) << 16 |
-                                    decode(e[u][3]) << 24;
+                    gstore<uint32_t>(q, decode(e[u][0]) | decode(e[u][1]) << 8 | decode(e[u][2]) << 16 |
+                                            decode(e[u][3]) << 24);
                 } else {
 #pragma unroll
                     for (int k = 0; k < 4; ++k)
-                        if (m >> k & 1u) q[k] = (uint8_t)decode(e[u][k]);
+                        if (m >> k & 1u) gstore<uint8_t>(q + k, (uint8_t)decode(e[u][k]));
                 }
             }
         }
@@ -474,11 +473,11 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
                 const int gy = wrap_add(gy0 + ly, Ly), gz = wrap_add(gz0 + lz, Lz);
                 const size_t cell = ((size_t)gz * Ly + gy) * Lx + gx;
                 if (corner && body)
-                    *(uint16_t*)(g + 2 * cell) = (uint16_t)(decode(vc[u]) | decode(vb[u]) << 8);
+                    gstore<uint16_t>(g + 2 * cell, (uint16_t)(decode(vc[u]) | decode(vb[u]) << 8));
                 else if (corner)
-                    g[2 * cell] = (uint8_t)decode(vc[u]);
+                    gstore<uint8_t>(g + 2 * cell, (uint8_t)decode(vc[u]));
                 else
-                    g[2 * cell + 1] = (uint8_t)decode(vb[u]);
+                    gstore<uint8_t>(g + 2 * cell + 1, (uint8_t)decode(vb[u]));
             }
         }
     }

@@ -199,7 +199,7 @@ void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem*
     __shared__ int32_t s_w[wplanes(KMAXF, SMAX) * wplane(KMAXF)];
     __shared__ __attribute__((aligned(16))) uint8_t s_lat[kWavesPerGroup * kWaveLdsF];
 
-    const int wave = threadIdx.x / kWave;
+    const int wave = wave_id();
     const int lane = threadIdx.x % kWave;
     int li = 0, f = blockIdx.x * kWavesPerGroup;
     if (items) {
@@ -229,12 +229,9 @@ void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem*
     const int ox = (int)(((uint64_t)sh[0] * (uint32_t)Lx) >> 32);
     const int oy = (int)(((uint64_t)sh[1] * (uint32_t)Ly) >> 32);
     const int oz = (int)(((uint64_t)sh[2] * (uint32_t)Lz) >> 32);
-    const int x0 = (int)(((int64_t)kx * Lx) / D.nb[0]);
-    const int y0 = (int)(((int64_t)ky * Ly) / D.nb[1]);
-    const int z0 = (int)(((int64_t)kz * Lz) / D.nb[2]);
-    const int wx = (int)(((int64_t)(kx + 1) * Lx) / D.nb[0]) - x0;
-    const int wy = (int)(((int64_t)(ky + 1) * Ly) / D.nb[1]) - y0;
-    const int wz = (int)(((int64_t)(kz + 1) * Lz) / D.nb[2]) - z0;
+    const int x0 = block_lo(kx, Lx, D.nb[0]), wx = block_lo(kx + 1, Lx, D.nb[0]) - x0;
+    const int y0 = block_lo(ky, Ly, D.nb[1]), wy = block_lo(ky + 1, Ly, D.nb[1]) - y0;
+    const int z0 = block_lo(kz, Lz, D.nb[2]), wz = block_lo(kz + 1, Lz, D.nb[2]) - z0;
     const int gx0 = wrap_add(x0 + ox, Lx), gy0 = wrap_add(y0 + oy, Ly), gz0 = wrap_add(z0 + oz, Lz);
     const uint32_t k0 = D.key[0], k1 = D.key[1];
 
@@ -266,7 +263,7 @@ void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem*
                 const int it = it0 + u;
                 const int ly = min((lane >> 4) + 4 * (it & 3) - 2, wy + 1), lz = min((it >> 2) - 2, wz + 1);
                 const int gy = wrap_add(gy0 + ly, Ly), gz = wrap_add(gz0 + lz, Lz);
-                v16[u] = *(const uint32_t*)(g + 4 * (((size_t)gz * Ly + gy) * Lx + gx));
+                v16[u] = gload<uint32_t>(g + 4 * (((size_t)gz * Ly + gy) * Lx + gx));
             }
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
@@ -357,11 +354,11 @@ void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem*
                 const int gy = wrap_add(gy0 + ly, Ly), gz = wrap_add(gz0 + lz, Lz);
                 uint8_t* q = g + 4 * (((size_t)gz * Ly + gy) * Lx + gx);
                 if (v[0] && v[1] && v[2] && v[3]) {
-                    *(uint32_t*)q = e;
+                    gstore<uint32_t>(q, e);
                 } else {
 #pragma unroll
                     for (int b = 0; b < 4; ++b)
-                        if (v[b]) q[b] = (uint8_t)(e >> (8 * b));
+                        if (v[b]) gstore<uint8_t>(q + b, (uint8_t)(e >> (8 * b)));
                 }
             }
         }
