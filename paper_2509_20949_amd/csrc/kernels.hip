@@ -283,32 +283,29 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
         }
     } else {
         // a periodic wrap along x: one cell (two bytes) per lane, rows
-        // r = (lane >> 4) + 4 it; the loads of 16 rows are issued together
-        // (lanes and rows outside the halo load a clamped in-range cell)
+        // r = (lane >> 4) + 4 it; all 64 loads of a lane are issued before
+        // any LDS write, as on the fast path (lanes and rows outside the
+        // halo load a clamped in-range cell)
         const int lx = (lane & 15) - 2;
         const bool okx = lx <= wx + 1;
         const int gx = wrap_add(gx0 + (okx ? lx : -2), Lx);
-        for (int it0 = 0; it0 < 64; it0 += 16) {
-            uint32_t v16[16];
+        uint32_t v64[64];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int it = it0 + u;
-                const int ly = min((lane >> 4) + 4 * (it & 3) - 2, wy + 1), lz = min((it >> 2) - 2, wz + 1);
-                const int gy = wrap_add(gy0 + ly, Ly), gz = wrap_add(gz0 + lz, Lz);
-                const size_t cell = ((size_t)gz * Ly + gy) * Lx + gx;
-                v16[u] = gload<uint16_t>(g + 2 * cell);
-            }
+        for (int it = 0; it < 64; ++it) {
+            const int ly = min((lane >> 4) + 4 * (it & 3) - 2, wy + 1), lz = min((it >> 2) - 2, wz + 1);
+            const int gy = wrap_add(gy0 + ly, Ly), gz = wrap_add(gz0 + lz, Lz);
+            const size_t cell = ((size_t)gz * Ly + gy) * Lx + gx;
+            v64[it] = gload<uint16_t>(g + 2 * cell);
+        }
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int it = it0 + u;
-                const int ly = (lane >> 4) + 4 * (it & 3) - 2, lz = (it >> 2) - 2;
-                if (!okx || ly > wy + 1 || lz > wz + 1) continue;
-                const uint32_t v = encode4(v16[u], F);
-                if (lx >= -1 && ly >= -1 && lz >= -1)
-                    lat[(lz + 1) * kPP + (ly + 1) * kP + (lx + 1)] = (uint8_t)v;
-                if (lx <= wx && ly <= wy && lz <= wz)
-                    lat[kArr + (lz + 2) * kPP + (ly + 2) * kP + (lx + 2)] = (uint8_t)(v >> 8);
-            }
+        for (int it = 0; it < 64; ++it) {
+            const int ly = (lane >> 4) + 4 * (it & 3) - 2, lz = (it >> 2) - 2;
+            if (!okx || ly > wy + 1 || lz > wz + 1) continue;
+            const uint32_t v = encode4(v64[it], F);
+            if (lx >= -1 && ly >= -1 && lz >= -1)
+                lat[(lz + 1) * kPP + (ly + 1) * kP + (lx + 1)] = (uint8_t)v;
+            if (lx <= wx && ly <= wy && lz <= wz)
+                lat[kArr + (lz + 2) * kPP + (ly + 2) * kP + (lx + 2)] = (uint8_t)(v >> 8);
         }
     }
 
@@ -392,12 +389,41 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
     // Fast path (no periodic wrap along x): 8 lanes per row, each owning one
     // aligned dword of the row's span (corner(-1) .. body(w)); it stores the
     // dword whole, or only its bytes that belong to the corner box [0, w]^3
-    // or the body box [-1, w-1]^3 where the span or a box ends.  Rows go in
-    // batches of four per lane: the 16 LDS reads of a batch are issued
-    // before any is used.  Rows and cells outside the boxes read clamped
-    // in-image LDS bytes and store nothing.
+    // or the body box [-1, w-1]^3 where the span or a box ends.  Lane
+    // (lrow, c) = (lane >> 3, lane & 7) takes rows ly = lrow - 1 + 8h
+    // (h = 0, 1), lz = -1 .. w.  The cells its dword holds depend only on
+    // the parity p of the row's first cell index in the lattice: cells lxa
+    // and lxa + 1, lxa = 2c - 2 + p.  The per-lane x and y parts (store
+    // masks, LDS offsets, lattice offsets) are set up once; a row adds its
+    // wave-uniform z part.  Rows go in batches of four: the 16 LDS reads of
+    // a batch are issued before any is used.  Rows and cells outside the
+    // boxes read in-image LDS bytes and store nothing.
     if (gx0 >= 1 && gx0 + wx < Lx) {
-        const int lrow = lane >> 3;                 // rows lrow + 8 it: ly = lrow - 1 + 8 (it & 1), lz = (it >> 1) - 1
+        const int lrow = lane >> 3, c8 = lane & 7;
+        uint32_t xm2 = 0u;                           // store masks for p = 0 (bits 0-3) and 1 (bits 4-7)
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int lxa = 2 * c8 - 2 + p;
+            xm2 |= ((uint32_t)(lxa >= 0 && lxa <= wx)               // corner(lxa)
+                  | (uint32_t)(lxa >= -1 && lxa < wx) << 1         // body(lxa)
+                  | (uint32_t)(lxa + 1 >= 0 && lxa + 1 <= wx) << 2 // corner(lxa + 1)
+                  | (uint32_t)(lxa + 1 < wx) << 3) << (4 * p);     // body(lxa + 1)
+        }
+        // corner byte of cell lxa sits at x offset max(lxa, -1) + 1 (lxa = -2
+        // only for c = 0, p = 0, and that byte is never stored), body at lxa + 2
+        const int cx0 = max(2 * c8 - 2, -1) + 1, cxp = c8 > 0 ? 1 : 0, bx0 = 2 * c8;
+        uint32_t ym[2], ypar[2];
+        int ylds[2];
+        uint64_t yb[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int ly = lrow - 1 + 8 * h, lyc = min(ly, wy);
+            ym[h] = (ly >= 0 && ly <= wy ? 5u : 0u) | (ly < wy ? 10u : 0u);
+            const uint64_t yrow = (uint64_t)(uint32_t)wrap_add(gy0 + lyc, Ly) * (uint32_t)Lx + (uint32_t)gx0;
+            ypar[h] = (uint32_t)yrow & 1u;
+            yb[h] = 2 * yrow + 4u * (uint32_t)c8 - 4u;   // byte of this lane's dword, less the z part and 2p
+            ylds[h] = (lyc + 1) * kP;
+        }
         const int nit = 2 * (wz + 2);               // rows with lz <= wz
         for (int it0 = 0; it0 < nit; it0 += 4) {
             uint32_t e[4][4];
@@ -405,28 +431,18 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
             uint32_t msk[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int it = it0 + u;
-                const int ly = lrow - 1 + 8 * (it & 1), lz = (it >> 1) - 1;
-                const bool ok = ly <= wy && lz <= wz;
-                const int lyc = min(ly, wy), lzc = min(lz, wz);
-                const uint32_t gy = (uint32_t)wrap_add(gy0 + lyc, Ly), gz = (uint32_t)wrap_add(gz0 + lzc, Lz);
-                const size_t row = narrow ? (size_t)(__umul24(gz, LxLy) + __umul24(gy, (uint32_t)Lx))
-                                          : ((size_t)gz * (uint32_t)Ly + gy) * (uint32_t)Lx;
-                const size_t at0 = 2 * (row + (size_t)gx0);           // byte of corner(0)
-                const size_t d = ((at0 - 2) & ~(size_t)3) + 4u * (uint32_t)(lane & 7);
-                const int lxa = (int)((int64_t)(d - at0) / 2);        // cells lxa, lxa + 1; lxa in -2..13
-                const bool cy = ok && ly >= 0 && lz >= 0, by = ok && ly < wy && lz < wz;
-                msk[u] = (uint32_t)(cy && lxa >= 0 && lxa <= wx)                // corner(lxa)
-                       | (uint32_t)(by && lxa >= -1 && lxa < wx) << 1          // body(lxa)
-                       | (uint32_t)(cy && lxa + 1 >= 0 && lxa + 1 <= wx) << 2  // corner(lxa + 1)
-                       | (uint32_t)(by && lxa + 1 >= -1 && lxa + 1 < wx) << 3; // body(lxa + 1)
-                const int crow = (lzc + 1) * kPP + (lyc + 1) * kP + (max(lxa, -1) + 1);
-                const int brow = kArr + (lzc + 2) * kPP + (lyc + 2) * kP + (lxa + 2);
+                const int h = u & 1, lz = ((it0 + u) >> 1) - 1, lzc = min(lz, wz);
+                const uint32_t zm = (lz >= 0 && lz <= wz ? 5u : 0u) | (lz < wz ? 10u : 0u);
+                const uint64_t zrow = (uint64_t)(uint32_t)wrap_add(gz0 + lzc, Lz) * ((uint64_t)Lx * (uint32_t)Ly);
+                const uint32_t pp = ypar[h] ^ ((uint32_t)zrow & 1u);
+                msk[u] = (xm2 >> (4 * pp)) & ym[h] & zm;
+                const int crow = (lzc + 1) * kPP + ylds[h] + cx0 + (int)(pp & (uint32_t)cxp);
+                const int brow = kArr + (lzc + 2) * kPP + kP + ylds[h] + bx0 + (int)pp;
                 e[u][0] = lat[crow];
                 e[u][1] = lat[brow];
                 e[u][2] = lat[crow + 1];
                 e[u][3] = lat[brow + 1];
-                dst[u] = g + d;
+                dst[u] = g + (2 * zrow + yb[h] + 2 * pp);
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
