@@ -39,7 +39,7 @@ __device__ __forceinline__ void keep(uint32_t& h) { asm("" : "+v"(h)); }
 // 4-byte banks, equal rows broadcast (a row-per-lane layout made most lanes
 // collide, its rows all starting on the same few banks).
 constexpr int wplane(int kmax) { return ((kmax * kmax + 31) / 32) * 32; }
-constexpr int wplanes(int kmax, int smax) { return smax * kmax + 1; }
+constexpr int wplanes(int kmax, int smax) { return wrow_entries(kmax, smax); }
 
 // Fill the LDS planes from the row-major table of wrow(KMAX, SMAX) ints per row.
 template <int KMAX, int SMAX>

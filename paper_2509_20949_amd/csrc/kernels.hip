@@ -24,6 +24,21 @@ namespace smcx {
 // v.  One shift-add per neighbour then counts species into packed fields.
 template <int KMAX> struct Field { static constexpr int F = KMAX <= 6 ? 5 : 4; };
 
+// Byte-dot codes (weight rows in kWtabDot form, KMAX <= 5): species
+// v < KMAX-1 is stored as 40 v, i.e. counted by a shift of 8 v into byte v
+// of the histogram word; the last species as 31 + 32 v, counted into bit 31,
+// which the weighing masks off.  The top 3 bits still give v back.  For up
+// to four species bytes at once.
+template <int KMAX>
+__device__ __forceinline__ uint32_t encode4_dot(uint32_t v)
+{
+    static_assert(KMAX <= 5, "byte-dot codes need KMAX <= 5");
+    constexpr uint32_t c = 8 - (KMAX - 1);                 // v + c >= 8 iff v == KMAX-1
+    const uint32_t last = ((v + c * 0x01010101u) >> 3) & 0x01010101u;
+    constexpr uint32_t k = (uint32_t)(31 - 8 * (KMAX - 1)); // code change of the last species, mod 2^32
+    return (v << 5) + (v << 3) + last * k;                   // no carries or borrows between bytes
+}
+
 __device__ __forceinline__ uint32_t encode4(uint32_t species, int F)
 {
     // up to four species bytes v_k -> bytes (F+32) v_k: no carries, as
@@ -130,12 +145,13 @@ __device__ __forceinline__ uint32_t weigh(const uint32_t (&hi)[kMaxS], const uin
     return acc;
 }
 
-template <int KMAX, int SMAX, int SUB, bool DROP>
+template <int KMAX, int SMAX, int SUB, int MODE>
 __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int yz, bool valid,
                                       const int32_t* wtab, const double* tab, int64_t& dEsum,
                                       uint32_t& nacc)
 {
     constexpr int F = Field<KMAX>::F;
+    constexpr bool DOT = MODE == kWtabDot;
     const uint32_t u_acc = u << 1;
     const int aj = ai + s1base<SUB>() + (int)(u >> 31) + yz;
     const uint32_t ci = lat[ai];
@@ -144,7 +160,8 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int yz, 
     // Species histograms of both neighbourhoods (the partner is counted in
     // the first shell of i and i in that of j; the constant term undoes it).
     uint32_t hi[kMaxS], hj[kMaxS];
-    constexpr uint32_t bias = F == 5 ? 0x10u * (1u | 1u << 5 | 1u << 10 | 1u << 15 | 1u << 20 | 1u << 25) : 0u;
+    constexpr uint32_t bias = DOT ? 0x20202020u
+                            : F == 5 ? 0x10u * (1u | 1u << 5 | 1u << 10 | 1u << 15 | 1u << 20 | 1u << 25) : 0u;
 #pragma unroll
     for (int s = 0; s < kMaxS; ++s) { hi[s] = bias; hj[s] = 0u; }
     histogram<SMAX, SUB>(lat, ai, hi);
@@ -154,10 +171,27 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int yz, 
     // the row index into the table (their result is discarded)
     const uint32_t a = min(decode(ci), (uint32_t)(KMAX - 1)), b = min(decode(cj), (uint32_t)(KMAX - 1));
     const int32_t* w = wtab + (a * KMAX + b);   // row (a, b) of the weight planes
-    // With DROP the rows fold in the last species, whose count differences
-    // follow from the others (both sites have the same number of neighbours
-    // per shell): only fields 0 .. KMAX-2 are read.
-    const uint32_t acc = weigh<KMAX, SMAX, DROP ? KMAX - 1 : KMAX>(hi, hj, w, (uint32_t)w[SMAX * KMAX * wplane(KMAX)]);
+    uint32_t acc;
+    if constexpr (DOT) {
+        // bytes 32 + n_i - n_j (bit 31, the last species, masked off) dotted
+        // with the three base-256 digits of the folded weights
+        constexpr int PS = wplane(KMAX);
+        int32_t A0 = 0, A1 = 0, A2 = 0;
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) {
+            const int32_t d = (int32_t)((hi[s] - hj[s]) & 0x7fffffffu);
+            A0 = __builtin_amdgcn_sdot4(d, w[(3 * s + 0) * PS], A0, false);
+            A1 = __builtin_amdgcn_sdot4(d, w[(3 * s + 1) * PS], A1, false);
+            A2 = __builtin_amdgcn_sdot4(d, w[(3 * s + 2) * PS], A2, false);
+        }
+        acc = (uint32_t)w[3 * SMAX * PS] + (uint32_t)A0 + ((uint32_t)A1 << 8) + ((uint32_t)A2 << 16);
+    } else {
+        // With kWtabDrop the rows fold in the last species, whose count
+        // differences follow from the others (both sites have the same
+        // number of neighbours per shell): only fields 0 .. KMAX-2 are read.
+        acc = weigh<KMAX, SMAX, MODE == kWtabDrop ? KMAX - 1 : KMAX>(hi, hj, w,
+                                                                      (uint32_t)w[SMAX * KMAX * wplane(KMAX)]);
+    }
     const int32_t dE = (int32_t)acc;
 
     // Metropolis decision, Eq. (3), on the FP64 byte tables.
@@ -235,6 +269,15 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
     const uint32_t LxLy = (uint32_t)Lx * (uint32_t)Ly;
     const bool narrow = LxLy < (1u << 24) && (uint64_t)LxLy * (uint32_t)Lz < (1ull << 32);
 
+    // species bytes -> LDS codes for this lattice's form of the weight rows
+    const bool dot_codes = KMAX <= 5 && D.drop_last == kWtabDot;
+    auto encode = [&](uint32_t v) -> uint32_t {
+        if constexpr (KMAX <= 5) {
+            if (dot_codes) return encode4_dot<KMAX>(v);
+        }
+        return encode4(v, F);
+    };
+
     // ---- stage block + halo: local cells -2..w+1 on each axis ----
     // Fast path (the block's x-range does not cross the periodic boundary):
     // 8 lanes per row, each reading two cells (corner, body, corner, body
@@ -272,7 +315,7 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
         for (int it = 0; it < 32; ++it) {
             const int ly = (lane >> 3) - 2 + 8 * (it & 1), lz = (it >> 1) - 2;
             if (!lane_ok || ly > wy + 1 || lz > wz + 1) continue;
-            const uint32_t v = encode4(__builtin_amdgcn_alignbyte(q1[it], q0[it], al[it]), F);
+            const uint32_t v = encode(__builtin_amdgcn_alignbyte(q1[it], q0[it], al[it]));
             const int crow = (lz + 1) * kPP + (ly + 1) * kP + (lx0 + 1);
             const int brow = kArr + (lz + 2) * kPP + (ly + 2) * kP + (lx0 + 2);
             const bool cy = ly >= -1 && lz >= -1, by = ly <= wy && lz <= wz;
@@ -301,7 +344,7 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
         for (int it = 0; it < 64; ++it) {
             const int ly = (lane >> 4) + 4 * (it & 3) - 2, lz = (it >> 2) - 2;
             if (!okx || ly > wy + 1 || lz > wz + 1) continue;
-            const uint32_t v = encode4(v64[it], F);
+            const uint32_t v = encode(v64[it]);
             if (lx >= -1 && ly >= -1 && lz >= -1)
                 lat[(lz + 1) * kPP + (ly + 1) * kP + (lx + 1)] = (uint8_t)v;
             if (lx <= wx && ly <= wy && lz <= wz)
@@ -348,10 +391,11 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
     }
     int64_t dEsum = 0;
     uint32_t nacc = 0;
-    // The rounds, instantiated for folded (DROP) or full weight rows: the
-    // choice is per lattice, so each instance stays branch-free.
-    auto all_rounds = [&](auto drop_tag) {
-        constexpr bool DROP = decltype(drop_tag)::value;
+    // The rounds, instantiated for each form of the weight rows (byte-dot or
+    // full for KMAX <= 5, folded or full above): the form is per lattice, so
+    // each instance stays branch-free.
+    auto all_rounds = [&](auto mode_tag) {
+        constexpr int MODE = decltype(mode_tag)::value;
         // rounds of residue class m (corner then body) with draws uc, ub and
         // the four partner bits of sub-colours 2m, 2m+1 in b4
         auto rounds = [&](int m, uint32_t uc, uint32_t ub, uint32_t b4) {
@@ -360,9 +404,9 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
             const int ac = lane_c + (rz * kPP + ry * kP + rx);
             const int yz0 = (int)(b4 & 1u) * kP + (int)((b4 >> 1) & 1u) * kPP;
             const int yz1 = (int)((b4 >> 2) & 1u) * kP + (int)((b4 >> 3) & 1u) * kPP;
-            trial<KMAX, SMAX, 0, DROP>(lat, ac, uc, yz0, valid, s_w, s_tab, dEsum, nacc);
+            trial<KMAX, SMAX, 0, MODE>(lat, ac, uc, yz0, valid, s_w, s_tab, dEsum, nacc);
             __builtin_amdgcn_wave_barrier();
-            trial<KMAX, SMAX, 1, DROP>(lat, ac + kBodyFromCorner, ub, yz1, valid, s_w, s_tab, dEsum, nacc);
+            trial<KMAX, SMAX, 1, MODE>(lat, ac + kBodyFromCorner, ub, yz1, valid, s_w, s_tab, dEsum, nacc);
             __builtin_amdgcn_wave_barrier();
         };
         uint32_t w[4] = {base_lo, base_hi, s, (uint32_t)colour};
@@ -380,10 +424,17 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
         }
         rounds(26, w[0], w[1], (uint32_t)(yz_hi >> 40));   // bits 104 .. 107
     };
-    if (D.drop_last)
-        all_rounds(std::integral_constant<bool, true>{});
-    else
-        all_rounds(std::integral_constant<bool, false>{});
+    if constexpr (KMAX <= 5) {
+        if (D.drop_last == kWtabDot)
+            all_rounds(std::integral_constant<int, kWtabDot>{});
+        else
+            all_rounds(std::integral_constant<int, kWtabFull>{});
+    } else {
+        if (D.drop_last == kWtabDrop)
+            all_rounds(std::integral_constant<int, kWtabDrop>{});
+        else
+            all_rounds(std::integral_constant<int, kWtabFull>{});
+    }
 
     // ---- write back: corner cells 0..w, body cells -1..w-1 ----
     // Fast path (no periodic wrap along x): 8 lanes per row, each owning one

@@ -35,8 +35,19 @@ static_assert(kPP >= 15 * kP && kArr > 14 * kPP + 14 * kP + 14, "LDS array too s
 constexpr int kTab = 768;
 
 // Row of the pair-weight table for one (sigma_i, sigma_j) = (a, b):
-// W[s][p] = V_s(b, p) - V_s(a, p) for s < SMAX, p < KMAX, then a constant.
-__host__ __device__ constexpr int wrow(int kmax, int smax) { return ((smax * kmax + 1) + 3) & ~3; }
+// W[s][p] = V_s(b, p) - V_s(a, p) for s < SMAX, p < KMAX, then a constant;
+// or, in the byte-dot form (tables.cpp), 3 SMAX packed digit words and a
+// constant.  Entries per row, padded to a multiple of 4:
+__host__ __device__ constexpr int wrow_entries(int kmax, int smax)
+{
+    return (smax * kmax > 3 * smax ? smax * kmax : 3 * smax) + 1;
+}
+__host__ __device__ constexpr int wrow(int kmax, int smax) { return (wrow_entries(kmax, smax) + 3) & ~3; }
+
+// DevLattice::drop_last: the form of the weight rows (tables.cpp).
+constexpr int kWtabFull = 0;   // KMAX fields per shell
+constexpr int kWtabDrop = 1;   // KMAX-1 fields, the last species folded in
+constexpr int kWtabDot = 2;    // byte-dot digits (BCC, KMAX <= 5)
 
 // Running energy (micro-eV, int64) and accepted-swap count (uint64) of one
 // lattice, spread over kSpread slots one cache line apart: the wave of block
@@ -65,7 +76,7 @@ struct DevLattice {
     int32_t K;
     int32_t blocks_per_colour;
     int32_t lattice;         // 0 BCC, 1 FCC
-    int32_t drop_last;       // 1: weight rows fold in the last species (fields 0..KMAX-2 read)
+    int32_t drop_last;       // form of the weight rows: kWtabFull, kWtabDrop or kWtabDot
 };
 
 // One workgroup's share of a batched phase: kWavesPerGroup consecutive
@@ -122,7 +133,9 @@ void build_thresholds(double T, double* out768);
 // bias: the per-field offset the kernel packs into its histogram words
 // (16 for BCC with K <= 6, 0 for BCC with K <= 8, 32 for FCC).  Returns the
 // value of DevLattice::drop_last the rows are built for.
-int build_wtab(const int32_t* epi, int K, int S, int kmax, int smax, int bias, int32_t* out);
+// dot_ok: the byte-dot form may be used (BCC; taken when kmax <= 5 and the
+// weights have three-digit forms).
+int build_wtab(const int32_t* epi, int K, int S, int kmax, int smax, int bias, bool dot_ok, int32_t* out);
 
 // Launchers (kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_sweep_phase(int lattice, const DevLattice* d_lat, const WorkItem* d_items, int n_groups,

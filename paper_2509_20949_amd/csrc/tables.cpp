@@ -38,13 +38,62 @@ void build_thresholds(double T, double* out)
 // times the sum of the weights it reads.  Row layout: weight (s, p) at
 // s*kmax + p, the constant at smax*kmax, all modulo 2^32 (the kernel sums
 // modulo 2^32).
-int build_wtab(const int32_t* epi, int K, int S, int kmax, int smax, int bias, int32_t* out)
+//
+// Byte-dot rows (returned value kWtabDot; BCC with kmax <= 5): the kernel
+// counts species p < kmax-1 in byte p of a 32-bit word (the last species
+// in bit 31, which it masks off), forms bytes 32 + d[s][p] and takes dot
+// products of 4 signed bytes.  Each folded weight W'[s][p] = W[s][p] -
+// W[s][kmax-1] is written in three signed base-256 digits, W' = w0 + 2^8 w1
+// + 2^16 w2 with w0, w1, w2 in [-128, 127]; row entry 3s + k packs digit k
+// of W'[s][0..3] into bytes 0..3, and entry 3 smax holds the constant (the
+// bond term less 32 times the sum of the W').  Used when every W' has such
+// digits (|W'| < 2^23 - 2^15 suffices).
+static bool digits3(int64_t w, int32_t d[3])
+{
+    for (int k = 0; k < 3; ++k) {
+        const int64_t r = (int64_t)(int8_t)(uint8_t)(uint64_t)w;   // low digit in [-128, 127]
+        d[k] = (int32_t)r;
+        w = (w - r) / 256;
+    }
+    return w == 0;
+}
+
+int build_wtab(const int32_t* epi, int K, int S, int kmax, int smax, int bias, bool dot_ok, int32_t* out)
 {
     const int wr = wrow(kmax, smax);
     auto W = [&](int a, int b, int s, int p) -> int64_t {   // zero for species beyond K
         return p < K ? (int64_t)epi[(s * K + b) * K + p] - epi[(s * K + a) * K + p] : 0;
     };
-    int drop = 1;
+    if (dot_ok && kmax <= 5) {
+        bool fits = true;
+        int32_t dg[3];
+        for (int a = 0; a < K && fits; ++a)
+            for (int b = 0; b < K && fits; ++b)
+                for (int s = 0; s < S && fits; ++s)
+                    for (int p = 0; p < kmax - 1 && fits; ++p)
+                        fits = digits3(W(a, b, s, p) - W(a, b, s, kmax - 1), dg);
+        if (fits) {
+            std::memset(out, 0, sizeof(int32_t) * (size_t)kmax * kmax * wr);
+            for (int a = 0; a < K; ++a)
+                for (int b = 0; b < K; ++b) {
+                    int32_t* row = out + (size_t)(a * kmax + b) * wr;
+                    int64_t sum = 0;
+                    for (int s = 0; s < S; ++s)
+                        for (int p = 0; p < kmax - 1; ++p) {
+                            const int64_t w = W(a, b, s, p) - W(a, b, s, kmax - 1);
+                            digits3(w, dg);
+                            for (int k = 0; k < 3; ++k)
+                                row[3 * s + k] = (int32_t)((uint32_t)row[3 * s + k] | ((uint32_t)(uint8_t)dg[k] << (8 * p)));
+                            sum += w;
+                        }
+                    const int64_t corr = -((int64_t)epi[a * K + a] + epi[b * K + b] - 2 * (int64_t)epi[a * K + b]);
+                    row[3 * smax] = (int32_t)(uint32_t)(uint64_t)(corr - 32 * sum);
+                }
+            return kWtabDot;
+        }
+    }
+    // (the BCC kernels for kmax <= 5 take the byte-dot or the full rows)
+    int drop = dot_ok && kmax <= 5 ? 0 : 1;
     for (int a = 0; a < K && drop; ++a)
         for (int b = 0; b < K && drop; ++b)
             for (int s = 0; s < S && drop; ++s)
