@@ -239,10 +239,17 @@ const char* smcx_server_last_error(const smcx_server* srv);
  * smcx_threshold_table: the host table the library builds for T (768 doubles:
  * T0, T1, T2).  smcx_device_thresholds: the threshold products computed by
  * the device's FP64 unit for n energy changes (host arrays; synchronous).
+ * smcx_device_accept_bounds: for n acceptance draws u (host array), the
+ * bounds the sweep kernels use to skip the table test of Eq. (3): they
+ * accept an uphill change dE <= lo[k] and reject dE > hi[k] without the
+ * table, and evaluate the table only in between (and for u = 0); the
+ * library claims that these decisions equal the table test's (host arrays;
+ * synchronous).
  * smcx_device_philox: Philox4x32-10 evaluated on the device for n counters
  * (host arrays of 4n words; synchronous). */
 smcx_status smcx_threshold_table(double T_kelvin, double* out768);
 smcx_status smcx_device_thresholds(double T_kelvin, const int32_t* dE, int32_t n, double* out);
+smcx_status smcx_device_accept_bounds(double T_kelvin, const uint32_t* u, int32_t n, int32_t* lo, int32_t* hi);
 smcx_status smcx_device_philox(const uint32_t* ctr, const uint32_t key[2], int32_t n, uint32_t* out);
 
 #ifdef __cplusplus

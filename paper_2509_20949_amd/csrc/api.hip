@@ -565,7 +565,9 @@ smcx_status smcx_threshold_table(double T, double* out)
     if (!out) return fail_global(SMCX_E_INVALID, "out is NULL");
     smcx_status st = validate_T(T);
     if (st) return st;
-    build_thresholds(T, out);
+    double tab[kTab];
+    build_thresholds(T, tab);
+    std::memcpy(out, tab, sizeof(double) * 768);
     return SMCX_OK;
 }
 
@@ -590,6 +592,34 @@ smcx_status smcx_device_thresholds(double T, const int32_t* dE, int32_t n, doubl
     if (d_out) (void)hipFree(d_out);
     if (d_dE) (void)hipFree(d_dE);
     if (e != hipSuccess) return fail_global(SMCX_E_DEVICE, "device thresholds: %s", hipGetErrorString(e));
+    return SMCX_OK;
+}
+
+smcx_status smcx_device_accept_bounds(double T, const uint32_t* u, int32_t n, int32_t* lo, int32_t* hi)
+{
+    if (!u || !lo || !hi || n < 0) return fail_global(SMCX_E_INVALID, "bad argument");
+    smcx_status st = validate_T(T);
+    if (st) return st;
+    if (n == 0) return SMCX_OK;
+    double tab[kTab];
+    build_thresholds(T, tab);
+    double* d_tab = nullptr;
+    uint32_t* d_u = nullptr;
+    int32_t *d_lo = nullptr, *d_hi = nullptr;
+    hipError_t e = hipMalloc(&d_tab, sizeof(tab));
+    if (e == hipSuccess) e = hipMalloc(&d_u, sizeof(uint32_t) * n);
+    if (e == hipSuccess) e = hipMalloc(&d_lo, sizeof(int32_t) * n);
+    if (e == hipSuccess) e = hipMalloc(&d_hi, sizeof(int32_t) * n);
+    if (e == hipSuccess) e = hipMemcpy(d_tab, tab, sizeof(tab), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_u, u, sizeof(uint32_t) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_accept_bounds(d_tab, d_u, n, d_lo, d_hi, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(lo, d_lo, sizeof(int32_t) * n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(hi, d_hi, sizeof(int32_t) * n, hipMemcpyDeviceToHost);
+    if (d_tab) (void)hipFree(d_tab);
+    if (d_u) (void)hipFree(d_u);
+    if (d_lo) (void)hipFree(d_lo);
+    if (d_hi) (void)hipFree(d_hi);
+    if (e != hipSuccess) return fail_global(SMCX_E_DEVICE, "device accept bounds: %s", hipGetErrorString(e));
     return SMCX_OK;
 }
 

@@ -41,11 +41,12 @@ __device__ __forceinline__ void keep(uint32_t& h) { asm("" : "+v"(h)); }
 constexpr int wplane(int kmax) { return ((kmax * kmax + 31) / 32) * 32; }
 constexpr int wplanes(int kmax, int smax) { return wrow_entries(kmax, smax); }
 
-// Fill the LDS planes from the row-major table of wrow(KMAX, SMAX) ints per row.
-template <int KMAX, int SMAX>
+// Fill the LDS planes (PS dwords apart, PS >= KMAX*KMAX) from the
+// row-major table of wrow(KMAX, SMAX) ints per row.
+template <int KMAX, int SMAX, int PS = wplane(KMAX)>
 __device__ __forceinline__ void load_wplanes(int32_t* s_w, const int32_t* wtab)
 {
-    constexpr int PS = wplane(KMAX), WR = wrow(KMAX, SMAX);
+    constexpr int WR = wrow(KMAX, SMAX);
     for (int k = threadIdx.x; k < wplanes(KMAX, SMAX) * PS; k += blockDim.x) {
         const int f = k / PS, row = k - f * PS;
         s_w[k] = row < KMAX * KMAX ? wtab[row * WR + f] : 0;
@@ -77,6 +78,26 @@ template <class T> __device__ __forceinline__ T gload(const uint8_t* p)
 template <class T> __device__ __forceinline__ void gstore(uint8_t* p, T v)
 {
     *(__attribute__((address_space(1))) T*)p = v;
+}
+
+// Bounds of the Metropolis test (Eq. (3)) for an acceptance draw u (even).
+// The exact test accepts an uphill change dE iff u < thr(dE), thr the FP64
+// table product, equal to 2^32 exp(-dE / k_B T) to a relative 1e-12.  Let x
+// be the energy with 2^32 exp(-x / k_B T) = u, x = (32 - log2 u) ln2 k_B T.
+// e below is x in FP32 from v_log_f32; over all even u > 0 the device's
+// 32 - log2(float(u)) is within 2.0e-6 of the exact value (checked
+// exhaustively), so |e - x| <= 6.3e-6 ln2 k_B T + 2^-23 x <= 2 micro-eV
+// for T <= 5000 K, and the FP32 sums e -+ M add at most 0.6 more.  Hence
+// with M = 8: every dE <= lo lies below x by more than the table's error
+// and is accepted by the exact test, every dE > hi is rejected, and only
+// lo < dE <= hi (and u = 0, where x is infinite but thr may underflow)
+// need the table.  c = ln2 k_B T in micro-eV, as a float.
+constexpr float kAcceptMargin = 8.0f;
+__device__ __forceinline__ void accept_bounds(uint32_t u, float c, int& lo, int& hi)
+{
+    const float e = fminf((32.0f - __builtin_amdgcn_logf((float)u)) * c, 1.0e9f);   // u = 0: +inf -> 1e9
+    lo = (int)(e - kAcceptMargin);   // truncation: floor where positive
+    hi = (int)(e + kAcceptMargin);
 }
 
 __device__ __forceinline__ int wrap_add(int v, int L)   // v in [-L, 2L)

@@ -58,6 +58,12 @@ constexpr int kS1Body = -kArr - (kPP + kP + 1);      // + ex + ey*kP + ez*kPP, e
 
 template <int SUB> __device__ __forceinline__ constexpr int s1base() { return SUB == 0 ? kS1Corner : kS1Body; }
 
+// Weight planes of the BCC kernel: 64 rows each, so that the row a*KMAX + b
+// of any two 3-bit codes (a lane without a site may decode a stale halo
+// byte) stays inside its plane without clamping.
+constexpr int kPlane = 64;
+static_assert(7 * kMaxK + 7 < kPlane, "weight plane too narrow");
+
 // Shell offsets inside one sublattice array.
 __device__ __forceinline__ constexpr int s2off(int k)
 {
@@ -113,11 +119,6 @@ __device__ __forceinline__ void histogram(const uint8_t* lat, int a, uint32_t (&
     }
 }
 
-// One trial: site at LDS byte ai (sublattice SUB) with its 32-bit draw u.
-// The partner is the first neighbour whose x step is the top bit of u and
-// whose y and z steps (shared by the whole round) give yz = ey*kP + ez*kPP;
-// the acceptance draw is u << 1.  Returns through dEsum / nacc; updates the
-// LDS image in place.
 // acc + sum over shells s < SMAX and fields p < NF of field(s, p) * w[s*KMAX + p],
 // modulo 2^32: field = bias + n_i - n_j read from the packed difference
 // (F = 5), or n_i - n_j from the two 4-bit fields (F = 4).  The constant may
@@ -127,7 +128,7 @@ template <int KMAX, int SMAX, int NF>
 __device__ __forceinline__ uint32_t weigh(const uint32_t (&hi)[kMaxS], const uint32_t (&hj)[kMaxS],
                                           const int32_t* w, uint32_t acc)
 {
-    constexpr int PS = wplane(KMAX);
+    constexpr int PS = kPlane;
 #pragma unroll
     for (int s = 0; s < SMAX; ++s) {
         if constexpr (Field<KMAX>::F == 5) {
@@ -145,14 +146,22 @@ __device__ __forceinline__ uint32_t weigh(const uint32_t (&hi)[kMaxS], const uin
     return acc;
 }
 
+// One trial: site at LDS byte ai (sublattice SUB) with its 32-bit draw u.
+// The partner is the first neighbour whose x step is the top bit of u and
+// whose y and z steps (shared by the whole round) give yz = ey*kP + ez*kPP;
+// the acceptance draw is u << 1.  Adds the accepted energy change to the
+// lane's dEsum and the wave's accepted count to nacc (the same in every
+// lane); updates the LDS image in place.
 template <int KMAX, int SMAX, int SUB, int MODE>
 __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int yz, bool valid,
-                                      const int32_t* wtab, const double* tab, int64_t& dEsum,
+                                      const int32_t* wtab, const double* tab, float ln2kT, int64_t& dEsum,
                                       uint32_t& nacc)
 {
     constexpr int F = Field<KMAX>::F;
     constexpr bool DOT = MODE == kWtabDot;
     const uint32_t u_acc = u << 1;
+    int e_lo, e_hi;
+    accept_bounds(u_acc, ln2kT, e_lo, e_hi);   // depends on the draw only: off the critical path
     const int aj = ai + s1base<SUB>() + (int)(u >> 31) + yz;
     const uint32_t ci = lat[ai];
     const uint32_t cj = lat[aj];
@@ -167,16 +176,16 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int yz, 
     histogram<SMAX, SUB>(lat, ai, hi);
     histogram<SMAX, 1 - SUB>(lat, aj, hj);
 
-    // lanes without a site in this round may decode stale halo bytes: clamp
-    // the row index into the table (their result is discarded)
-    const uint32_t a = min(decode(ci), (uint32_t)(KMAX - 1)), b = min(decode(cj), (uint32_t)(KMAX - 1));
+    // (lanes without a site in this round may decode stale halo bytes: their
+    // row still lies inside the planes, and their result is discarded)
+    const uint32_t a = decode(ci), b = decode(cj);
     const int32_t* w = wtab + (a * KMAX + b);   // row (a, b) of the weight planes
     uint32_t acc;
     if constexpr (DOT) {
         // bytes 32 + n_i - n_j (bit 31, the last species, masked off) dotted
         // with the three base-256 digits of the folded weights
-        constexpr int PS = wplane(KMAX);
-        int32_t A0 = 0, A1 = 0, A2 = 0;
+        constexpr int PS = kPlane;
+        int32_t A0 = w[3 * SMAX * PS], A1 = 0, A2 = 0;   // A0 starts at the row constant
 #pragma unroll
         for (int s = 0; s < SMAX; ++s) {
             const int32_t d = (int32_t)((hi[s] - hj[s]) & 0x7fffffffu);
@@ -184,28 +193,35 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int yz, 
             A1 = __builtin_amdgcn_sdot4(d, w[(3 * s + 1) * PS], A1, false);
             A2 = __builtin_amdgcn_sdot4(d, w[(3 * s + 2) * PS], A2, false);
         }
-        acc = (uint32_t)w[3 * SMAX * PS] + (uint32_t)A0 + ((uint32_t)A1 << 8) + ((uint32_t)A2 << 16);
+        acc = (uint32_t)A0 + ((uint32_t)A1 << 8) + ((uint32_t)A2 << 16);
     } else {
         // With kWtabDrop the rows fold in the last species, whose count
         // differences follow from the others (both sites have the same
         // number of neighbours per shell): only fields 0 .. KMAX-2 are read.
         acc = weigh<KMAX, SMAX, MODE == kWtabDrop ? KMAX - 1 : KMAX>(hi, hj, w,
-                                                                      (uint32_t)w[SMAX * KMAX * wplane(KMAX)]);
+                                                                      (uint32_t)w[SMAX * KMAX * kPlane]);
     }
     const int32_t dE = (int32_t)acc;
 
-    // Metropolis decision, Eq. (3), on the FP64 byte tables.
-    const int e = dE < 1 ? 1 : (dE > (1 << 24) - 1 ? (1 << 24) - 1 : dE);
-    const double thr = (tab[512 + (e >> 16)] * tab[256 + ((e >> 8) & 255)]) * tab[e & 255];
-    const bool up_ok = (dE < (1 << 24)) & ((double)u_acc < thr);
+    // Metropolis decision, Eq. (3): the exact test on the FP64 byte tables,
+    // evaluated only when a lane's dE falls between its bounds (a
+    // wave-uniform branch, taken by a few percent of the rounds).
+    const bool up = (dE > 0) & (dE < (1 << 24));
+    const bool near = up & (((dE > e_lo) & (dE <= e_hi)) | (u_acc == 0u));
+    bool up_ok = up & (dE <= e_lo);
+    if (__ballot(near)) {
+        const int e = dE < 1 ? 1 : (dE > (1 << 24) - 1 ? (1 << 24) - 1 : dE);
+        const double thr = (tab[512 + (e >> 16)] * tab[256 + ((e >> 8) & 255)]) * tab[e & 255];
+        up_ok = near ? (double)u_acc < thr : up_ok;
+    }
     const bool accept = valid & (ci != cj) & ((dE <= 0) | up_ok);
     // Both bytes are stored by every lane (unchanged unless accepted): no
     // two lanes of a round touch the same byte, and a branch-free trial
     // keeps the whole round in one basic block for the scheduler.
     lat[ai] = (uint8_t)(accept ? cj : ci);
     lat[aj] = (uint8_t)(accept ? ci : cj);
-    dEsum += accept ? (int64_t)dE : 0;
-    nacc += accept ? 1u : 0u;
+    dEsum += (int64_t)(accept ? dE : 0);
+    nacc += (uint32_t)__popcll(__ballot(accept));   // wave-uniform: counted on the scalar unit
 }
 
 // ---------------------------------------------------------------------------
@@ -216,7 +232,7 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
 {
     constexpr int F = Field<KMAX>::F;
     __shared__ double s_tab[kTab];
-    __shared__ int32_t s_w[wplanes(KMAX, SMAX) * wplane(KMAX)];
+    __shared__ int32_t s_w[wplanes(KMAX, SMAX) * kPlane];
     __shared__ __attribute__((aligned(16))) uint8_t s_lat[kWavesPerGroup * kWaveLds];
 
     const int wave = wave_id();
@@ -235,7 +251,7 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
         ti = ti < 0 ? 0 : (ti >= D.n_tabs ? D.n_tabs - 1 : ti);
         const double* tab = D.tabs + (size_t)ti * kTab;
         for (int k = threadIdx.x; k < kTab; k += blockDim.x) s_tab[k] = tab[k];
-        load_wplanes<KMAX, SMAX>(s_w, D.wtab);
+        load_wplanes<KMAX, SMAX, kPlane>(s_w, D.wtab);
     }
     __syncthreads();
 
@@ -391,6 +407,7 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
     }
     int64_t dEsum = 0;
     uint32_t nacc = 0;
+    const float ln2kT = (float)s_tab[kTabLn2kT];
     // The rounds, instantiated for each form of the weight rows (byte-dot or
     // full for KMAX <= 5, folded or full above): the form is per lattice, so
     // each instance stays branch-free.
@@ -404,9 +421,9 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
             const int ac = lane_c + (rz * kPP + ry * kP + rx);
             const int yz0 = (int)(b4 & 1u) * kP + (int)((b4 >> 1) & 1u) * kPP;
             const int yz1 = (int)((b4 >> 2) & 1u) * kP + (int)((b4 >> 3) & 1u) * kPP;
-            trial<KMAX, SMAX, 0, MODE>(lat, ac, uc, yz0, valid, s_w, s_tab, dEsum, nacc);
+            trial<KMAX, SMAX, 0, MODE>(lat, ac, uc, yz0, valid, s_w, s_tab, ln2kT, dEsum, nacc);
             __builtin_amdgcn_wave_barrier();
-            trial<KMAX, SMAX, 1, MODE>(lat, ac + kBodyFromCorner, ub, yz1, valid, s_w, s_tab, dEsum, nacc);
+            trial<KMAX, SMAX, 1, MODE>(lat, ac + kBodyFromCorner, ub, yz1, valid, s_w, s_tab, ln2kT, dEsum, nacc);
             __builtin_amdgcn_wave_barrier();
         };
         uint32_t w[4] = {base_lo, base_hi, s, (uint32_t)colour};
@@ -551,13 +568,12 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
 
     // ---- wavefront reduction of the energy change and accepted count ----
     uint64_t sum = (uint64_t)dEsum;
-    uint32_t cnt = nacc;
+    const uint32_t cnt = nacc;   // already the wave's total
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
         const uint32_t lo = __shfl_xor((uint32_t)sum, o, kWave);
         const uint32_t hi = __shfl_xor((uint32_t)(sum >> 32), o, kWave);
         sum += (uint64_t)lo | ((uint64_t)hi << 32);
-        cnt += __shfl_xor(cnt, o, kWave);
     }
     if (lane == 0) {
         unsigned long long* slot = (unsigned long long*)(D.state + (f % kSpread) * kSlotWords);
@@ -715,6 +731,25 @@ hipError_t launch_thresholds(const double* d_tab, const int32_t* d_dE, int n, do
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(thresholds_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, d_tab, d_dE, n, d_out);
+    return hipGetLastError();
+}
+
+__global__ void accept_bounds_kernel(const double* __restrict__ tab, const uint32_t* __restrict__ u, int n,
+                                     int32_t* __restrict__ lo, int32_t* __restrict__ hi)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int a, b;
+    accept_bounds(u[k], (float)tab[kTabLn2kT], a, b);
+    lo[k] = a;
+    hi[k] = b;
+}
+
+hipError_t launch_accept_bounds(const double* d_tab, const uint32_t* d_u, int n, int32_t* d_lo, int32_t* d_hi,
+                                hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(accept_bounds_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, d_tab, d_u, n, d_lo, d_hi);
     return hipGetLastError();
 }
 

@@ -31,8 +31,10 @@ constexpr int kArr = 3460;           // bytes per sublattice array (last byte 14
 constexpr int kWaveLds = 2 * kArr + 4;
 static_assert(kPP >= 15 * kP && kArr > 14 * kPP + 14 * kP + 14, "LDS array too small");
 
-// Threshold tables: T0 | T1 | T2, 256 doubles each.
-constexpr int kTab = 768;
+// Threshold tables: T0 | T1 | T2, 256 doubles each, then ln(2) k_B T in
+// micro-eV (the scale of the acceptance bounds, device_common.h) and a pad.
+constexpr int kTab = 770;
+constexpr int kTabLn2kT = 768;
 
 // Row of the pair-weight table for one (sigma_i, sigma_j) = (a, b):
 // W[s][p] = V_s(b, p) - V_s(a, p) for s < SMAX, p < KMAX, then a constant;
@@ -129,7 +131,7 @@ __host__ __device__ inline int axis_blocks(int L, int B)
 }
 
 // Host helpers (tables.cpp).
-void build_thresholds(double T, double* out768);
+void build_thresholds(double T, double* out /* kTab */);
 // bias: the per-field offset the kernel packs into its histogram words
 // (16 for BCC with K <= 6, 0 for BCC with K <= 8, 32 for FCC).  Returns the
 // value of DevLattice::drop_last the rows are built for.
@@ -148,6 +150,8 @@ hipError_t launch_pair_counts_fcc(const uint8_t* species, const int32_t L[3], in
                                   unsigned long long* d_counts, hipStream_t stream);
 hipError_t launch_species_max(const uint8_t* species, size_t n, unsigned int* d_max, hipStream_t stream);
 hipError_t launch_thresholds(const double* d_tab, const int32_t* d_dE, int n, double* d_out, hipStream_t stream);
+hipError_t launch_accept_bounds(const double* d_tab, const uint32_t* d_u, int n, int32_t* d_lo, int32_t* d_hi,
+                                hipStream_t stream);
 hipError_t launch_philox(const uint32_t* d_ctr, uint32_t k0, uint32_t k1, int n, uint32_t* d_out,
                          hipStream_t stream);
 

@@ -19,6 +19,8 @@ void build_thresholds(double T, double* out)
         out[256 + l] = std::exp(-((double)(l * 256) * beta));
         out[512 + l] = std::ldexp(std::exp(-((double)(l * 65536) * beta)), 32);
     }
+    out[kTabLn2kT] = std::log(2.0) * kB * T;
+    out[kTabLn2kT + 1] = 0.0;
 }
 
 // Pair-weight rows for the swap of species a (at site i) and b (at its

@@ -91,6 +91,7 @@ def lib():
     _sig(L, "smcx_threshold_table", st, [dbl, _P(dbl)])
     _sig(L, "smcx_device_thresholds", st, [dbl, _P(i32), i32, _P(dbl)])
     _sig(L, "smcx_device_philox", st, [_P(C.c_uint32), _P(C.c_uint32), i32, _P(C.c_uint32)])
+    _sig(L, "smcx_device_accept_bounds", st, [dbl, _P(C.c_uint32), i32, _P(i32), _P(i32)])
     _lib = L
     return L
 
@@ -220,6 +221,16 @@ def smcx_device_thresholds(T_kelvin: float, dE) -> np.ndarray:
     out = np.zeros(d.size, np.float64)
     _check(lib().smcx_device_thresholds(float(T_kelvin), _ptr(d, C.c_int32), int(d.size), _ptr(out, C.c_double)))
     return out
+
+
+def smcx_device_accept_bounds(T_kelvin: float, u):
+    """(lo, hi) per acceptance draw, as the sweep kernels compute them."""
+    v = np.ascontiguousarray(u, dtype=np.uint32)
+    lo = np.zeros(v.size, np.int32)
+    hi = np.zeros(v.size, np.int32)
+    _check(lib().smcx_device_accept_bounds(float(T_kelvin), _ptr(v, C.c_uint32), int(v.size), _ptr(lo, C.c_int32),
+                                           _ptr(hi, C.c_int32)))
+    return lo, hi
 
 
 def smcx_device_philox(ctr, key) -> np.ndarray:

@@ -102,6 +102,35 @@ def test_device_fp64_threshold_products(smcx, orc, T):
     assert got.tobytes() == want.tobytes()
 
 
+@pytest.mark.parametrize("T", [1.0, 250.0, 800.0, 2000.0, 5000.0])
+def test_device_accept_bounds_agree_with_table_test(smcx, orc, T):
+    """The kernels decide an uphill swap without the threshold tables when dE
+    lies outside (lo, hi]: every dE <= lo must pass the exact test of
+    Eq. (3) (u < thr(dE) on the oracle's tables) and every dE > hi fail it.
+    Checked next to both bounds for random and edge-case draws; the band in
+    between stays a few micro-eV wide."""
+    note(f"accept bounds T={T}")
+    rng = np.random.default_rng(int(T) + 7)
+    u = np.concatenate([rng.integers(1, 1 << 31, 60000) * 2,
+                        [2, 4, 6, 8, 1 << 31, (1 << 32) - 2, (1 << 32) - 4, 3 << 30]]).astype(np.uint32)
+    lo, hi = smcx.smcx_device_accept_bounds(T, u)
+    tab = orc.thresholds(T)
+
+    def passes(dE):   # exact test for 0 < dE < 2^24, vectorised like the oracle's expression
+        e = dE.astype(np.int64)
+        thr = (tab[512 + (e >> 16)] * tab[256 + ((e >> 8) & 255)]) * tab[e & 255]
+        return u.astype(np.float64) < thr
+
+    assert np.all(hi >= lo) and np.all(hi - lo <= 2 * 8 + 1)
+    for k in range(4):
+        d = lo.astype(np.int64) - k
+        m = (d > 0) & (d < (1 << 24))
+        assert np.all(passes(np.clip(d, 1, (1 << 24) - 1))[m]), (T, k)
+        d = hi.astype(np.int64) + 1 + k
+        m = (d > 0) & (d < (1 << 24))
+        assert not np.any(passes(np.clip(d, 1, (1 << 24) - 1))[m]), (T, k)
+
+
 def test_config1_parity_every_sweep(smcx, orc):
     job = W.config1(n_sweeps=100)
     run_parity(smcx, orc, job, (12, 12, 12), 100)
