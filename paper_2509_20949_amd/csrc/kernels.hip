@@ -58,6 +58,14 @@ constexpr int kS1Body = -kArr - (kPP + kP + 1);      // + ex + ey*kP + ez*kPP, e
 
 template <int SUB> __device__ __forceinline__ constexpr int s1base() { return SUB == 0 ? kS1Corner : kS1Body; }
 
+// Waves per SIMD the BCC sweep kernel is compiled for (registers); LDS
+// (4 block images and the weight planes per workgroup) admits 5 workgroups
+// of 4 waves per CU.
+constexpr int kSweepWavesPerSimd = 5;
+// Rows whose loads a lane issues together when staging a block (registers
+// bound it: three words per row on the fast path).
+constexpr int kStageBatch = 16;
+
 // Weight planes of the BCC kernel: 64 rows each, so that the row a*KMAX + b
 // of any two 3-bit codes (a lane without a site may decode a stale halo
 // byte) stays inside its plane without clamping.
@@ -211,7 +219,9 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int yz, 
     bool up_ok = up & (dE <= e_lo);
     if (__ballot(near)) {
         const int e = dE < 1 ? 1 : (dE > (1 << 24) - 1 ? (1 << 24) - 1 : dE);
-        const double thr = (tab[512 + (e >> 16)] * tab[256 + ((e >> 8) & 255)]) * tab[e & 255];
+        const uint8_t* tb = (const uint8_t*)tab;   // global memory (L2-resident)
+        const double thr = (gload<double>(tb + 8 * (512 + (e >> 16))) * gload<double>(tb + 8 * (256 + ((e >> 8) & 255)))) *
+                           gload<double>(tb + 8 * (e & 255));
         up_ok = near ? (double)u_acc < thr : up_ok;
     }
     const bool accept = valid & (ci != cj) & ((dE <= 0) | up_ok);
@@ -226,12 +236,11 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int yz, 
 
 // ---------------------------------------------------------------------------
 template <int KMAX, int SMAX>
-__global__ __launch_bounds__(kWave * kWavesPerGroup)
+__global__ __launch_bounds__(kWave * kWavesPerGroup) __attribute__((amdgpu_waves_per_eu(kSweepWavesPerSimd)))
 void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __restrict__ items,
                         int t, int colour)
 {
     constexpr int F = Field<KMAX>::F;
-    __shared__ double s_tab[kTab];
     __shared__ int32_t s_w[wplanes(KMAX, SMAX) * kPlane];
     __shared__ __attribute__((aligned(16))) uint8_t s_lat[kWavesPerGroup * kWaveLds];
 
@@ -245,15 +254,14 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
     const DevLattice& D = lats[li];
     const uint32_t s = D.sweep0 + (uint32_t)t;
 
-    // per-workgroup tables
-    {
-        int ti = (int)(s - D.tab_s0);
-        ti = ti < 0 ? 0 : (ti >= D.n_tabs ? D.n_tabs - 1 : ti);
-        const double* tab = D.tabs + (size_t)ti * kTab;
-        for (int k = threadIdx.x; k < kTab; k += blockDim.x) s_tab[k] = tab[k];
-        load_wplanes<KMAX, SMAX, kPlane>(s_w, D.wtab);
-    }
+    // Weight planes in LDS; the threshold tables of sweep s stay in global
+    // memory (read only for the few draws whose decision needs them), which
+    // leaves LDS for five workgroups per CU.
+    load_wplanes<KMAX, SMAX, kPlane>(s_w, D.wtab);
     __syncthreads();
+    int ti = (int)(s - D.tab_s0);
+    ti = ti < 0 ? 0 : (ti >= D.n_tabs ? D.n_tabs - 1 : ti);
+    const double* g_tab = D.tabs + (size_t)ti * kTab;
 
     f += wave;
     if (f >= D.blocks_per_colour) return;   // no later barrier
@@ -315,30 +323,35 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
             const int ly = min((lane >> 3) - 2 + 8 * h, wy + 1);
             gyrow[h] = (uint32_t)wrap_add(gy0 + ly, Ly);
         }
-        uint32_t q0[32], q1[32], al[32];
 #pragma unroll
-        for (int it = 0; it < 32; ++it) {
-            const int lz = min((it >> 1) - 2, wz + 1);
-            const uint32_t gz = (uint32_t)wrap_add(gz0 + lz, Lz), gy = gyrow[it & 1];
-            const size_t row = narrow ? (size_t)(__umul24(gz, LxLy) + __umul24(gy, (uint32_t)Lx))
-                                      : ((size_t)gz * (uint32_t)Ly + gy) * (uint32_t)Lx;
-            const size_t at = 2 * (row + (size_t)(gx0 + lxa));     // byte of corner(lxa)
-            q0[it] = gload<uint32_t>(g + (at & ~(size_t)3));
-            q1[it] = gload<uint32_t>(g + ((at + 2) & ~(size_t)3));
-            al[it] = (uint32_t)at & 2u;
-        }
+        for (int it0 = 0; it0 < 32; it0 += kStageBatch) {
+            uint32_t q0[kStageBatch], q1[kStageBatch], al[kStageBatch];
 #pragma unroll
-        for (int it = 0; it < 32; ++it) {
-            const int ly = (lane >> 3) - 2 + 8 * (it & 1), lz = (it >> 1) - 2;
-            if (!lane_ok || ly > wy + 1 || lz > wz + 1) continue;
-            const uint32_t v = encode(__builtin_amdgcn_alignbyte(q1[it], q0[it], al[it]));
-            const int crow = (lz + 1) * kPP + (ly + 1) * kP + (lx0 + 1);
-            const int brow = kArr + (lz + 2) * kPP + (ly + 2) * kP + (lx0 + 2);
-            const bool cy = ly >= -1 && lz >= -1, by = ly <= wy && lz <= wz;
-            if (cy && c0) lat[crow] = (uint8_t)v;
-            if (cy && c1) lat[crow + 1] = (uint8_t)(v >> 16);
-            if (by && b0) lat[brow] = (uint8_t)(v >> 8);
-            if (by && b1) lat[brow + 1] = (uint8_t)(v >> 24);
+            for (int u = 0; u < kStageBatch; ++u) {
+                const int it = it0 + u;
+                const int lz = min((it >> 1) - 2, wz + 1);
+                const uint32_t gz = (uint32_t)wrap_add(gz0 + lz, Lz), gy = gyrow[it & 1];
+                const size_t row = narrow ? (size_t)(__umul24(gz, LxLy) + __umul24(gy, (uint32_t)Lx))
+                                          : ((size_t)gz * (uint32_t)Ly + gy) * (uint32_t)Lx;
+                const size_t at = 2 * (row + (size_t)(gx0 + lxa));     // byte of corner(lxa)
+                q0[u] = gload<uint32_t>(g + (at & ~(size_t)3));
+                q1[u] = gload<uint32_t>(g + ((at + 2) & ~(size_t)3));
+                al[u] = (uint32_t)at & 2u;
+            }
+#pragma unroll
+            for (int u = 0; u < kStageBatch; ++u) {
+                const int it = it0 + u;
+                const int ly = (lane >> 3) - 2 + 8 * (it & 1), lz = (it >> 1) - 2;
+                if (!lane_ok || ly > wy + 1 || lz > wz + 1) continue;
+                const uint32_t v = encode(__builtin_amdgcn_alignbyte(q1[u], q0[u], al[u]));
+                const int crow = (lz + 1) * kPP + (ly + 1) * kP + (lx0 + 1);
+                const int brow = kArr + (lz + 2) * kPP + (ly + 2) * kP + (lx0 + 2);
+                const bool cy = ly >= -1 && lz >= -1, by = ly <= wy && lz <= wz;
+                if (cy && c0) lat[crow] = (uint8_t)v;
+                if (cy && c1) lat[crow + 1] = (uint8_t)(v >> 16);
+                if (by && b0) lat[brow] = (uint8_t)(v >> 8);
+                if (by && b1) lat[brow + 1] = (uint8_t)(v >> 24);
+            }
         }
     } else {
         // a periodic wrap along x: one cell (two bytes) per lane, rows
@@ -348,23 +361,28 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
         const int lx = (lane & 15) - 2;
         const bool okx = lx <= wx + 1;
         const int gx = wrap_add(gx0 + (okx ? lx : -2), Lx);
-        uint32_t v64[64];
 #pragma unroll
-        for (int it = 0; it < 64; ++it) {
-            const int ly = min((lane >> 4) + 4 * (it & 3) - 2, wy + 1), lz = min((it >> 2) - 2, wz + 1);
-            const int gy = wrap_add(gy0 + ly, Ly), gz = wrap_add(gz0 + lz, Lz);
-            const size_t cell = ((size_t)gz * Ly + gy) * Lx + gx;
-            v64[it] = gload<uint16_t>(g + 2 * cell);
-        }
+        for (int it0 = 0; it0 < 64; it0 += 2 * kStageBatch) {
+            uint32_t v2[2 * kStageBatch];
 #pragma unroll
-        for (int it = 0; it < 64; ++it) {
-            const int ly = (lane >> 4) + 4 * (it & 3) - 2, lz = (it >> 2) - 2;
-            if (!okx || ly > wy + 1 || lz > wz + 1) continue;
-            const uint32_t v = encode(v64[it]);
-            if (lx >= -1 && ly >= -1 && lz >= -1)
-                lat[(lz + 1) * kPP + (ly + 1) * kP + (lx + 1)] = (uint8_t)v;
-            if (lx <= wx && ly <= wy && lz <= wz)
-                lat[kArr + (lz + 2) * kPP + (ly + 2) * kP + (lx + 2)] = (uint8_t)(v >> 8);
+            for (int u = 0; u < 2 * kStageBatch; ++u) {
+                const int it = it0 + u;
+                const int ly = min((lane >> 4) + 4 * (it & 3) - 2, wy + 1), lz = min((it >> 2) - 2, wz + 1);
+                const int gy = wrap_add(gy0 + ly, Ly), gz = wrap_add(gz0 + lz, Lz);
+                const size_t cell = ((size_t)gz * Ly + gy) * Lx + gx;
+                v2[u] = gload<uint16_t>(g + 2 * cell);
+            }
+#pragma unroll
+            for (int u = 0; u < 2 * kStageBatch; ++u) {
+                const int it = it0 + u;
+                const int ly = (lane >> 4) + 4 * (it & 3) - 2, lz = (it >> 2) - 2;
+                if (!okx || ly > wy + 1 || lz > wz + 1) continue;
+                const uint32_t v = encode(v2[u]);
+                if (lx >= -1 && ly >= -1 && lz >= -1)
+                    lat[(lz + 1) * kPP + (ly + 1) * kP + (lx + 1)] = (uint8_t)v;
+                if (lx <= wx && ly <= wy && lz <= wz)
+                    lat[kArr + (lz + 2) * kPP + (ly + 2) * kP + (lx + 2)] = (uint8_t)(v >> 8);
+            }
         }
     }
 
@@ -407,7 +425,7 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
     }
     int64_t dEsum = 0;
     uint32_t nacc = 0;
-    const float ln2kT = (float)s_tab[kTabLn2kT];
+    const float ln2kT = (float)g_tab[kTabLn2kT];
     // The rounds, instantiated for each form of the weight rows (byte-dot or
     // full for KMAX <= 5, folded or full above): the form is per lattice, so
     // each instance stays branch-free.
@@ -421,9 +439,9 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
             const int ac = lane_c + (rz * kPP + ry * kP + rx);
             const int yz0 = (int)(b4 & 1u) * kP + (int)((b4 >> 1) & 1u) * kPP;
             const int yz1 = (int)((b4 >> 2) & 1u) * kP + (int)((b4 >> 3) & 1u) * kPP;
-            trial<KMAX, SMAX, 0, MODE>(lat, ac, uc, yz0, valid, s_w, s_tab, ln2kT, dEsum, nacc);
+            trial<KMAX, SMAX, 0, MODE>(lat, ac, uc, yz0, valid, s_w, g_tab, ln2kT, dEsum, nacc);
             __builtin_amdgcn_wave_barrier();
-            trial<KMAX, SMAX, 1, MODE>(lat, ac + kBodyFromCorner, ub, yz1, valid, s_w, s_tab, ln2kT, dEsum, nacc);
+            trial<KMAX, SMAX, 1, MODE>(lat, ac + kBodyFromCorner, ub, yz1, valid, s_w, g_tab, ln2kT, dEsum, nacc);
             __builtin_amdgcn_wave_barrier();
         };
         uint32_t w[4] = {base_lo, base_hi, s, (uint32_t)colour};
