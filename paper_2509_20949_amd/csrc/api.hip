@@ -271,7 +271,8 @@ double temperature_of(const smcx_ctx* c, uint64_t s)
 
 smcx_status enqueue_sweeps(smcx_ctx* c, int32_t n)
 {
-    const int groups = (c->h_lat.blocks_per_colour + kWavesPerGroup - 1) / kWavesPerGroup;
+    const int wpg = waves_per_group(c->h_lat.lattice);
+    const int groups = (c->h_lat.blocks_per_colour + wpg - 1) / wpg;
     for (int32_t k = 0; k < n; ++k) {
         const uint32_t s = (uint32_t)(c->sweeps + (uint64_t)k);
         for (int col = 0; col < 8; ++col) {

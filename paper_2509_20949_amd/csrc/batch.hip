@@ -159,9 +159,10 @@ smcx_status smcx_batch_create(int32_t n, const smcx_desc* descs, const uint8_t* 
         L.sweep0 = 0;
         L.tab_s0 = 0;
         L.n_tabs = 1;
-        b->groups[r] = (L.blocks_per_colour + kWavesPerGroup - 1) / kWavesPerGroup;
+        const int wpg = waves_per_group(L.lattice);
+        b->groups[r] = (L.blocks_per_colour + wpg - 1) / wpg;
         b->first_static[r] = (int32_t)items.size();
-        for (int g = 0; g < b->groups[r]; ++g) items.push_back(WorkItem{r, g * kWavesPerGroup});
+        for (int g = 0; g < b->groups[r]; ++g) items.push_back(WorkItem{r, g * wpg});
 
         smcx_ctx* v = new (std::nothrow) smcx_ctx();
         if (!v) { st = bfail(b, SMCX_E_NOMEM, "host allocation failed"); break; }
@@ -247,7 +248,8 @@ smcx_status smcx_batch_run(smcx_batch* b, const int32_t* n_sweeps)
         std::vector<int32_t> prefix_end(b->n);   // items of order[0..k]
         for (int k = 0; k < b->n; ++k) {
             const int r = order[k];
-            for (int g = 0; g < b->groups[r]; ++g) items.push_back(WorkItem{r, g * kWavesPerGroup});
+            const int wpg = waves_per_group(b->h_lats[r].lattice);
+            for (int g = 0; g < b->groups[r]; ++g) items.push_back(WorkItem{r, g * wpg});
             prefix_end[k] = (int32_t)items.size();
         }
         if (!items.empty()) {

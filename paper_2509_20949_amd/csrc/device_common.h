@@ -84,7 +84,7 @@ template <class T> __device__ __forceinline__ void gstore(uint8_t* p, T v)
 // The exact test accepts an uphill change dE iff u < thr(dE), thr the FP64
 // table product, equal to 2^32 exp(-dE / k_B T) to a relative 1e-12.  Let x
 // be the energy with 2^32 exp(-x / k_B T) = u, x = (32 - log2 u) ln2 k_B T.
-// e below is x in FP32 from v_log_f32; over all even u > 0 the device's
+// e below is x in FP32 from v_log_f32; over all u > 0 the device's
 // 32 - log2(float(u)) is within 2.0e-6 of the exact value (checked
 // exhaustively), so |e - x| <= 6.3e-6 ln2 k_B T + 2^-23 x <= 2 micro-eV
 // for T <= 5000 K, and the FP32 sums e -+ M add at most 0.6 more.  Hence

@@ -103,8 +103,11 @@ constexpr uint32_t kBias = 32u * (1u | 1u << 6 | 1u << 12 | 1u << 18 | 1u << 24)
 // set = +1), acceptance draw u_acc.
 template <int SMAX, int B, int BP>
 __device__ __forceinline__ void trial(uint8_t* lat, int ai, int signs, uint32_t u_acc, bool valid, bool drop,
-                                      const int32_t* wtab, const double* tab, int64_t& dEsum, uint32_t& nacc)
+                                      const int32_t* wtab, const double* tab, float ln2kT, int64_t& dEsum,
+                                      uint32_t& nacc)
 {
+    int e_lo, e_hi;
+    accept_bounds(u_acc, ln2kT, e_lo, e_hi);   // depends on the draw only
     constexpr int PS = wplane(KMAXF);
     constexpr int a1 = axis1(B, BP), a2 = axis2(B, BP);
     const int bit1 = signs & 1, bit2 = (signs >> 1) & 1;
@@ -137,27 +140,37 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, int signs, uint32_t 
         }
     }
     const int32_t dE = (int32_t)acc;
-    const int e = dE < 1 ? 1 : (dE > (1 << 24) - 1 ? (1 << 24) - 1 : dE);
-    const double thr = (tab[512 + (e >> 16)] * tab[256 + ((e >> 8) & 255)]) * tab[e & 255];
-    const bool up_ok = (dE < (1 << 24)) & ((double)u_acc < thr);
+    // Metropolis decision, Eq. (3): the exact table test (tables in global
+    // memory) only for lanes between their bounds
+    const bool up = (dE > 0) & (dE < (1 << 24));
+    const bool near = up & (((dE > e_lo) & (dE <= e_hi)) | (u_acc == 0u));
+    bool up_ok = up & (dE <= e_lo);
+    if (__ballot(near)) {
+        const int e = dE < 1 ? 1 : (dE > (1 << 24) - 1 ? (1 << 24) - 1 : dE);
+        const uint8_t* tb = (const uint8_t*)tab;
+        const double thr = (gload<double>(tb + 8 * (512 + (e >> 16))) * gload<double>(tb + 8 * (256 + ((e >> 8) & 255)))) *
+                           gload<double>(tb + 8 * (e & 255));
+        up_ok = near ? (double)u_acc < thr : up_ok;
+    }
     const bool accept = valid & (ci != cj) & ((dE <= 0) | up_ok);
     // both bytes stored by every lane (unchanged unless accepted): no two
     // lanes of a round touch the same byte
     lat[ai] = (uint8_t)(accept ? cj : ci);
     lat[aj] = (uint8_t)(accept ? ci : cj);
-    dEsum += accept ? (int64_t)dE : 0;
-    nacc += accept ? 1u : 0u;
+    dEsum += (int64_t)(accept ? dE : 0);
+    nacc += (uint32_t)__popcll(__ballot(accept));   // wave-uniform
 }
 
 // Partner sublattice BP (a wave-uniform value) selects one instantiation.
 template <int SMAX, int B>
 __device__ __forceinline__ void trial_any(int bp, uint8_t* lat, int ai, int signs, uint32_t u_acc, bool valid, bool drop,
-                                          const int32_t* wtab, const double* tab, int64_t& dEsum, uint32_t& nacc)
+                                          const int32_t* wtab, const double* tab, float ln2kT, int64_t& dEsum,
+                                          uint32_t& nacc)
 {
-    if constexpr (B != 0) { if (bp == 0) { trial<SMAX, B, 0>(lat, ai, signs, u_acc, valid, drop, wtab, tab, dEsum, nacc); return; } }
-    if constexpr (B != 1) { if (bp == 1) { trial<SMAX, B, 1>(lat, ai, signs, u_acc, valid, drop, wtab, tab, dEsum, nacc); return; } }
-    if constexpr (B != 2) { if (bp == 2) { trial<SMAX, B, 2>(lat, ai, signs, u_acc, valid, drop, wtab, tab, dEsum, nacc); return; } }
-    if constexpr (B != 3) { if (bp == 3) { trial<SMAX, B, 3>(lat, ai, signs, u_acc, valid, drop, wtab, tab, dEsum, nacc); return; } }
+    if constexpr (B != 0) { if (bp == 0) { trial<SMAX, B, 0>(lat, ai, signs, u_acc, valid, drop, wtab, tab, ln2kT, dEsum, nacc); return; } }
+    if constexpr (B != 1) { if (bp == 1) { trial<SMAX, B, 1>(lat, ai, signs, u_acc, valid, drop, wtab, tab, ln2kT, dEsum, nacc); return; } }
+    if constexpr (B != 2) { if (bp == 2) { trial<SMAX, B, 2>(lat, ai, signs, u_acc, valid, drop, wtab, tab, ln2kT, dEsum, nacc); return; } }
+    if constexpr (B != 3) { if (bp == 3) { trial<SMAX, B, 3>(lat, ai, signs, u_acc, valid, drop, wtab, tab, ln2kT, dEsum, nacc); return; } }
 }
 
 template <int B>
@@ -190,32 +203,30 @@ __device__ __forceinline__ int lds_index(int b, int lx, int ly, int lz)
 }  // namespace fcc
 
 template <int SMAX>
-__global__ __launch_bounds__(kWave * kWavesPerGroup)
+__global__ __launch_bounds__(kWave * kWavesPerGroupFcc)
 void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem* __restrict__ items, int t,
                             int colour)
 {
     using namespace fcc;
-    __shared__ double s_tab[kTab];
     __shared__ int32_t s_w[wplanes(KMAXF, SMAX) * wplane(KMAXF)];
-    __shared__ __attribute__((aligned(16))) uint8_t s_lat[kWavesPerGroup * kWaveLdsF];
+    __shared__ __attribute__((aligned(16))) uint8_t s_lat[kWavesPerGroupFcc * kWaveLdsF];
 
     const int wave = wave_id();
     const int lane = threadIdx.x % kWave;
-    int li = 0, f = blockIdx.x * kWavesPerGroup;
+    int li = 0, f = blockIdx.x * kWavesPerGroupFcc;
     if (items) {
         li = items[blockIdx.x].lattice;
         f = items[blockIdx.x].first_block;
     }
     const DevLattice& D = lats[li];
     const uint32_t s = D.sweep0 + (uint32_t)t;
-    {
-        int ti = (int)(s - D.tab_s0);
-        ti = ti < 0 ? 0 : (ti >= D.n_tabs ? D.n_tabs - 1 : ti);
-        const double* tab = D.tabs + (size_t)ti * kTab;
-        for (int k = threadIdx.x; k < kTab; k += blockDim.x) s_tab[k] = tab[k];
-        load_wplanes<KMAXF, SMAX>(s_w, D.wtab);
-    }
+    // weight planes in LDS; the threshold tables stay in global memory
+    load_wplanes<KMAXF, SMAX>(s_w, D.wtab);
     __syncthreads();
+    int ti = (int)(s - D.tab_s0);
+    ti = ti < 0 ? 0 : (ti >= D.n_tabs ? D.n_tabs - 1 : ti);
+    const double* g_tab = D.tabs + (size_t)ti * kTab;
+    const float ln2kT = (float)g_tab[kTabLn2kT];
     f += wave;
     if (f >= D.blocks_per_colour) return;   // no later barrier
 
@@ -306,16 +317,16 @@ void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem*
         philox4x32_10(ra, k0, k1);
         const int q0 = 4 * m;
         int pb = __builtin_amdgcn_readfirstlane(lat[kBpOff + q0]);
-        trial_any<SMAX, 0>(pb & 3, lat, site_addr<0>(lx, ly, lz), pb >> 2, ra[0], valid, drop, s_w, s_tab, dEsum, nacc);
+        trial_any<SMAX, 0>(pb & 3, lat, site_addr<0>(lx, ly, lz), pb >> 2, ra[0], valid, drop, s_w, g_tab, ln2kT, dEsum, nacc);
         __builtin_amdgcn_wave_barrier();
         pb = __builtin_amdgcn_readfirstlane(lat[kBpOff + q0 + 1]);
-        trial_any<SMAX, 1>(pb & 3, lat, site_addr<1>(lx, ly, lz), pb >> 2, ra[1], valid, drop, s_w, s_tab, dEsum, nacc);
+        trial_any<SMAX, 1>(pb & 3, lat, site_addr<1>(lx, ly, lz), pb >> 2, ra[1], valid, drop, s_w, g_tab, ln2kT, dEsum, nacc);
         __builtin_amdgcn_wave_barrier();
         pb = __builtin_amdgcn_readfirstlane(lat[kBpOff + q0 + 2]);
-        trial_any<SMAX, 2>(pb & 3, lat, site_addr<2>(lx, ly, lz), pb >> 2, ra[2], valid, drop, s_w, s_tab, dEsum, nacc);
+        trial_any<SMAX, 2>(pb & 3, lat, site_addr<2>(lx, ly, lz), pb >> 2, ra[2], valid, drop, s_w, g_tab, ln2kT, dEsum, nacc);
         __builtin_amdgcn_wave_barrier();
         pb = __builtin_amdgcn_readfirstlane(lat[kBpOff + q0 + 3]);
-        trial_any<SMAX, 3>(pb & 3, lat, site_addr<3>(lx, ly, lz), pb >> 2, ra[3], valid, drop, s_w, s_tab, dEsum, nacc);
+        trial_any<SMAX, 3>(pb & 3, lat, site_addr<3>(lx, ly, lz), pb >> 2, ra[3], valid, drop, s_w, g_tab, ln2kT, dEsum, nacc);
         __builtin_amdgcn_wave_barrier();
     }
 
@@ -365,13 +376,12 @@ void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem*
     }
 
     uint64_t sum = (uint64_t)dEsum;
-    uint32_t cnt = nacc;
+    const uint32_t cnt = nacc;   // already the wave's total
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
         const uint32_t lo = __shfl_xor((uint32_t)sum, o, kWave);
         const uint32_t hi = __shfl_xor((uint32_t)(sum >> 32), o, kWave);
         sum += (uint64_t)lo | ((uint64_t)hi << 32);
-        cnt += __shfl_xor(cnt, o, kWave);
     }
     if (lane == 0) {
         unsigned long long* slot = (unsigned long long*)(D.state + (f % kSpread) * kSlotWords);
@@ -384,7 +394,7 @@ hipError_t launch_sweep_phase_fcc(const DevLattice* d_lat, const WorkItem* d_ite
                                   int smax, hipStream_t stream)
 {
     if (n_groups <= 0) return hipSuccess;
-    const dim3 grid(n_groups), block(kWave * kWavesPerGroup);
+    const dim3 grid(n_groups), block(kWave * kWavesPerGroupFcc);
     switch (smax) {
     case 1: hipLaunchKernelGGL(sweep_phase_fcc_kernel<1>, grid, block, 0, stream, d_lat, d_items, t, colour); break;
     case 2: hipLaunchKernelGGL(sweep_phase_fcc_kernel<2>, grid, block, 0, stream, d_lat, d_items, t, colour); break;

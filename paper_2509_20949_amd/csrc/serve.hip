@@ -154,7 +154,8 @@ smcx_status admit(smcx_server* s, Request* q)
     L.drop_last = drop;
     L.state = s->d_states + (size_t)kStateWords * q->slot;
     L.n_tabs = 1;
-    q->groups = (L.blocks_per_colour + kWavesPerGroup - 1) / kWavesPerGroup;
+    const int wpg = waves_per_group(L.lattice);
+    q->groups = (L.blocks_per_colour + wpg - 1) / wpg;
     int64_t E0 = 0;
     st = initial_energy(s, q, &E0);
     if (st) return st;
@@ -289,7 +290,7 @@ smcx_status smcx_server_step(smcx_server* s, int32_t* n_resident, int32_t* n_wai
             if (groups.empty() || groups.back().lattice != q->desc.lattice || groups.back().kmax != q->kmax ||
                 groups.back().smax != q->smax)
                 groups.push_back(Group{q->desc.lattice, q->kmax, q->smax, items.size(), {}});
-            for (int g = 0; g < q->groups; ++g) items.push_back(WorkItem{q->slot, g * kWavesPerGroup});
+            for (int g = 0; g < q->groups; ++g) items.push_back(WorkItem{q->slot, g * waves_per_group(q->desc.lattice)});
             groups.back().ends.push_back({steps_of(q), items.size()});
         }
         if (items.size() > s->items_cap) {

@@ -11,7 +11,8 @@
 namespace smcx {
 
 constexpr int kWave = 64;            // CDNA wavefront width
-constexpr int kWavesPerGroup = 4;    // blocks (one per wave) per workgroup
+constexpr int kWavesPerGroup = 4;    // blocks (one per wave) per workgroup, BCC
+constexpr int kWavesPerGroupFcc = 2; // FCC: its 13.9 KB block images fit 5 workgroups of 2 per CU
 constexpr int kMaxBlock = 12;        // widest block: 4 x 4 x 4 cells per sub-colour round
 constexpr int kMaxK = 8;
 constexpr int kMaxS = 3;
@@ -161,6 +162,7 @@ int kmax_for(int K);
 inline int kmax_for(int lattice, int K) { return lattice == 1 ? 5 : kmax_for(K); }
 inline int wtab_bias(int lattice, int kmax) { return lattice == 1 ? 32 : (kmax <= 6 ? 16 : 0); }
 inline int sites_per_cell(int lattice) { return lattice == 1 ? 4 : 2; }
+inline int waves_per_group(int lattice) { return lattice == 1 ? kWavesPerGroupFcc : kWavesPerGroup; }
 inline int first_shell(int lattice) { return lattice == 1 ? 12 : 8; }
 inline int shell_size(int lattice, int s)
 {
