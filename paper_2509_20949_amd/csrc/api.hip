@@ -218,7 +218,7 @@ static smcx_status ctx_init(smcx_ctx* c, const smcx_desc* d, const int32_t B[3],
     if (st) return st;
     const int wr = wrow(c->kmax, c->smax);
     std::vector<int32_t> w((size_t)c->kmax * c->kmax * wr);
-    const int drop = build_wtab(epi, c->K, c->S, c->kmax, c->smax, wtab_bias(d->lattice, c->kmax), d->lattice == 0,
+    const int drop = build_wtab(epi, c->K, c->S, c->kmax, c->smax, wtab_bias(d->lattice, c->kmax), true,
                                 w.data());
     st = ctx_hip(c, hipMalloc(&c->d_wtab, sizeof(int32_t) * w.size()), "hipMalloc(weights)");
     if (st) return st;

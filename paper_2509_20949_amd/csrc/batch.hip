@@ -143,7 +143,7 @@ smcx_status smcx_batch_create(int32_t n, const smcx_desc* descs, const uint8_t* 
         st = bhip(b, hipMemcpy(b->d_species + off[r], species[r], N, hipMemcpyHostToDevice), "hipMemcpy(lattice)");
         if (st) break;
         const int drop = build_wtab(epi[r], d.n_species, d.n_shells, kmax, smax, wtab_bias(d.lattice, kmax),
-                                    d.lattice == 0, w.data());
+                                    true, w.data());
         st = bhip(b, hipMemcpy(b->d_wtabs + wsize * r, w.data(), sizeof(int32_t) * wsize, hipMemcpyHostToDevice),
                   "hipMemcpy(weights)");
         if (!st) st = upload_table(b, r);

@@ -53,6 +53,21 @@ __device__ __forceinline__ void load_wplanes(int32_t* s_w, const int32_t* wtab)
     }
 }
 
+// Byte-dot codes (weight rows in kWtabDot form, KMAX <= 5): species
+// v < KMAX-1 is stored as 40 v, i.e. counted by a shift of 8 v into byte v
+// of the histogram word; the last species as 31 + 32 v, counted into bit 31,
+// which the weighing masks off.  The top 3 bits still give v back.  For up
+// to four species bytes at once.
+template <int KMAX>
+__device__ __forceinline__ uint32_t encode4_dot(uint32_t v)
+{
+    static_assert(KMAX <= 5, "byte-dot codes need KMAX <= 5");
+    constexpr uint32_t c = 8 - (KMAX - 1);                 // v + c >= 8 iff v == KMAX-1
+    const uint32_t last = ((v + c * 0x01010101u) >> 3) & 0x01010101u;
+    constexpr uint32_t k = (uint32_t)(31 - 8 * (KMAX - 1)); // code change of the last species, mod 2^32
+    return (v << 5) + (v << 3) + last * k;                   // no carries or borrows between bytes
+}
+
 // Lower bound floor(k L / n) of block k of n along an axis of L cells
 // (0 <= k <= n <= L).  k L <= L^2 < 2^32 whenever L <= 65535; wider axes
 // divide in 64 bits.  Called with wave-uniform arguments, so it runs on the scalar unit.

@@ -76,20 +76,34 @@ template <int B> struct Off { static constexpr Offsets v = make_offsets(B); };
 constexpr int axis1(int B, int BP) { return SUB[B][0] != SUB[BP][0] ? 0 : 1; }
 constexpr int axis2(int B, int BP) { return SUB[B][2] != SUB[BP][2] ? 2 : 1; }
 
+// Packed species counts of the neighbours of the site at LDS byte a, one
+// word per shell, added to h.  Each shell is summed in NC short chains of
+// shift-adds (kept apart by keep(), so each step stays one v_lshl_add),
+// joined at the end: short dependency chains, one instruction per neighbour.
+template <int N, int NC>
+__device__ __forceinline__ uint32_t count_shell(const uint8_t* lat, int a, const int (&off)[N], uint32_t h)
+{
+    uint32_t c[NC];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) c[j] = j == 0 ? h : 0u;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        c[k % NC] += 1u << (lat[a + off[k]] & 31u);
+        keep(c[k % NC]);
+    }
+    uint32_t t = c[0];
+#pragma unroll
+    for (int j = 1; j < NC; ++j) t += c[j];
+    return t;
+}
+
 template <int SMAX, int B>
 __device__ __forceinline__ void histogram(const uint8_t* lat, int a, uint32_t (&h)[kMaxS])
 {
     constexpr Offsets O = Off<B>::v;
-#pragma unroll
-    for (int k = 0; k < 12; ++k) { h[0] += 1u << (lat[a + O.s1[k]] & 31u); keep(h[0]); }
-    if constexpr (SMAX >= 2) {
-#pragma unroll
-        for (int k = 0; k < 6; ++k) { h[1] += 1u << (lat[a + O.s2[k]] & 31u); keep(h[1]); }
-    }
-    if constexpr (SMAX >= 3) {
-#pragma unroll
-        for (int k = 0; k < 24; ++k) { h[2] += 1u << (lat[a + O.s3[k]] & 31u); keep(h[2]); }
-    }
+    h[0] = count_shell<12, 3>(lat, a, O.s1, h[0]);
+    if constexpr (SMAX >= 2) h[1] = count_shell<6, 2>(lat, a, O.s2, h[1]);
+    if constexpr (SMAX >= 3) h[2] = count_shell<24, 4>(lat, a, O.s3, h[2]);
 }
 
 // Species fields: 6 bits each (up to 24 neighbours per shell), 5 species,
@@ -101,8 +115,9 @@ constexpr uint32_t kBias = 32u * (1u | 1u << 6 | 1u << 12 | 1u << 18 | 1u << 24)
 // One trial: site at LDS byte ai (sublattice B), partner in sublattice BP
 // with the wave-uniform signs (bit 0: first differing axis, bit 1: second;
 // set = +1), acceptance draw u_acc.
+// mode: the form of the weight rows (wave-uniform): kWtabDot or kWtabFull.
 template <int SMAX, int B, int BP>
-__device__ __forceinline__ void trial(uint8_t* lat, int ai, int signs, uint32_t u_acc, bool valid, bool drop,
+__device__ __forceinline__ void trial(uint8_t* lat, int ai, int signs, uint32_t u_acc, bool valid, int mode,
                                       const int32_t* wtab, const double* tab, float ln2kT, int64_t& dEsum,
                                       uint32_t& nacc)
 {
@@ -116,22 +131,28 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, int signs, uint32_t 
     const uint32_t cj = lat[aj];
     uint32_t hi[kMaxS], hj[kMaxS];
 #pragma unroll
-    for (int s = 0; s < kMaxS; ++s) { hi[s] = kBias; hj[s] = 0u; }
+    for (int s = 0; s < kMaxS; ++s) { hi[s] = mode == kWtabDot ? 0x20202020u : kBias; hj[s] = 0u; }
     histogram<SMAX, B>(lat, ai, hi);
     histogram<SMAX, BP>(lat, aj, hj);
     const uint32_t a = min(decode(ci), (uint32_t)(KMAXF - 1)), b = min(decode(cj), (uint32_t)(KMAXF - 1));
     const int32_t* w = wtab + (a * KMAXF + b);   // row (a, b) of the weight planes
-    // drop (wave-uniform): the rows fold in the last species, whose count
-    // differences follow from the others; only fields 0 .. KMAXF-2 are read
-    uint32_t acc = (uint32_t)w[SMAX * KMAXF * PS];
-    if (drop) {
+    // (kmax = 5: the table builder gives the byte-dot rows or, when the
+    // weights are too large for them, full rows of KMAXF fields per shell)
+    uint32_t acc;
+    if (mode == kWtabDot) {
+        // bytes 32 + n_i - n_j (bit 31, the last species, masked off) dotted
+        // with the three base-256 digits of the folded weights
+        int32_t A0 = w[3 * SMAX * PS], A1 = 0, A2 = 0;
 #pragma unroll
         for (int s = 0; s < SMAX; ++s) {
-            const uint32_t d = hi[s] - hj[s];
-#pragma unroll
-            for (int p = 0; p < KMAXF - 1; ++p) acc = mad24((d >> (F * p)) & 63u, w[(s * KMAXF + p) * PS], acc);
+            const int32_t d = (int32_t)((hi[s] - hj[s]) & 0x7fffffffu);
+            A0 = __builtin_amdgcn_sdot4(d, w[(3 * s + 0) * PS], A0, false);
+            A1 = __builtin_amdgcn_sdot4(d, w[(3 * s + 1) * PS], A1, false);
+            A2 = __builtin_amdgcn_sdot4(d, w[(3 * s + 2) * PS], A2, false);
         }
+        acc = (uint32_t)A0 + ((uint32_t)A1 << 8) + ((uint32_t)A2 << 16);
     } else {
+        acc = (uint32_t)w[SMAX * KMAXF * PS];
 #pragma unroll
         for (int s = 0; s < SMAX; ++s) {
             const uint32_t d = hi[s] - hj[s];
@@ -163,7 +184,7 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, int signs, uint32_t 
 
 // Partner sublattice BP (a wave-uniform value) selects one instantiation.
 template <int SMAX, int B>
-__device__ __forceinline__ void trial_any(int bp, uint8_t* lat, int ai, int signs, uint32_t u_acc, bool valid, bool drop,
+__device__ __forceinline__ void trial_any(int bp, uint8_t* lat, int ai, int signs, uint32_t u_acc, bool valid, int drop,
                                           const int32_t* wtab, const double* tab, float ln2kT, int64_t& dEsum,
                                           uint32_t& nacc)
 {
@@ -260,6 +281,7 @@ void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem*
         lat[kBpOff + q] = (uint8_t)((k + (k >= b ? 1 : 0)) | (int)(r[1] >> 30) << 2);
     }
 
+    const bool dot_codes = D.drop_last == kWtabDot;   // LDS codes for the byte-dot weight rows
     // ---- stage block + halo: one cell (4 sublattice bytes, one dword) per lane ----
     // Rows r = (lane >> 4) + 4 it; the loads of 16 rows are issued together
     // (lanes and rows outside the halo load a clamped in-range cell).
@@ -282,7 +304,7 @@ void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem*
                 const int ly = (lane >> 4) + 4 * (it & 3) - 2, lz = (it >> 2) - 2;
                 if (!okx || ly > wy + 1 || lz > wz + 1) continue;
                 uint32_t v = v16[u];
-                v = (v << 5) + (v << 2) + (v << 1);     // (6 + 32) * species, per byte
+                v = dot_codes ? encode4_dot<KMAXF>(v) : (v << 5) + (v << 2) + (v << 1);   // else (6 + 32) * species
 #pragma unroll
                 for (int b = 0; b < 4; ++b)
                     if (in_halo(b, lx, ly, lz, wx, wy, wz)) lat[lds_index(b, lx, ly, lz)] = (uint8_t)(v >> (8 * b));
@@ -298,7 +320,7 @@ void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem*
     const bool narrow = LxLy < (1u << 24) && (uint64_t)LxLy * (uint32_t)Lz < (1ull << 32);
     int64_t dEsum = 0;
     uint32_t nacc = 0;
-    const bool drop = D.drop_last != 0;
+    const int drop = D.drop_last;   // the form of the weight rows
     for (int m = 0; m < 27; ++m) {
         const int rx = m % 3, ry = (m / 3) % 3, rz = m / 9;
         const int lx = rx + 3 * ix, ly = ry + 3 * iy, lz = rz + 3 * iz;

@@ -139,7 +139,7 @@ smcx_status admit(smcx_server* s, Request* q)
     build_thresholds(q->T, tab);
     std::vector<int32_t> w((size_t)q->kmax * q->kmax * wrow(q->kmax, q->smax));
     const int drop = build_wtab(q->epi.data(), q->desc.n_species, q->desc.n_shells, q->kmax, q->smax,
-                                wtab_bias(q->desc.lattice, q->kmax), q->desc.lattice == 0, w.data());
+                                wtab_bias(q->desc.lattice, q->kmax), true, w.data());
     st = shipc(s, hipMemcpy(q->d_mem, q->species.data(), N, hipMemcpyHostToDevice), "hipMemcpy(lattice)");
     if (!st) st = shipc(s, hipMemcpy(q->d_mem + off_tab, tab, sizeof(tab), hipMemcpyHostToDevice), "hipMemcpy(table)");
     if (!st) st = shipc(s, hipMemcpy(q->d_mem + off_w, w.data(), sizeof(int32_t) * w.size(), hipMemcpyHostToDevice),

@@ -50,7 +50,7 @@ __host__ __device__ constexpr int wrow(int kmax, int smax) { return (wrow_entrie
 // DevLattice::drop_last: the form of the weight rows (tables.cpp).
 constexpr int kWtabFull = 0;   // KMAX fields per shell
 constexpr int kWtabDrop = 1;   // KMAX-1 fields, the last species folded in
-constexpr int kWtabDot = 2;    // byte-dot digits (BCC, KMAX <= 5)
+constexpr int kWtabDot = 2;    // byte-dot digits (KMAX <= 5)
 
 // Running energy (micro-eV, int64) and accepted-swap count (uint64) of one
 // lattice, spread over kSpread slots one cache line apart: the wave of block
@@ -136,8 +136,8 @@ void build_thresholds(double T, double* out /* kTab */);
 // bias: the per-field offset the kernel packs into its histogram words
 // (16 for BCC with K <= 6, 0 for BCC with K <= 8, 32 for FCC).  Returns the
 // value of DevLattice::drop_last the rows are built for.
-// dot_ok: the byte-dot form may be used (BCC; taken when kmax <= 5 and the
-// weights have three-digit forms).
+// dot_ok: the byte-dot form may be used (taken when kmax <= 5 and the
+// weights have three-digit forms; both lattice kernels read it).
 int build_wtab(const int32_t* epi, int K, int S, int kmax, int smax, int bias, bool dot_ok, int32_t* out);
 
 // Launchers (kernels.hip).  Return hipSuccess or the launch error.

@@ -41,7 +41,7 @@ void build_thresholds(double T, double* out)
 // s*kmax + p, the constant at smax*kmax, all modulo 2^32 (the kernel sums
 // modulo 2^32).
 //
-// Byte-dot rows (returned value kWtabDot; BCC with kmax <= 5): the kernel
+// Byte-dot rows (returned value kWtabDot; kmax <= 5): the kernel
 // counts species p < kmax-1 in byte p of a 32-bit word (the last species
 // in bit 31, which it masks off), forms bytes 32 + d[s][p] and takes dot
 // products of 4 signed bytes.  Each folded weight W'[s][p] = W[s][p] -

@@ -82,6 +82,21 @@ def test_fcc_parity_every_sweep(smcx, orc, L, K, S, block):
     run_parity(smcx, orc, job, block, 8)
 
 
+def test_fcc_extreme_interactions_full_rows(smcx, orc):
+    """Pair energies of +-(2^22 - 1) micro-eV put the folded weights outside
+    the three-digit byte-dot range, so the kernel weighs full 6-bit count
+    fields (the other form of the weight rows); at 1 K and at 5000 K."""
+    rng = np.random.default_rng(19)
+    K, S = 5, 3
+    v = rng.choice([-(1 << 22) + 1, (1 << 22) - 1, 0, 123456], size=(S, K, K)).astype(np.int32)
+    epi = np.triu(v) + np.transpose(np.triu(v, 1), (0, 2, 1))
+    L = (6, 6, 6)
+    sigma = W.configuration(W.equiatomic(K, W.n_sites(L, FCC)), rng)
+    for T in (1.0, 5000.0):
+        job = W.Lattice(L, epi, sigma, 91, np.full(6, T), name=f"extreme T={T}", lattice=FCC)
+        run_parity(smcx, orc, job, (3, 3, 3), 6)
+
+
 def test_fcc_alloy_composition_anneal_and_sro(smcx, orc):
     """FCC quinary at the paper's Fe29Co29Ni28Al7Ti7 composition, annealed
     1600 K -> 900 K, SRO compared after the run."""
