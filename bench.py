@@ -51,8 +51,8 @@ BYTES_PER_TRIAL = 2
 # (profiles/sweep_phase_bcc512_k5s3_hbm_counters.md).  It describes the
 # kernel built from the sources with this SHA-256 only; for other sources
 # the bench reports traffic as null.
-MEASURED_TRAFFIC = {"sources_sha256": "87a31d92b0c0b010b6f2112ea31a78d7ef3b7471c97d203c60bfa3fe78d15b0c",
-                    "bytes_per_launch": 297612500}
+MEASURED_TRAFFIC = {"sources_sha256": "82266b0fbfd8e18c2e21254be1d5279002e4703803d48f0bf296ec4c9e122e9f",
+                    "bytes_per_launch": 297643336}
 KERNEL_SOURCES = ("paper_2509_20949_amd/csrc/kernels.hip", "paper_2509_20949_amd/csrc/device_common.h",
                   "paper_2509_20949_amd/csrc/smcx_internal.h")
 
