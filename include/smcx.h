@@ -248,6 +248,15 @@ const char* smcx_server_last_error(const smcx_server* srv);
  * smcx_device_philox: Philox4x32-10 evaluated on the device for n counters
  * (host arrays of 4n words; synchronous). */
 smcx_status smcx_threshold_table(double T_kelvin, double* out768);
+/* smcx_weight_rows: the pair-weight rows the library builds for a lattice
+ * type (0 BCC, 1 FCC), K species, S shells and an EPI table [S][K][K]
+ * (host memory; no device).  *form: 0 full fields, 1 the last species
+ * folded in, 2 byte-dot digits; the table has kmax*kmax rows of *row_len
+ * int32 entries, row (a, b) at a*kmax + b (layouts in the library's
+ * tables.cpp).  out may be NULL to query kmax and row_len; otherwise it
+ * must hold n >= kmax*kmax*row_len ints.  Errors as smcx_create's EPI checks. */
+smcx_status smcx_weight_rows(int32_t lattice, int32_t K, int32_t S, const int32_t* epi, int32_t* form,
+                             int32_t* kmax, int32_t* row_len, int32_t* out, size_t n);
 smcx_status smcx_device_thresholds(double T_kelvin, const int32_t* dE, int32_t n, double* out);
 smcx_status smcx_device_accept_bounds(double T_kelvin, const uint32_t* u, int32_t n, int32_t* lo, int32_t* hi);
 smcx_status smcx_device_philox(const uint32_t* ctr, const uint32_t key[2], int32_t n, uint32_t* out);

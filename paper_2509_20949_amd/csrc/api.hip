@@ -572,6 +572,27 @@ smcx_status smcx_threshold_table(double T, double* out)
     return SMCX_OK;
 }
 
+smcx_status smcx_weight_rows(int32_t lattice, int32_t K, int32_t S, const int32_t* epi, int32_t* form,
+                             int32_t* kmax_out, int32_t* row_len, int32_t* out, size_t n)
+{
+    if (lattice != 0 && lattice != 1) return fail_global(SMCX_E_INVALID, "lattice must be 0 (BCC) or 1 (FCC)");
+    if (K < 1 || K > (lattice == 1 ? 5 : kMaxK)) return fail_global(SMCX_E_INVALID, "K = %d outside the kernels' range", K);
+    if (S < 1 || S > kMaxS) return fail_global(SMCX_E_INVALID, "S = %d outside 1..%d", S, kMaxS);
+    smcx_status st = validate_epi(epi, K, S);
+    if (st) return st;
+    const int kmax = kmax_for(lattice, K), wr = wrow(kmax, S);
+    const size_t need = (size_t)kmax * kmax * wr;
+    if (kmax_out) *kmax_out = kmax;
+    if (row_len) *row_len = wr;
+    std::vector<int32_t> w(need);
+    const int f = build_wtab(epi, K, S, kmax, S, wtab_bias(lattice, kmax), true, w.data());
+    if (form) *form = f;
+    if (!out) return SMCX_OK;
+    if (n < need) return fail_global(SMCX_E_INVALID, "out holds %zu ints < %zu", n, need);
+    std::memcpy(out, w.data(), sizeof(int32_t) * need);
+    return SMCX_OK;
+}
+
 smcx_status smcx_device_thresholds(double T, const int32_t* dE, int32_t n, double* out)
 {
     if (!dE || !out || n < 0) return fail_global(SMCX_E_INVALID, "bad argument");

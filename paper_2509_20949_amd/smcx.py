@@ -92,6 +92,7 @@ def lib():
     _sig(L, "smcx_device_thresholds", st, [dbl, _P(i32), i32, _P(dbl)])
     _sig(L, "smcx_device_philox", st, [_P(C.c_uint32), _P(C.c_uint32), i32, _P(C.c_uint32)])
     _sig(L, "smcx_device_accept_bounds", st, [dbl, _P(C.c_uint32), i32, _P(i32), _P(i32)])
+    _sig(L, "smcx_weight_rows", st, [i32, i32, i32, _P(i32), _P(i32), _P(i32), _P(i32), _P(i32), C.c_size_t])
     _lib = L
     return L
 
@@ -221,6 +222,18 @@ def smcx_device_thresholds(T_kelvin: float, dE) -> np.ndarray:
     out = np.zeros(d.size, np.float64)
     _check(lib().smcx_device_thresholds(float(T_kelvin), _ptr(d, C.c_int32), int(d.size), _ptr(out, C.c_double)))
     return out
+
+
+def smcx_weight_rows(lattice: int, K: int, S: int, epi):
+    """(form, table[kmax*kmax, row_len]) of the pair-weight rows the library builds."""
+    e = np.ascontiguousarray(epi, dtype=np.int32)
+    form, kmax, row_len = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().smcx_weight_rows(int(lattice), int(K), int(S), _ptr(e, C.c_int32), C.byref(form), C.byref(kmax),
+                                  C.byref(row_len), None, 0))
+    out = np.zeros(kmax.value * kmax.value * row_len.value, np.int32)
+    _check(lib().smcx_weight_rows(int(lattice), int(K), int(S), _ptr(e, C.c_int32), C.byref(form), C.byref(kmax),
+                                  C.byref(row_len), _ptr(out, C.c_int32), out.size))
+    return form.value, out.reshape(kmax.value * kmax.value, row_len.value)
 
 
 def smcx_device_accept_bounds(T_kelvin: float, u):
