@@ -115,6 +115,23 @@ __device__ __forceinline__ void accept_bounds(uint32_t u, float c, int& lo, int&
     hi = (int)(e + kAcceptMargin);
 }
 
+// XCD-aware workgroup order of a single-lattice launch.  Workgroups are
+// handed to the 8 XCDs of the chip in turn (workgroup b to XCD b % 8), each
+// XCD with its own L2.  Workgroup b therefore takes group
+// (b % 8) * chunk + b / 8 of the n groups (chunk = ceil(n / 8), grid =
+// 8 * chunk): each XCD works through one contiguous range of blocks, the
+// same range in every colour launch, so the halo a block stages was mostly
+// written by blocks of the previous colour that ran on the same XCD and may
+// still sit in its L2.  Any order is correct; returns -1 for workgroups
+// beyond n.
+__device__ __forceinline__ int xcd_group(int n)
+{
+    const int chunk = (n + 7) / 8;
+    const int g = (int)(blockIdx.x % 8u) * chunk + (int)(blockIdx.x / 8u);
+    return g < n ? g : -1;
+}
+inline int xcd_grid(int n) { return 8 * ((n + 7) / 8); }
+
 __device__ __forceinline__ int wrap_add(int v, int L)   // v in [-L, 2L)
 {
     v = v < 0 ? v + L : v;

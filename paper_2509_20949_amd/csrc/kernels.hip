@@ -231,12 +231,16 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
 
     const int wave = wave_id();
     const int lane = threadIdx.x % kWave;
-    int li = 0, f = blockIdx.x * kWavesPerGroup;
+    int li = 0, f = 0;
     if (items) {
         li = items[blockIdx.x].lattice;
         f = items[blockIdx.x].first_block;
     }
     const DevLattice& D = lats[li];
+    if (!items) {
+        const int g = xcd_group((D.blocks_per_colour + kWavesPerGroup - 1) / kWavesPerGroup);
+        f = g < 0 ? D.blocks_per_colour : g * kWavesPerGroup;   // beyond the last group: no block
+    }
     const uint32_t s = D.sweep0 + (uint32_t)t;
 
     // Weight planes in LDS; the threshold tables of sweep s stay in global
@@ -599,7 +603,8 @@ template <int KMAX, int SMAX>
 static hipError_t launch_t(const DevLattice* d_lat, const WorkItem* d_items, int n_groups, int t,
                            int colour, hipStream_t stream)
 {
-    hipLaunchKernelGGL((sweep_phase_kernel<KMAX, SMAX>), dim3(n_groups), dim3(kWave * kWavesPerGroup), 0,
+    const int grid = d_items ? n_groups : xcd_grid(n_groups);   // single lattice: XCD-aware order
+    hipLaunchKernelGGL((sweep_phase_kernel<KMAX, SMAX>), dim3(grid), dim3(kWave * kWavesPerGroup), 0,
                        stream, d_lat, d_items, t, colour);
     return hipGetLastError();
 }

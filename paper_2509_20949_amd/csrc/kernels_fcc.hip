@@ -234,12 +234,16 @@ void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem*
 
     const int wave = wave_id();
     const int lane = threadIdx.x % kWave;
-    int li = 0, f = blockIdx.x * kWavesPerGroupFcc;
+    int li = 0, f = 0;
     if (items) {
         li = items[blockIdx.x].lattice;
         f = items[blockIdx.x].first_block;
     }
     const DevLattice& D = lats[li];
+    if (!items) {
+        const int g = xcd_group((D.blocks_per_colour + kWavesPerGroupFcc - 1) / kWavesPerGroupFcc);
+        f = g < 0 ? D.blocks_per_colour : g * kWavesPerGroupFcc;   // beyond the last group: no block
+    }
     const uint32_t s = D.sweep0 + (uint32_t)t;
     // weight planes in LDS; the threshold tables stay in global memory
     load_wplanes<KMAXF, SMAX>(s_w, D.wtab);
@@ -416,7 +420,7 @@ hipError_t launch_sweep_phase_fcc(const DevLattice* d_lat, const WorkItem* d_ite
                                   int smax, hipStream_t stream)
 {
     if (n_groups <= 0) return hipSuccess;
-    const dim3 grid(n_groups), block(kWave * kWavesPerGroupFcc);
+    const dim3 grid(d_items ? n_groups : xcd_grid(n_groups)), block(kWave * kWavesPerGroupFcc);
     switch (smax) {
     case 1: hipLaunchKernelGGL(sweep_phase_fcc_kernel<1>, grid, block, 0, stream, d_lat, d_items, t, colour); break;
     case 2: hipLaunchKernelGGL(sweep_phase_fcc_kernel<2>, grid, block, 0, stream, d_lat, d_items, t, colour); break;
