@@ -51,8 +51,8 @@ BYTES_PER_TRIAL = 2
 # (profiles/sweep_phase_bcc512_k5s3_hbm_counters.md).  It describes the
 # kernel built from the sources with this SHA-256 only; for other sources
 # the bench reports traffic as null.
-MEASURED_TRAFFIC = {"sources_sha256": "1c9bb6bd8e54665d41cfe9f67a403b3f6a2b4016dd49a7704241c1111684ada3",
-                    "bytes_per_launch": 216550546}
+MEASURED_TRAFFIC = {"sources_sha256": "93cc2582648db0ae452111b282b266b7f2df073341513a9a1715bf5d22d2e1da",
+                    "bytes_per_launch": 216600090}
 KERNEL_SOURCES = ("paper_2509_20949_amd/csrc/kernels.hip", "paper_2509_20949_amd/csrc/device_common.h",
                   "paper_2509_20949_amd/csrc/smcx_internal.h")
 

@@ -115,14 +115,15 @@ __device__ __forceinline__ void accept_bounds(uint32_t u, float c, int& lo, int&
     hi = (int)(e + kAcceptMargin);
 }
 
-// XCD-aware workgroup order of a single-lattice launch.  Workgroups are
+// XCD-aware workgroup order of a sweep launch.  Workgroups are
 // handed to the 8 XCDs of the chip in turn (workgroup b to XCD b % 8), each
 // XCD with its own L2.  Workgroup b therefore takes group
 // (b % 8) * chunk + b / 8 of the n groups (chunk = ceil(n / 8), grid =
 // 8 * chunk): each XCD works through one contiguous range of blocks, the
 // same range in every colour launch, so the halo a block stages was mostly
 // written by blocks of the previous colour that ran on the same XCD and may
-// still sit in its L2.  Any order is correct; returns -1 for workgroups
+// still sit in its L2 (in a batched launch, consecutive work items are the
+// blocks of one replica).  Any order is correct; returns -1 for workgroups
 // beyond n.
 __device__ __forceinline__ int xcd_group(int n)
 {

@@ -222,7 +222,7 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int yz, 
 // ---------------------------------------------------------------------------
 template <int KMAX, int SMAX>
 __global__ __launch_bounds__(kWave * kWavesPerGroup) __attribute__((amdgpu_waves_per_eu(kSweepWavesPerSimd)))
-void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __restrict__ items,
+void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __restrict__ items, int n_groups,
                         int t, int colour)
 {
     constexpr int F = Field<KMAX>::F;
@@ -231,16 +231,16 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
 
     const int wave = wave_id();
     const int lane = threadIdx.x % kWave;
-    int li = 0, f = 0;
+    // group grp of the launch's n_groups (XCD-aware order): work item g of a
+    // batched launch, or blocks 4g .. 4g+3 of a single lattice
+    const int grp = xcd_group(n_groups);
+    if (grp < 0) return;   // no later barrier in a workgroup without a group
+    int li = 0, f = grp * kWavesPerGroup;
     if (items) {
-        li = items[blockIdx.x].lattice;
-        f = items[blockIdx.x].first_block;
+        li = items[grp].lattice;
+        f = items[grp].first_block;
     }
     const DevLattice& D = lats[li];
-    if (!items) {
-        const int g = xcd_group((D.blocks_per_colour + kWavesPerGroup - 1) / kWavesPerGroup);
-        f = g < 0 ? D.blocks_per_colour : g * kWavesPerGroup;   // beyond the last group: no block
-    }
     const uint32_t s = D.sweep0 + (uint32_t)t;
 
     // Weight planes in LDS; the threshold tables of sweep s stay in global
@@ -603,9 +603,8 @@ template <int KMAX, int SMAX>
 static hipError_t launch_t(const DevLattice* d_lat, const WorkItem* d_items, int n_groups, int t,
                            int colour, hipStream_t stream)
 {
-    const int grid = d_items ? n_groups : xcd_grid(n_groups);   // single lattice: XCD-aware order
-    hipLaunchKernelGGL((sweep_phase_kernel<KMAX, SMAX>), dim3(grid), dim3(kWave * kWavesPerGroup), 0,
-                       stream, d_lat, d_items, t, colour);
+    hipLaunchKernelGGL((sweep_phase_kernel<KMAX, SMAX>), dim3(xcd_grid(n_groups)), dim3(kWave * kWavesPerGroup), 0,
+                       stream, d_lat, d_items, n_groups, t, colour);
     return hipGetLastError();
 }
 

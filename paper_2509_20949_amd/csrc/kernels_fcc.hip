@@ -225,8 +225,8 @@ __device__ __forceinline__ int lds_index(int b, int lx, int ly, int lz)
 
 template <int SMAX>
 __global__ __launch_bounds__(kWave * kWavesPerGroupFcc)
-void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem* __restrict__ items, int t,
-                            int colour)
+void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem* __restrict__ items, int n_groups,
+                            int t, int colour)
 {
     using namespace fcc;
     __shared__ int32_t s_w[wplanes(KMAXF, SMAX) * wplane(KMAXF)];
@@ -234,16 +234,16 @@ void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem*
 
     const int wave = wave_id();
     const int lane = threadIdx.x % kWave;
-    int li = 0, f = 0;
+    // group grp of the launch's n_groups (XCD-aware order): work item g of a
+    // batched launch, or blocks 2g, 2g+1 of a single lattice
+    const int grp = xcd_group(n_groups);
+    if (grp < 0) return;   // no later barrier in a workgroup without a group
+    int li = 0, f = grp * kWavesPerGroupFcc;
     if (items) {
-        li = items[blockIdx.x].lattice;
-        f = items[blockIdx.x].first_block;
+        li = items[grp].lattice;
+        f = items[grp].first_block;
     }
     const DevLattice& D = lats[li];
-    if (!items) {
-        const int g = xcd_group((D.blocks_per_colour + kWavesPerGroupFcc - 1) / kWavesPerGroupFcc);
-        f = g < 0 ? D.blocks_per_colour : g * kWavesPerGroupFcc;   // beyond the last group: no block
-    }
     const uint32_t s = D.sweep0 + (uint32_t)t;
     // weight planes in LDS; the threshold tables stay in global memory
     load_wplanes<KMAXF, SMAX>(s_w, D.wtab);
@@ -420,11 +420,11 @@ hipError_t launch_sweep_phase_fcc(const DevLattice* d_lat, const WorkItem* d_ite
                                   int smax, hipStream_t stream)
 {
     if (n_groups <= 0) return hipSuccess;
-    const dim3 grid(d_items ? n_groups : xcd_grid(n_groups)), block(kWave * kWavesPerGroupFcc);
+    const dim3 grid(xcd_grid(n_groups)), block(kWave * kWavesPerGroupFcc);
     switch (smax) {
-    case 1: hipLaunchKernelGGL(sweep_phase_fcc_kernel<1>, grid, block, 0, stream, d_lat, d_items, t, colour); break;
-    case 2: hipLaunchKernelGGL(sweep_phase_fcc_kernel<2>, grid, block, 0, stream, d_lat, d_items, t, colour); break;
-    case 3: hipLaunchKernelGGL(sweep_phase_fcc_kernel<3>, grid, block, 0, stream, d_lat, d_items, t, colour); break;
+    case 1: hipLaunchKernelGGL(sweep_phase_fcc_kernel<1>, grid, block, 0, stream, d_lat, d_items, n_groups, t, colour); break;
+    case 2: hipLaunchKernelGGL(sweep_phase_fcc_kernel<2>, grid, block, 0, stream, d_lat, d_items, n_groups, t, colour); break;
+    case 3: hipLaunchKernelGGL(sweep_phase_fcc_kernel<3>, grid, block, 0, stream, d_lat, d_items, n_groups, t, colour); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
