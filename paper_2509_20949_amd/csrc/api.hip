@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -130,27 +131,41 @@ bool geometry_ok(const DevLattice& L)
 
 smcx_status upload_tables(smcx_ctx* c, const double* T, int n, uint64_t s0)
 {
-    // tables are read by enqueued sweeps: wait before replacing them
+    // The tables are read by enqueued sweeps: wait before replacing them.
+    // Two buffers alternate: the new tables go into the one the descriptor
+    // does not point at, and the descriptor is repointed only after they are
+    // on the device.  A failed call therefore leaves the context sweeping on
+    // its previous tables, untouched.
     smcx_status st = ctx_hip(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
     if (st) return st;
     std::vector<double> h((size_t)n * kTab);
     for (int k = 0; k < n; ++k) build_thresholds(T[k], h.data() + (size_t)k * kTab);
-    if (n > c->tab_cap) {
-        if (c->d_tabs) (void)hipFree(c->d_tabs);
-        c->d_tabs = nullptr;
-        c->tab_cap = 0;
-        st = ctx_hip(c, hipMalloc(&c->d_tabs, sizeof(double) * kTab * (size_t)n), "hipMalloc(tables)");
+    if (n > c->tab_spare_cap) {
+        double* buf = nullptr;
+        st = ctx_hip(c, hipMalloc(&buf, sizeof(double) * kTab * (size_t)n), "hipMalloc(tables)");
         if (st) return st;
-        c->tab_cap = n;
+        if (c->d_tabs_spare) (void)hipFree(c->d_tabs_spare);
+        c->d_tabs_spare = buf;
+        c->tab_spare_cap = n;
     }
-    st = ctx_hip(c, hipMemcpy(c->d_tabs, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice),
+    // SMCX_FAULT_TABLES=1 (tests) makes the upload fail here, after the
+    // spare buffer has been (re)allocated, as a failed copy would.
+    const char* fault = std::getenv("SMCX_FAULT_TABLES");
+    if (fault && std::strcmp(fault, "1") == 0)
+        return fail(c, SMCX_E_DEVICE, "table upload failure forced by SMCX_FAULT_TABLES");
+    st = ctx_hip(c, hipMemcpy(c->d_tabs_spare, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice),
                  "hipMemcpy(tables)");
     if (st) return st;
-    c->h_lat.tabs = c->d_tabs;
-    c->h_lat.tab_s0 = (uint32_t)s0;
-    c->h_lat.n_tabs = n;
-    return ctx_hip(c, hipMemcpy(c->d_lat, &c->h_lat, sizeof(DevLattice), hipMemcpyHostToDevice),
-                   "hipMemcpy(lattice descriptor)");
+    DevLattice next = c->h_lat;
+    next.tabs = c->d_tabs_spare;
+    next.tab_s0 = (uint32_t)s0;
+    next.n_tabs = n;
+    st = ctx_hip(c, hipMemcpy(c->d_lat, &next, sizeof(DevLattice), hipMemcpyHostToDevice), "hipMemcpy(lattice descriptor)");
+    if (st) return st;
+    std::swap(c->d_tabs, c->d_tabs_spare);
+    std::swap(c->tab_cap, c->tab_spare_cap);
+    c->h_lat = next;
+    return SMCX_OK;
 }
 
 smcx_status read_state(smcx_ctx* c, int64_t* E, uint64_t* accepted)
@@ -250,6 +265,7 @@ void ctx_release(smcx_ctx* c)
     if (c->d_counts) (void)hipFree(c->d_counts);
     if (c->d_wtab) (void)hipFree(c->d_wtab);
     if (c->d_tabs) (void)hipFree(c->d_tabs);
+    if (c->d_tabs_spare) (void)hipFree(c->d_tabs_spare);
     if (c->owns_stream && c->stream) (void)hipStreamDestroy(c->stream);
     c->d_species = nullptr;
     c->d_lat = nullptr;
@@ -257,6 +273,7 @@ void ctx_release(smcx_ctx* c)
     c->d_counts = nullptr;
     c->d_wtab = nullptr;
     c->d_tabs = nullptr;
+    c->d_tabs_spare = nullptr;
     c->stream = nullptr;
 }
 
@@ -269,6 +286,42 @@ double temperature_of(const smcx_ctx* c, uint64_t s)
     return k < c->sched.size() ? c->sched[k] : c->sched.back();
 }
 
+// Kernel timing: event pairs are taken from a pool that grows up to
+// kEventPairs pairs; when it is full, the elapsed times recorded so far are
+// added to the running total (which waits for them) and the pool is reused.
+constexpr size_t kEventPairs = 4096;
+
+static smcx_status harvest_events(smcx_ctx* c)
+{
+    for (size_t k = 0; k < c->ev_used; ++k) {
+        float ms = 0.f;
+        smcx_status st = ctx_hip(c, hipEventSynchronize(c->events[2 * k + 1]), "hipEventSynchronize");
+        if (!st) st = ctx_hip(c, hipEventElapsedTime(&ms, c->events[2 * k], c->events[2 * k + 1]), "hipEventElapsedTime");
+        if (st) return st;
+        c->ev_total_ms += ms;
+        c->ev_launches += 1;
+    }
+    c->ev_used = 0;
+    return SMCX_OK;
+}
+
+static smcx_status next_event_pair(smcx_ctx* c, hipEvent_t* e0, hipEvent_t* e1)
+{
+    if (c->ev_used == kEventPairs) {
+        smcx_status st = harvest_events(c);
+        if (st) return st;
+    }
+    while (c->events.size() < 2 * (c->ev_used + 1)) {
+        hipEvent_t e;
+        smcx_status st = ctx_hip(c, hipEventCreate(&e), "hipEventCreate");
+        if (st) return st;
+        c->events.push_back(e);
+    }
+    *e0 = c->events[2 * c->ev_used];
+    *e1 = c->events[2 * c->ev_used + 1];
+    return SMCX_OK;
+}
+
 smcx_status enqueue_sweeps(smcx_ctx* c, int32_t n)
 {
     const int wpg = waves_per_group(c->h_lat.lattice);
@@ -276,20 +329,20 @@ smcx_status enqueue_sweeps(smcx_ctx* c, int32_t n)
     for (int32_t k = 0; k < n; ++k) {
         const uint32_t s = (uint32_t)(c->sweeps + (uint64_t)k);
         for (int col = 0; col < 8; ++col) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
             if (c->profiling) {
-                hipEvent_t e0, e1;
-                smcx_status st = ctx_hip(c, hipEventCreate(&e0), "hipEventCreate");
+                smcx_status st = next_event_pair(c, &e0, &e1);
+                if (!st) st = ctx_hip(c, hipEventRecord(e0, c->stream), "hipEventRecord");
                 if (st) return st;
-                st = ctx_hip(c, hipEventCreate(&e1), "hipEventCreate");
-                if (st) { (void)hipEventDestroy(e0); return st; }
-                c->events.push_back(e0);
-                c->events.push_back(e1);
-                (void)hipEventRecord(e0, c->stream);
             }
             hipError_t e = launch_sweep_phase(c->h_lat.lattice, c->d_lat, nullptr, groups, (int)s, col, c->kmax, c->smax,
                                               c->stream);
             if (e != hipSuccess) return ctx_hip(c, e, "sweep_phase launch");
-            if (c->profiling) (void)hipEventRecord(c->events.back(), c->stream);
+            if (c->profiling) {
+                smcx_status st = ctx_hip(c, hipEventRecord(e1, c->stream), "hipEventRecord");
+                if (st) return st;
+                ++c->ev_used;
+            }
         }
     }
     c->sweeps += (uint64_t)n;
@@ -410,9 +463,11 @@ smcx_status smcx_set_temperature(smcx_ctx* c, double T)
     if (c->view) return fail(c, SMCX_E_STATE, "batch views take smcx_batch_set_temperature");
     smcx_status st = validate_T(T);
     if (st) return fail(c, st, "%s", g_error.c_str());
+    st = upload_tables(c, &T, 1, c->sweeps);
+    if (st) return st;
     c->sched.clear();
     c->T_default = T;
-    return upload_tables(c, &T, 1, c->sweeps);
+    return SMCX_OK;
 }
 
 smcx_status smcx_set_schedule(smcx_ctx* c, const double* T, int32_t n)
@@ -424,10 +479,12 @@ smcx_status smcx_set_schedule(smcx_ctx* c, const double* T, int32_t n)
         smcx_status st = validate_T(T[k]);
         if (st) return fail(c, st, "schedule[%d]: %s", k, g_error.c_str());
     }
+    smcx_status st = upload_tables(c, T, n, c->sweeps);
+    if (st) return st;
     c->sched.assign(T, T + n);
     c->sched_s0 = c->sweeps;
     c->T_default = T[n - 1];
-    return upload_tables(c, T, n, c->sweeps);
+    return SMCX_OK;
 }
 
 smcx_status smcx_sweep(smcx_ctx* c, int32_t n)
@@ -530,8 +587,9 @@ smcx_status smcx_profile(smcx_ctx* c, int32_t enable)
     if (!c) return fail_global(SMCX_E_INVALID, "ctx is NULL");
     smcx_status st = ctx_hip(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
     if (st) return st;
-    for (auto& e : c->events) (void)hipEventDestroy(e);
-    c->events.clear();
+    c->ev_used = 0;
+    c->ev_total_ms = 0.0;
+    c->ev_launches = 0;
     c->profiling = enable != 0;
     return SMCX_OK;
 }
@@ -540,16 +598,10 @@ smcx_status smcx_kernel_time(smcx_ctx* c, double* total_ms, uint64_t* launches)
 {
     if (!c) return fail_global(SMCX_E_INVALID, "ctx is NULL");
     smcx_status st = ctx_hip(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    if (!st) st = harvest_events(c);
     if (st) return st;
-    double tot = 0.0;
-    for (size_t k = 0; k + 1 < c->events.size(); k += 2) {
-        float ms = 0.f;
-        st = ctx_hip(c, hipEventElapsedTime(&ms, c->events[k], c->events[k + 1]), "hipEventElapsedTime");
-        if (st) return st;
-        tot += ms;
-    }
-    if (total_ms) *total_ms = tot;
-    if (launches) *launches = c->events.size() / 2;
+    if (total_ms) *total_ms = c->ev_total_ms;
+    if (launches) *launches = c->ev_launches;
     return SMCX_OK;
 }
 

@@ -23,15 +23,20 @@ struct smcx_ctx {
     void* d_state = nullptr;                 // int64 running energy, uint64 accepted
     unsigned long long* d_counts = nullptr;  // pair-count scratch [kMaxS][kMaxK][kMaxK]
     int32_t* d_wtab = nullptr;
-    double* d_tabs = nullptr;
+    double* d_tabs = nullptr;                // tables the descriptor points at
     int tab_cap = 0;
+    double* d_tabs_spare = nullptr;          // the other buffer of the pair (upload_tables)
+    int tab_spare_cap = 0;
     uint64_t sweeps = 0, attempted = 0;
     double T_default = 0.0;
     std::vector<double> sched;
     uint64_t sched_s0 = 0;
     uint64_t counts[smcx::kMaxS * smcx::kMaxK * smcx::kMaxK] = {};
     bool profiling = false;
-    std::vector<hipEvent_t> events;
+    std::vector<hipEvent_t> events;          // pool of (start, end) pairs, reused
+    size_t ev_used = 0;                      // pairs recorded since the last harvest
+    double ev_total_ms = 0.0;                // harvested kernel time since profiling was enabled
+    uint64_t ev_launches = 0;
     bool view = false;                       // replica view owned by a batch
     std::string err;
 };
