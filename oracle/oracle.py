@@ -7,6 +7,7 @@ contraction, so the FP64 threshold products round exactly as written).
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -20,15 +21,61 @@ LIB = os.path.join(HERE, "libsmcx_oracle.so")
 _lib = None
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle into oracle/libsmcx_oracle.so."""
-    if force or not os.path.exists(LIB):
-        tmp = LIB + ".tmp"
+def build(force: bool = True, src: str = SRC, out: str = LIB) -> str:
+    """Compile the oracle (by default smcx_oracle.c into oracle/libsmcx_oracle.so)."""
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
         subprocess.check_call([
             "gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
-            "-fno-fast-math", "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
-    return LIB
+            "-fno-fast-math", "-Wall", "-Wextra", "-I", HERE, "-o", tmp, src, "-lm"])
+        os.replace(tmp, out)
+    return out
+
+
+def _bind(path: str):
+    L = C.CDLL(path)
+    p = C.POINTER
+    L.or_set_threads.argtypes = [C.c_int]
+    L.or_get_threads.restype = C.c_int
+    L.or_philox4x32_10.argtypes = [p(C.c_uint32), p(C.c_uint32), p(C.c_uint32)]
+    L.or_philox4x64_10.argtypes = [p(C.c_uint64), p(C.c_uint64), p(C.c_uint64)]
+    L.or_thresholds.argtypes = [C.c_double, p(C.c_double)]
+    L.or_accept.argtypes = [C.c_int64, C.c_uint32, p(C.c_double)]
+    L.or_accept.restype = C.c_int
+    L.or_axis_blocks.argtypes = [C.c_int, C.c_int]
+    L.or_axis_blocks.restype = C.c_int
+    L.or_axis_bounds.argtypes = [C.c_int, C.c_int, p(C.c_int32)]
+    L.or_sweep_shift.argtypes = [p(C.c_int32), C.c_uint64, C.c_uint32, p(C.c_int32)]
+    L.or_schedule.argtypes = [C.c_int, p(C.c_int32), p(C.c_int32), C.c_uint64, C.c_uint32,
+                              p(C.c_uint8), p(C.c_uint8), p(C.c_int64)]
+    L.or_neighbour.argtypes = [C.c_int, p(C.c_int32), C.c_int64, C.c_int]
+    L.or_bcc_draws.argtypes = [p(C.c_int32), p(C.c_int32), C.c_uint64, C.c_uint32, p(C.c_uint32),
+                               p(C.c_uint8), p(C.c_uint8), p(C.c_uint32)]
+    L.or_bcc_draws.restype = C.c_int
+    L.or_fcc_draws.argtypes = [p(C.c_int32), p(C.c_int32), C.c_uint64, C.c_uint32, p(C.c_int64), p(C.c_uint32)]
+    L.or_fcc_draws.restype = C.c_int
+    L.or_shell_size.argtypes = [C.c_int, C.c_int]
+    L.or_n_sub.argtypes = [C.c_int]
+    L.or_neighbour.restype = C.c_int64
+    L.or_energy.argtypes = [C.c_int, p(C.c_int32), C.c_int, C.c_int, p(C.c_int32), p(C.c_uint8)]
+    L.or_energy.restype = C.c_int64
+    L.or_delta_energy.argtypes = [C.c_int, p(C.c_int32), C.c_int, C.c_int, p(C.c_int32), p(C.c_uint8),
+                                  C.c_int64, C.c_int64]
+    L.or_delta_energy.restype = C.c_int64
+    L.or_pair_counts.argtypes = [C.c_int, p(C.c_int32), C.c_int, C.c_int, p(C.c_uint8), p(C.c_uint64)]
+    L.or_sro.argtypes = [C.c_int, p(C.c_int32), C.c_int, C.c_int, p(C.c_uint8), p(C.c_double),
+                         p(C.c_uint64)]
+    L.or_sweep.argtypes = [C.c_int, p(C.c_int32), p(C.c_int32), C.c_int, C.c_int, p(C.c_int32),
+                           C.c_uint64, C.c_uint32, C.c_int32, p(C.c_double), p(C.c_uint8),
+                           p(C.c_int64), p(C.c_uint64), p(C.c_int64), p(C.c_uint64)]
+    L.or_sweep.restype = C.c_int
+    L.or_exchange_accept.argtypes = [C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_uint64,
+                                     C.c_uint32, C.c_uint64]
+    L.or_exchange_accept.restype = C.c_int
+    L.or_enumerate.argtypes = [C.c_int, p(C.c_int32), C.c_int, C.c_int, p(C.c_int32), p(C.c_int32),
+                               C.c_int64, p(C.c_int64), p(C.c_uint64)]
+    L.or_enumerate.restype = C.c_int64
+    return L
 
 
 def lib():
@@ -36,50 +83,21 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB):
             build()
-        L = C.CDLL(LIB)
-        p = C.POINTER
-        L.or_set_threads.argtypes = [C.c_int]
-        L.or_get_threads.restype = C.c_int
-        L.or_philox4x32_10.argtypes = [p(C.c_uint32), p(C.c_uint32), p(C.c_uint32)]
-        L.or_philox4x64_10.argtypes = [p(C.c_uint64), p(C.c_uint64), p(C.c_uint64)]
-        L.or_thresholds.argtypes = [C.c_double, p(C.c_double)]
-        L.or_accept.argtypes = [C.c_int64, C.c_uint32, p(C.c_double)]
-        L.or_accept.restype = C.c_int
-        L.or_axis_blocks.argtypes = [C.c_int, C.c_int]
-        L.or_axis_blocks.restype = C.c_int
-        L.or_axis_bounds.argtypes = [C.c_int, C.c_int, p(C.c_int32)]
-        L.or_sweep_shift.argtypes = [p(C.c_int32), C.c_uint64, C.c_uint32, p(C.c_int32)]
-        L.or_schedule.argtypes = [C.c_int, p(C.c_int32), p(C.c_int32), C.c_uint64, C.c_uint32,
-                                  p(C.c_uint8), p(C.c_uint8), p(C.c_int64)]
-        L.or_neighbour.argtypes = [C.c_int, p(C.c_int32), C.c_int64, C.c_int]
-        L.or_bcc_draws.argtypes = [p(C.c_int32), p(C.c_int32), C.c_uint64, C.c_uint32, p(C.c_uint32),
-                                   p(C.c_uint8), p(C.c_uint8), p(C.c_uint32)]
-        L.or_bcc_draws.restype = C.c_int
-        L.or_fcc_draws.argtypes = [p(C.c_int32), p(C.c_int32), C.c_uint64, C.c_uint32, p(C.c_int64), p(C.c_uint32)]
-        L.or_fcc_draws.restype = C.c_int
-        L.or_shell_size.argtypes = [C.c_int, C.c_int]
-        L.or_n_sub.argtypes = [C.c_int]
-        L.or_neighbour.restype = C.c_int64
-        L.or_energy.argtypes = [C.c_int, p(C.c_int32), C.c_int, C.c_int, p(C.c_int32), p(C.c_uint8)]
-        L.or_energy.restype = C.c_int64
-        L.or_delta_energy.argtypes = [C.c_int, p(C.c_int32), C.c_int, C.c_int, p(C.c_int32), p(C.c_uint8),
-                                      C.c_int64, C.c_int64]
-        L.or_delta_energy.restype = C.c_int64
-        L.or_pair_counts.argtypes = [C.c_int, p(C.c_int32), C.c_int, C.c_int, p(C.c_uint8), p(C.c_uint64)]
-        L.or_sro.argtypes = [C.c_int, p(C.c_int32), C.c_int, C.c_int, p(C.c_uint8), p(C.c_double),
-                             p(C.c_uint64)]
-        L.or_sweep.argtypes = [C.c_int, p(C.c_int32), p(C.c_int32), C.c_int, C.c_int, p(C.c_int32),
-                               C.c_uint64, C.c_uint32, C.c_int32, p(C.c_double), p(C.c_uint8),
-                               p(C.c_int64), p(C.c_uint64), p(C.c_int64), p(C.c_uint64)]
-        L.or_sweep.restype = C.c_int
-        L.or_exchange_accept.argtypes = [C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_uint64,
-                                         C.c_uint32, C.c_uint64]
-        L.or_exchange_accept.restype = C.c_int
-        L.or_enumerate.argtypes = [C.c_int, p(C.c_int32), C.c_int, C.c_int, p(C.c_int32), p(C.c_int32),
-                                   C.c_int64, p(C.c_int64), p(C.c_uint64)]
-        L.or_enumerate.restype = C.c_int64
-        _lib = L
+        _lib = _bind(LIB)
     return _lib
+
+
+@contextlib.contextmanager
+def using(path: str):
+    """Route every call of this module through another build of the oracle
+    (the planted-mistake tests load deliberately broken copies)."""
+    global _lib
+    saved = lib()
+    _lib = _bind(path)
+    try:
+        yield
+    finally:
+        _lib = saved
 
 
 def set_threads(n: int) -> None:

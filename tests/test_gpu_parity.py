@@ -85,6 +85,11 @@ def test_device_philox_matches_oracle(smcx, orc):
     got = smcx.smcx_device_philox(ctr, key)
     for k in range(0, 4096, 37):
         assert np.array_equal(got[k], orc.philox4x32(ctr[k], key))
+    # the published Random123 known answers, on the device itself
+    from test_oracle_philox_kat import RANDOM123_KAT
+    for c, k, want in RANDOM123_KAT:
+        out = smcx.smcx_device_philox(np.array([c], np.uint32), np.array(k, np.uint32))
+        assert [int(v) for v in out[0]] == list(want)
 
 
 @pytest.mark.parametrize("T", [1.0, 250.0, 800.0, 2000.0, 5000.0])
@@ -243,3 +248,37 @@ def test_create_device_borrows_torch_memory(smcx, orc):
     with pytest.raises(smcx.SmcxError) as e:
         smcx.smcx_create_device(d, bad.data_ptr(), job.epi, 950.0, stream.cuda_stream)
     assert e.value.status == smcx.E_INVALID
+
+
+def test_failed_table_upload_keeps_previous_tables(smcx, orc):
+    """A temperature change whose table upload fails (forced from the host
+    with SMCX_FAULT_TABLES) returns an error and leaves the context sweeping
+    on its previous tables and schedule: the trajectory equals the oracle's
+    at the old temperature."""
+    job = W.lattice_job((10, 10, 10), 4, 3, 30.0, np.full(8, 900.0), stream=64, name="table-fault")
+    note("table upload fault")
+    lat = smcx.Lattice(job.L, job.epi, job.sigma, job.seed, 900.0, block=(5, 5, 5))
+    ref = orc.OracleState(job.L, (5, 5, 5), job.epi, job.sigma, job.seed)
+    try:
+        lat.sweep(3)
+        ref.sweep(900.0, 3)
+        os.environ["SMCX_FAULT_TABLES"] = "1"
+        try:
+            with pytest.raises(smcx.SmcxError):
+                lat.set_temperature(1500.0)
+            with pytest.raises(smcx.SmcxError):
+                lat.set_schedule(np.linspace(2000.0, 1000.0, 50))
+        finally:
+            del os.environ["SMCX_FAULT_TABLES"]
+        lat.sweep(5)
+        ref.sweep(900.0, 5)
+        assert np.array_equal(lat.config(), ref.sigma)
+        assert lat.energy() == int(ref.E[0])
+        # and a later change goes through
+        lat.set_temperature(1200.0)
+        lat.sweep(2)
+        ref.sweep(1200.0, 2)
+        assert np.array_equal(lat.config(), ref.sigma)
+        assert lat.energy() == int(ref.E[0])
+    finally:
+        lat.close()
