@@ -9,8 +9,6 @@
 //   back, and reduces its accepted energy changes.  Lanes of one round never
 //   touch each other's sites, and LDS operations of one wavefront complete in
 //   program order, so no barrier separates the rounds.
-// pair_counts: N_m[p'][p] for energy recomputation and Warren-Cowley SRO
-//   (Eq. (SRO)).
 #include <type_traits>
 
 #include "device_common.h"
@@ -634,75 +632,6 @@ hipError_t launch_sweep_phase(int lattice, const DevLattice* d_lat, const WorkIt
     case 8: return launch_k<8>(d_lat, d_items, n_groups, t, colour, smax, stream);
     }
     return hipErrorInvalidValue;
-}
-
-// ---------------------------------------------------------------------------
-// Pair counts N_m[p'][p] (Eq. (SRO) numerator; also the energy, as
-// E = 1/2 sum N_m[p'][p] V_m(p', p)).  One thread per cell, neighbours read
-// straight from HBM through the caches; per-workgroup LDS counters.
-__global__ __launch_bounds__(256)
-void pair_counts_kernel(const uint8_t* __restrict__ g, int Lx, int Ly, int Lz, int K, int S,
-                        unsigned long long* __restrict__ counts)
-{
-    __shared__ unsigned int c[kMaxS * kMaxK * kMaxK];
-    for (int k = threadIdx.x; k < kMaxS * kMaxK * kMaxK; k += blockDim.x) c[k] = 0u;
-    __syncthreads();
-    const size_t ncell = (size_t)Lx * Ly * Lz;
-    for (size_t cell = (size_t)blockIdx.x * blockDim.x + threadIdx.x; cell < ncell;
-         cell += (size_t)gridDim.x * blockDim.x) {
-        const int x = (int)(cell % Lx), y = (int)((cell / Lx) % Ly), z = (int)(cell / ((size_t)Lx * Ly));
-        auto at = [&](int X, int Y, int Z, int b) -> uint32_t {
-            X = X < 0 ? X + Lx : (X >= Lx ? X - Lx : X);
-            Y = Y < 0 ? Y + Ly : (Y >= Ly ? Y - Ly : Y);
-            Z = Z < 0 ? Z + Lz : (Z >= Lz ? Z - Lz : Z);
-            return g[2 * (((size_t)Z * Ly + Y) * Lx + X) + b];
-        };
-        for (int b = 0; b < 2; ++b) {
-            const uint32_t si = at(x, y, z, b);
-            uint32_t h[3] = {0u, 0u, 0u};   // 4-bit species fields per shell
-            // shell 1: other sublattice, cells {-1,0}^3 (corner) or {0,1}^3 (body)
-            for (int e = 0; e < 8; ++e) {
-                const int d = b == 0 ? -1 : 0;
-                h[0] += 1u << (4 * at(x + d + (e & 1), y + d + ((e >> 1) & 1), z + d + ((e >> 2) & 1), 1 - b));
-            }
-            if (S >= 2) {
-                h[1] += 1u << (4 * at(x + 1, y, z, b));
-                h[1] += 1u << (4 * at(x - 1, y, z, b));
-                h[1] += 1u << (4 * at(x, y + 1, z, b));
-                h[1] += 1u << (4 * at(x, y - 1, z, b));
-                h[1] += 1u << (4 * at(x, y, z + 1, b));
-                h[1] += 1u << (4 * at(x, y, z - 1, b));
-            }
-            if (S >= 3) {
-                for (int u = -1; u <= 1; u += 2)
-                    for (int v = -1; v <= 1; v += 2) {
-                        h[2] += 1u << (4 * at(x + u, y + v, z, b));
-                        h[2] += 1u << (4 * at(x + u, y, z + v, b));
-                        h[2] += 1u << (4 * at(x, y + u, z + v, b));
-                    }
-            }
-            for (int m = 0; m < S; ++m)
-                for (int p = 0; p < K; ++p) {
-                    const uint32_t n = (h[m] >> (4 * p)) & 15u;
-                    if (n) atomicAdd(&c[(m * kMaxK + si) * kMaxK + p], n);
-                }
-        }
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < kMaxS * kMaxK * kMaxK; k += blockDim.x)
-        if (c[k]) atomicAdd(&counts[k], (unsigned long long)c[k]);
-}
-
-hipError_t launch_pair_counts(int lattice, const uint8_t* species, const int32_t L[3], int K, int S,
-                              unsigned long long* d_counts, hipStream_t stream)
-{
-    if (lattice == 1) return launch_pair_counts_fcc(species, L, K, S, d_counts, stream);
-    const size_t ncell = (size_t)L[0] * L[1] * L[2];
-    size_t groups = (ncell + 255) / 256;
-    if (groups > 8192) groups = 8192;
-    hipLaunchKernelGGL(pair_counts_kernel, dim3((unsigned)groups), dim3(256), 0, stream, species, L[0], L[1],
-                       L[2], K, S, d_counts);
-    return hipGetLastError();
 }
 
 __global__ void species_max_kernel(const uint8_t* __restrict__ g, size_t n, unsigned int* __restrict__ out)

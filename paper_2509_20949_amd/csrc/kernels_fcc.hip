@@ -430,58 +430,4 @@ hipError_t launch_sweep_phase_fcc(const DevLattice* d_lat, const WorkItem* d_ite
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// FCC pair counts: one thread per cell (4 sites), neighbours read through the
-// caches, 5-bit species fields (up to 24 neighbours per shell).
-__global__ __launch_bounds__(256)
-void pair_counts_fcc_kernel(const uint8_t* __restrict__ g, int Lx, int Ly, int Lz, int K, int S,
-                            unsigned long long* __restrict__ counts)
-{
-    using namespace fcc;
-    __shared__ unsigned int c[kMaxS * kMaxK * kMaxK];
-    for (int k = threadIdx.x; k < kMaxS * kMaxK * kMaxK; k += blockDim.x) c[k] = 0u;
-    __syncthreads();
-    const size_t ncell = (size_t)Lx * Ly * Lz;
-    for (size_t cell = (size_t)blockIdx.x * blockDim.x + threadIdx.x; cell < ncell;
-         cell += (size_t)gridDim.x * blockDim.x) {
-        const int x = (int)(cell % Lx), y = (int)((cell / Lx) % Ly), z = (int)(cell / ((size_t)Lx * Ly));
-        auto at = [&](int X, int Y, int Z) -> uint32_t {   // doubled coordinates
-            X = X < 0 ? X + 2 * Lx : (X >= 2 * Lx ? X - 2 * Lx : X);
-            Y = Y < 0 ? Y + 2 * Ly : (Y >= 2 * Ly ? Y - 2 * Ly : Y);
-            Z = Z < 0 ? Z + 2 * Lz : (Z >= 2 * Lz ? Z - 2 * Lz : Z);
-            const int b = sub_of_parity(X & 1, Y & 1, Z & 1);
-            return g[4 * (((size_t)(Z >> 1) * Ly + (Y >> 1)) * Lx + (X >> 1)) + b];
-        };
-        for (int b = 0; b < 4; ++b) {
-            const int X = 2 * x + SUB[b][0], Y = 2 * y + SUB[b][1], Z = 2 * z + SUB[b][2];
-            const uint32_t si = g[4 * cell + b];
-            uint32_t h[3] = {0u, 0u, 0u};
-            for (int k = 0; k < 12; ++k) h[0] += 1u << (5 * at(X + SH1[k][0], Y + SH1[k][1], Z + SH1[k][2]));
-            if (S >= 2)
-                for (int k = 0; k < 6; ++k) h[1] += 1u << (5 * at(X + SH2[k][0], Y + SH2[k][1], Z + SH2[k][2]));
-            if (S >= 3)
-                for (int k = 0; k < 24; ++k) h[2] += 1u << (5 * at(X + SH3[k][0], Y + SH3[k][1], Z + SH3[k][2]));
-            for (int m = 0; m < S; ++m)
-                for (int p = 0; p < K; ++p) {
-                    const uint32_t n = (h[m] >> (5 * p)) & 31u;
-                    if (n) atomicAdd(&c[(m * kMaxK + si) * kMaxK + p], n);
-                }
-        }
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < kMaxS * kMaxK * kMaxK; k += blockDim.x)
-        if (c[k]) atomicAdd(&counts[k], (unsigned long long)c[k]);
-}
-
-hipError_t launch_pair_counts_fcc(const uint8_t* species, const int32_t L[3], int K, int S,
-                                  unsigned long long* d_counts, hipStream_t stream)
-{
-    const size_t ncell = (size_t)L[0] * L[1] * L[2];
-    size_t groups = (ncell + 255) / 256;
-    if (groups > 8192) groups = 8192;
-    hipLaunchKernelGGL(pair_counts_fcc_kernel, dim3((unsigned)groups), dim3(256), 0, stream, species, L[0], L[1], L[2],
-                       K, S, d_counts);
-    return hipGetLastError();
-}
-
 }  // namespace smcx

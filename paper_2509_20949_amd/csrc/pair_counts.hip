@@ -1,0 +1,349 @@
+// pair_counts.hip -- pair counts N_m[p'][p] = #{(i, delta in shell m):
+// sigma_i = p', sigma_{i+delta} = p} of a lattice: the numerator of the
+// Warren-Cowley parameters (Eq. (SRO)) and, as E = 1/2 sum N_m[p'][p]
+// V_m(p', p), the energy of the EPI model.  One kernel serves both lattice
+// types (BCC and FCC).
+//
+// Each bond is counted once, from the half of every shell's displacement
+// vectors whose first nonzero component is positive: with B_m[a][b] the
+// count of (i, delta in that half) with sigma_i = a, sigma_{i+delta} = b,
+// the other half gives B_m transposed (substitute j = i + delta), so
+// N_m = B_m + B_m^T.  That halves the neighbour reads of a full count.
+//
+// Work: a task is a run of 64 cells along x of one (y, z) row, one cell per
+// lane; a wavefront takes tasks in turn.  The row and its neighbour rows are
+// wave-uniform (scalar addresses).  A lane loads every neighbour cell its
+// sites' half-shells reach (one word per cell: the cell's 2 or 4 site bytes),
+// forms per site and shell a packed histogram of the neighbour species, and
+// adds it into its own counters in LDS (16-bit fields, two species per
+// dword, one ds_add per dword).  Counters belong to one lane, so the adds
+// never collide; at the end the workgroup sums each counter over its lanes
+// and adds B and B^T into the 64-bit totals with a few global atomics.
+#include <algorithm>
+#include <utility>
+
+#include "device_common.h"
+
+namespace smcx {
+namespace pc {
+
+// Geometry in doubled coordinates (units of a/2).
+struct Geo {
+    int nsub;
+    int sub[4][3];     // site offsets in the cell
+    int nvec[3];       // shell sizes
+    int vec[3][24][3]; // shell vectors
+};
+
+constexpr Geo bcc_geo()
+{
+    Geo g{};
+    g.nsub = 2;
+    g.sub[1][0] = g.sub[1][1] = g.sub[1][2] = 1;
+    int n = 0;
+    for (int e = 0; e < 8; ++e) {   // shell 1: (+-1, +-1, +-1)
+        g.vec[0][n][0] = e & 1 ? 1 : -1;
+        g.vec[0][n][1] = e & 2 ? 1 : -1;
+        g.vec[0][n][2] = e & 4 ? 1 : -1;
+        ++n;
+    }
+    g.nvec[0] = n;
+    n = 0;
+    for (int a = 0; a < 3; ++a)     // shell 2: (+-2, 0, 0) and permutations
+        for (int s = -1; s <= 1; s += 2) {
+            g.vec[1][n][a] = 2 * s;
+            ++n;
+        }
+    g.nvec[1] = n;
+    n = 0;
+    for (int a = 0; a < 3; ++a)     // shell 3: (+-2, +-2, 0) and permutations
+        for (int s = -1; s <= 1; s += 2)
+            for (int t = -1; t <= 1; t += 2) {
+                g.vec[2][n][a] = 2 * s;
+                g.vec[2][n][(a + 1) % 3] = 2 * t;
+                ++n;
+            }
+    g.nvec[2] = n;
+    return g;
+}
+
+constexpr Geo fcc_geo()
+{
+    Geo g{};
+    g.nsub = 4;
+    const int sub[4][3] = {{0, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
+    for (int b = 0; b < 4; ++b)
+        for (int a = 0; a < 3; ++a) g.sub[b][a] = sub[b][a];
+    int n = 0;
+    for (int a = 0; a < 3; ++a)     // shell 1: (+-1, +-1, 0) and permutations
+        for (int s = -1; s <= 1; s += 2)
+            for (int t = -1; t <= 1; t += 2) {
+                g.vec[0][n][a] = s;
+                g.vec[0][n][(a + 1) % 3] = t;
+                ++n;
+            }
+    g.nvec[0] = n;
+    n = 0;
+    for (int a = 0; a < 3; ++a)     // shell 2: (+-2, 0, 0) and permutations
+        for (int s = -1; s <= 1; s += 2) {
+            g.vec[1][n][a] = 2 * s;
+            ++n;
+        }
+    g.nvec[1] = n;
+    n = 0;
+    for (int a = 0; a < 3; ++a)     // shell 3: (+-2, +-1, +-1) and permutations
+        for (int s = -1; s <= 1; s += 2)
+            for (int t = -1; t <= 1; t += 2)
+                for (int u = -1; u <= 1; u += 2) {
+                    g.vec[2][n][a] = 2 * s;
+                    g.vec[2][n][(a + 1) % 3] = t;
+                    g.vec[2][n][(a + 2) % 3] = u;
+                    ++n;
+                }
+    g.nvec[2] = n;
+    return g;
+}
+
+constexpr int fdiv2(int t) { return t >= 0 ? t / 2 : -((-t + 1) / 2); }
+
+// Neighbour cells are numbered (dz+1)*9 + (dy+1)*3 + (dx+1), d in {-1,0,1}^3.
+struct Bond {
+    int cell;
+    int sub;
+};
+struct Bonds {
+    int n[4][3];
+    Bond b[4][3][12];
+    bool used[27];
+};
+
+constexpr Bonds make_bonds(const Geo g)
+{
+    Bonds r{};
+    for (int b = 0; b < g.nsub; ++b)
+        for (int m = 0; m < 3; ++m) {
+            int n = 0;
+            for (int k = 0; k < g.nvec[m]; ++k) {
+                const int* v = g.vec[m][k];
+                const int first = v[0] != 0 ? v[0] : (v[1] != 0 ? v[1] : v[2]);
+                if (first < 0) continue;   // the other half: B^T
+                int cd[3] = {0, 0, 0}, par[3] = {0, 0, 0};
+                for (int a = 0; a < 3; ++a) {
+                    const int t = g.sub[b][a] + v[a];
+                    cd[a] = fdiv2(t);
+                    par[a] = t - 2 * cd[a];
+                }
+                int bp = -1;
+                for (int q = 0; q < g.nsub; ++q)
+                    if (g.sub[q][0] == par[0] && g.sub[q][1] == par[1] && g.sub[q][2] == par[2]) bp = q;
+                const int cell = (cd[2] + 1) * 9 + (cd[1] + 1) * 3 + (cd[0] + 1);
+                r.b[b][m][n] = Bond{cell, bp};
+                r.used[cell] = true;
+                ++n;
+            }
+            r.n[b][m] = n;
+        }
+    r.used[13] = true;   // the cell itself
+    return r;
+}
+
+template <int LAT> struct Tables {
+    static constexpr Geo geo = LAT == 1 ? fcc_geo() : bcc_geo();
+    static constexpr Bonds bonds = make_bonds(geo);
+};
+
+// Counters are 16 bits wide and shared by the two lanes l and l + 32 of a
+// wave.  A task adds at most 2 * n_sub * 12 to one of them (two lanes, each
+// with four FCC sites of one species and the 12 half-shell-3 neighbours of
+// that species), so a wave takes at most this many tasks before its
+// counters could wrap.
+constexpr uint32_t kMaxTasksPerWave = 512;
+static_assert(kMaxTasksPerWave * 2 * 4 * 12 < 65536, "pair-count counters could wrap");
+constexpr int kBinLanes = 32;   // counter columns per wave
+
+// Packed histogram of site B's neighbours in shell M (the half-shell
+// bonds), F bits per species: bond K of the list reads byte sub of
+// neighbour-cell word cell.  Expanded at compile time.
+template <int LAT, int F, int B, int M, int... Ks>
+__device__ __forceinline__ uint32_t half_shell(const uint32_t (&v)[27], std::integer_sequence<int, Ks...>)
+{
+    using T = Tables<LAT>;
+    uint32_t h = 0u;
+    ((h += 1u << (F * ((v[T::bonds.b[B][M][Ks].cell] >> (8 * T::bonds.b[B][M][Ks].sub)) & 255u))), ...);
+    return h;
+}
+
+// Loads of one task: the words of every neighbour cell the half-shells of
+// the cell at x reach, rows (y + dy, z + dz) (wave-uniform).
+template <int LAT, int... Os>
+__device__ __forceinline__ void load_cells(const uint8_t* g, int Lx, int Ly, int Lz, int y, int z, const int (&xo)[3],
+                                           uint32_t (&v)[27], std::integer_sequence<int, Os...>)
+{
+    using T = Tables<LAT>;
+    constexpr int NSUB = T::geo.nsub;
+    auto one = [&](auto oc) {
+        constexpr int o = decltype(oc)::value;
+        if constexpr (T::bonds.used[o]) {
+            constexpr int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+            const int yy = wrap_add(y + dy, Ly), zz = wrap_add(z + dz, Lz);
+            const size_t row = ((size_t)zz * (uint32_t)Ly + (uint32_t)yy) * (uint32_t)Lx;   // wave-uniform
+            const uint8_t* p = g + NSUB * (row + (uint32_t)xo[dx + 1]);
+            v[o] = NSUB == 4 ? gload<uint32_t>(p) : (uint32_t)gload<uint16_t>(p);
+        }
+    };
+    (one(std::integral_constant<int, Os>{}), ...);
+}
+
+}  // namespace pc
+
+// F: bits per species field of a histogram word (8 for K <= 4, 4 for
+// K <= 8).  D counter dwords per (shell, centre species): dword k holds
+// species k (low half) and species k + 16/F (high half).
+template <int LAT, int F, int SMAX>
+__global__ __launch_bounds__(256)
+void pair_counts_kernel(const uint8_t* __restrict__ g, int Lx, int Ly, int Lz, int K, uint32_t n_tasks,
+                        unsigned long long* __restrict__ counts)
+{
+    using T = pc::Tables<LAT>;
+    constexpr int NSUB = T::geo.nsub;
+    constexpr int D = F == 8 ? 2 : 4;
+    constexpr int HI = 16 / F;                       // species offset of the high half
+    constexpr uint32_t MASK = F == 8 ? 0x00FF00FFu : 0x000F000Fu;
+    constexpr int C = pc::kBinLanes;
+    extern __shared__ uint32_t bins[];               // [wave][nb][C]
+
+    const int lane = threadIdx.x % kWave;
+    const int wave = wave_id();
+    const int nwv = blockDim.x / kWave;
+    const int nb = SMAX * K * D;
+    uint32_t* mine = bins + (size_t)wave * nb * C + (lane % C);
+    if (lane < C)
+        for (int d = 0; d < nb; ++d) mine[d * C] = 0u;
+
+    const uint32_t nwaves = gridDim.x * (uint32_t)nwv;
+    const uint32_t nchunk = (uint32_t)(Lx + kWave - 1) / kWave;
+    // task t: cells (t % nchunk) * 64 + lane of row t / nchunk
+    auto locate = [&](uint32_t t, int& y, int& z, int (&xo)[3]) -> bool {
+        const uint32_t c = t % nchunk, r = t / nchunk;
+        y = (int)(r % (uint32_t)Ly);
+        z = (int)(r / (uint32_t)Ly);
+        const int x = (int)c * kWave + lane;
+        const int xc = x < Lx ? x : Lx - 1;
+        xo[0] = xc == 0 ? Lx - 1 : xc - 1;
+        xo[1] = xc;
+        xo[2] = xc == Lx - 1 ? 0 : xc + 1;
+        return x < Lx;
+    };
+    const auto cells = std::make_integer_sequence<int, 27>{};
+    uint32_t t = blockIdx.x * (uint32_t)nwv + (uint32_t)wave;
+    uint32_t v[27], vn[27];
+    int y, z, xo[3];
+    bool valid = false;
+    if (t < n_tasks) {
+        valid = locate(t, y, z, xo);
+        pc::load_cells<LAT>(g, Lx, Ly, Lz, y, z, xo, v, cells);
+    }
+    while (t < n_tasks) {
+        // the next task's loads go out before this task's counting
+        const uint32_t tn = t + nwaves;
+        bool valid_n = false;
+        if (tn < n_tasks) {
+            int yn, zn, xon[3];
+            valid_n = locate(tn, yn, zn, xon);
+            pc::load_cells<LAT>(g, Lx, Ly, Lz, yn, zn, xon, vn, cells);
+        }
+        if (valid) {
+            auto site = [&](auto bc) {
+                constexpr int b = decltype(bc)::value;
+                const uint32_t a = min((v[13] >> (8 * b)) & 255u, (uint32_t)(K - 1));
+                uint32_t* base = mine + a * (D * C);
+                auto shell = [&](auto mc) {
+                    constexpr int m = decltype(mc)::value;
+                    if constexpr (m < SMAX) {
+                        const uint32_t h = pc::half_shell<LAT, F, b, m>(
+                            v, std::make_integer_sequence<int, T::bonds.n[b][m]>{});
+#pragma unroll
+                        for (int k = 0; k < D; ++k) atomicAdd(base + (m * K * D + k) * C, (h >> (F * k)) & MASK);
+                    }
+                };
+                shell(std::integral_constant<int, 0>{});
+                shell(std::integral_constant<int, 1>{});
+                shell(std::integral_constant<int, 2>{});
+            };
+            site(std::integral_constant<int, 0>{});
+            site(std::integral_constant<int, 1>{});
+            if constexpr (NSUB == 4) {
+                site(std::integral_constant<int, 2>{});
+                site(std::integral_constant<int, 3>{});
+            }
+        }
+#pragma unroll
+        for (int o = 0; o < 27; ++o) v[o] = vn[o];
+        valid = valid_n;
+        t = tn;
+    }
+    __syncthreads();
+    // Workgroup totals of each counter word; B and B^T into the 64-bit sums.
+    for (int d = threadIdx.x; d < nb; d += blockDim.x) {
+        uint32_t lo = 0u, hi = 0u;
+        for (int w = 0; w < nwv; ++w) {
+            const uint32_t* row = bins + ((size_t)w * nb + d) * C;
+            for (int j = 0; j < C; ++j) {
+                const uint32_t val = row[(j + d) & (C - 1)];   // rotated: lanes hit distinct banks
+                lo += val & 0xffffu;
+                hi += val >> 16;
+            }
+        }
+        const int m = d / (K * D), a = (d / D) % K, k = d % D;
+        if (lo) {
+            atomicAdd(&counts[(m * kMaxK + a) * kMaxK + k], (unsigned long long)lo);
+            atomicAdd(&counts[(m * kMaxK + k) * kMaxK + a], (unsigned long long)lo);
+        }
+        if (hi) {
+            atomicAdd(&counts[(m * kMaxK + a) * kMaxK + k + HI], (unsigned long long)hi);
+            atomicAdd(&counts[(m * kMaxK + k + HI) * kMaxK + a], (unsigned long long)hi);
+        }
+    }
+}
+
+template <int LAT, int F>
+static hipError_t launch_pc(const uint8_t* species, const int32_t L[3], int K, int S, unsigned long long* d_counts,
+                            hipStream_t stream)
+{
+    constexpr int D = F == 8 ? 2 : 4;
+    const int nb = S * K * D;
+    // LDS per workgroup: waves x nb counters x 32 columns x 4 bytes
+    const int waves_per_group = 4;
+    const uint64_t nchunk = ((uint64_t)L[0] + kWave - 1) / kWave;
+    const uint64_t tasks = nchunk * (uint64_t)L[1] * (uint64_t)L[2];
+    if (tasks > 0xffffffffull) return hipErrorInvalidValue;
+    uint64_t waves = (tasks + pc::kMaxTasksPerWave - 1) / pc::kMaxTasksPerWave;
+    waves = std::max<uint64_t>(waves, std::min<uint64_t>(tasks, 4096));
+    const uint64_t groups = (waves + waves_per_group - 1) / waves_per_group;
+    const size_t lds = (size_t)waves_per_group * nb * pc::kBinLanes * sizeof(uint32_t);
+    const dim3 grid((unsigned)groups), block((unsigned)(waves_per_group * kWave));
+    switch (S) {
+    case 1: hipLaunchKernelGGL((pair_counts_kernel<LAT, F, 1>), grid, block, lds, stream, species, L[0], L[1], L[2], K,
+                               (uint32_t)tasks, d_counts); break;
+    case 2: hipLaunchKernelGGL((pair_counts_kernel<LAT, F, 2>), grid, block, lds, stream, species, L[0], L[1], L[2], K,
+                               (uint32_t)tasks, d_counts); break;
+    case 3: hipLaunchKernelGGL((pair_counts_kernel<LAT, F, 3>), grid, block, lds, stream, species, L[0], L[1], L[2], K,
+                               (uint32_t)tasks, d_counts); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// d_counts ([kMaxS][kMaxK][kMaxK] uint64) receives N_m[p'][p] added to what
+// it holds; the caller clears it first.
+hipError_t launch_pair_counts(int lattice, const uint8_t* species, const int32_t L[3], int K, int S,
+                              unsigned long long* d_counts, hipStream_t stream)
+{
+    if (K < 1 || K > kMaxK || S < 1 || S > kMaxS) return hipErrorInvalidValue;
+    if (lattice == 1) return K <= 4 ? launch_pc<1, 8>(species, L, K, S, d_counts, stream)
+                                    : launch_pc<1, 4>(species, L, K, S, d_counts, stream);
+    return K <= 4 ? launch_pc<0, 8>(species, L, K, S, d_counts, stream)
+                  : launch_pc<0, 4>(species, L, K, S, d_counts, stream);
+}
+
+}  // namespace smcx

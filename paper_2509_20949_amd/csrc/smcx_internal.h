@@ -140,15 +140,13 @@ void build_thresholds(double T, double* out /* kTab */);
 // weights have three-digit forms; both lattice kernels read it).
 int build_wtab(const int32_t* epi, int K, int S, int kmax, int smax, int bias, bool dot_ok, int32_t* out);
 
-// Launchers (kernels.hip).  Return hipSuccess or the launch error.
+// Launchers (kernels.hip, kernels_fcc.hip, pair_counts.hip).  Return hipSuccess or the launch error.
 hipError_t launch_sweep_phase(int lattice, const DevLattice* d_lat, const WorkItem* d_items, int n_groups,
                               int t, int colour, int kmax, int smax, hipStream_t stream);
 hipError_t launch_pair_counts(int lattice, const uint8_t* species, const int32_t L[3], int K, int S,
                               unsigned long long* d_counts, hipStream_t stream);
 hipError_t launch_sweep_phase_fcc(const DevLattice* d_lat, const WorkItem* d_items, int n_groups, int t,
                                   int colour, int smax, hipStream_t stream);
-hipError_t launch_pair_counts_fcc(const uint8_t* species, const int32_t L[3], int K, int S,
-                                  unsigned long long* d_counts, hipStream_t stream);
 hipError_t launch_species_max(const uint8_t* species, size_t n, unsigned int* d_max, hipStream_t stream);
 hipError_t launch_thresholds(const double* d_tab, const int32_t* d_dE, int n, double* d_out, hipStream_t stream);
 hipError_t launch_accept_bounds(const double* d_tab, const uint32_t* d_u, int n, int32_t* d_lo, int32_t* d_hi,
