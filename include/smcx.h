@@ -235,6 +235,31 @@ size_t smcx_server_footprint(const smcx_desc* desc);
 void smcx_server_destroy(smcx_server* srv);
 const char* smcx_server_last_error(const smcx_server* srv);
 
+/* ---- sweeps without device allocation -----------------------------------
+ * For callers that cannot allocate device memory: code running under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * smcx_sweep_noalloc runs sweeps sweep0 .. sweep0+n-1 of the lattice in the
+ * caller's device buffer d_species (N bytes, canonical order, 4-byte
+ * aligned; updated in place) on hip_stream (NULL: the null stream) of the
+ * current device, with desc, EPI and T as for smcx_create_device and a fixed
+ * temperature.  The trajectory is that of a context created on the same
+ * inputs, set to sweep index sweep0 (smcx_set_state) and advanced by
+ * smcx_sweep(n), bit for bit.  dE_ueV and accepted (nullable) receive the
+ * energy change and the number of accepted swaps of these n sweeps.
+ * It calls no hipMalloc or hipFree: the lattice descriptor, the
+ * running-state slots, the threshold table and the pair-weight rows live in
+ * a library-owned device array of 32 KiB per device (held until the process
+ * ends; every valid desc fits, K <= 8 and S <= 3 need at most 22,784 bytes,
+ * and a larger need is rejected with SMCX_E_UNSUPPORTED).  All calls on one
+ * device share that array: calls that overlap in time on one device (from
+ * several threads, or on several streams) race and must not be made.  The
+ * call validates the species on the device and synchronises hip_stream
+ * before returning.  Errors: as smcx_create_device, RANGE if sweep0 + n
+ * passes 2^32, DEVICE. */
+smcx_status smcx_sweep_noalloc(const smcx_desc* desc, uint8_t* d_species, const int32_t* epi_ueV,
+                               double T_kelvin, uint64_t sweep0, int32_t n, void* hip_stream,
+                               int64_t* dE_ueV, uint64_t* accepted);
+
 /* ---- verification hooks ---------------------------------------------------
  * smcx_threshold_table: the host table the library builds for T (768 doubles:
  * T0, T1, T2).  smcx_device_thresholds: the threshold products computed by

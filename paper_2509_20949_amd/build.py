@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsmcx.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["kernels.hip", "kernels_fcc.hip", "pair_counts.hip", "api.hip", "batch.hip", "serve.hip", "tables.cpp"]
+SOURCES = ["kernels.hip", "kernels_fcc.hip", "pair_counts.hip", "api.hip", "batch.hip", "serve.hip", "noalloc.hip", "tables.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

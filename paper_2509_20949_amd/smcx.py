@@ -92,6 +92,7 @@ def lib():
     _sig(L, "smcx_device_thresholds", st, [dbl, _P(i32), i32, _P(dbl)])
     _sig(L, "smcx_device_philox", st, [_P(C.c_uint32), _P(C.c_uint32), i32, _P(C.c_uint32)])
     _sig(L, "smcx_device_accept_bounds", st, [dbl, _P(C.c_uint32), i32, _P(i32), _P(i32)])
+    _sig(L, "smcx_sweep_noalloc", st, [pd, vp, _P(i32), dbl, u64, i32, vp, _P(i64), _P(u64)])
     _sig(L, "smcx_weight_rows", st, [i32, i32, i32, _P(i32), _P(i32), _P(i32), _P(i32), _P(i32), C.c_size_t])
     _lib = L
     return L
@@ -140,6 +141,18 @@ def smcx_create_device(desc: smcx_desc, d_species_ptr: int, epi_ueV, T_kelvin: f
     _check(lib().smcx_create_device(C.byref(desc), C.c_void_p(d_species_ptr), _ptr(e, C.c_int32),
                                     float(T_kelvin), C.c_void_p(hip_stream or None), C.byref(out)))
     return out.value
+
+
+def smcx_sweep_noalloc(desc: smcx_desc, d_species_ptr: int, epi_ueV, T_kelvin: float, sweep0: int, n: int,
+                       hip_stream: int = 0):
+    """n sweeps of the lattice at d_species_ptr from sweep index sweep0 with no
+    device allocation; returns (energy change, accepted swaps)."""
+    e = np.ascontiguousarray(epi_ueV, dtype=np.int32)
+    dE, acc = C.c_int64(), C.c_uint64()
+    _check(lib().smcx_sweep_noalloc(C.byref(desc), C.c_void_p(d_species_ptr), _ptr(e, C.c_int32), float(T_kelvin),
+                                    int(sweep0), int(n), C.c_void_p(hip_stream or None), C.byref(dE),
+                                    C.byref(acc)))
+    return dE.value, acc.value
 
 
 def smcx_set_temperature(ctx, T_kelvin: float):
