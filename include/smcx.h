@@ -285,6 +285,16 @@ smcx_status smcx_weight_rows(int32_t lattice, int32_t K, int32_t S, const int32_
 smcx_status smcx_device_thresholds(double T_kelvin, const int32_t* dE, int32_t n, double* out);
 smcx_status smcx_device_accept_bounds(double T_kelvin, const uint32_t* u, int32_t n, int32_t* lo, int32_t* hi);
 smcx_status smcx_device_philox(const uint32_t* ctr, const uint32_t key[2], int32_t n, uint32_t* out);
+/* smcx_device_check_accept_bounds: the claim above, checked on the device
+ * for every 32-bit draw u at temperature T (the BCC draws are the even ones,
+ * the FCC draws all of them): violations_lo counts draws whose bound lo or
+ * lo - 1 (where in (0, 2^24)) fails the table test, violations_hi those
+ * whose hi + 1 or hi + 2 passes it; max_log2_error receives the largest
+ * |(32 - log2 float(u)) - (32 - log2 u)| of the device's FP32 logarithm over
+ * u > 0, max_band the widest hi - lo.  Every output is nullable; synchronous. */
+smcx_status smcx_device_check_accept_bounds(double T_kelvin, uint64_t* violations_lo, uint64_t* violations_hi,
+                                            double* max_log2_error, int32_t* max_band);
+
 
 #ifdef __cplusplus
 }

@@ -697,6 +697,32 @@ smcx_status smcx_device_accept_bounds(double T, const uint32_t* u, int32_t n, in
     return SMCX_OK;
 }
 
+smcx_status smcx_device_check_accept_bounds(double T, uint64_t* violations_lo, uint64_t* violations_hi,
+                                            double* max_log2_error, int32_t* max_band)
+{
+    smcx_status st = validate_T(T);
+    if (st) return st;
+    double tab[kTab];
+    build_thresholds(T, tab);
+    double* d_tab = nullptr;
+    unsigned long long* d_out = nullptr;
+    unsigned long long h[4] = {0, 0, 0, 0};
+    hipError_t e = hipMalloc(&d_tab, sizeof(tab));
+    if (e == hipSuccess) e = hipMalloc(&d_out, sizeof(h));
+    if (e == hipSuccess) e = hipMemcpy(d_tab, tab, sizeof(tab), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_out, h, sizeof(h), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_accept_bounds_check(d_tab, d_out, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(h, d_out, sizeof(h), hipMemcpyDeviceToHost);
+    if (d_tab) (void)hipFree(d_tab);
+    if (d_out) (void)hipFree(d_out);
+    if (e != hipSuccess) return fail_global(SMCX_E_DEVICE, "accept bounds check: %s", hipGetErrorString(e));
+    if (violations_lo) *violations_lo = h[0];
+    if (violations_hi) *violations_hi = h[1];
+    if (max_log2_error) std::memcpy(max_log2_error, &h[2], sizeof(double));
+    if (max_band) *max_band = (int32_t)h[3];
+    return SMCX_OK;
+}
+
 smcx_status smcx_device_philox(const uint32_t* ctr, const uint32_t key[2], int32_t n, uint32_t* out)
 {
     if (!ctr || !key || !out || n < 0) return fail_global(SMCX_E_INVALID, "bad argument");

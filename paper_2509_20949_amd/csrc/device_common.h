@@ -95,18 +95,20 @@ template <class T> __device__ __forceinline__ void gstore(uint8_t* p, T v)
     *(__attribute__((address_space(1))) T*)p = v;
 }
 
-// Bounds of the Metropolis test (Eq. (3)) for an acceptance draw u (even).
+// Bounds of the Metropolis test (Eq. (3)) for an acceptance draw u.
 // The exact test accepts an uphill change dE iff u < thr(dE), thr the FP64
 // table product, equal to 2^32 exp(-dE / k_B T) to a relative 1e-12.  Let x
 // be the energy with 2^32 exp(-x / k_B T) = u, x = (32 - log2 u) ln2 k_B T.
-// e below is x in FP32 from v_log_f32; over all u > 0 the device's
-// 32 - log2(float(u)) is within 2.0e-6 of the exact value (checked
-// exhaustively), so |e - x| <= 6.3e-6 ln2 k_B T + 2^-23 x <= 2 micro-eV
-// for T <= 5000 K, and the FP32 sums e -+ M add at most 0.6 more.  Hence
-// with M = 8: every dE <= lo lies below x by more than the table's error
-// and is accepted by the exact test, every dE > hi is rejected, and only
-// lo < dE <= hi (and u = 0, where x is infinite but thr may underflow)
-// need the table.  c = ln2 k_B T in micro-eV, as a float.
+// e below is x in FP32 from v_log_f32.  Over every u > 0 the device's
+// 32 - log2(float(u)) is within 2.0e-6 of 32 - log2(u) (checked for all
+// 2^32 draws by smcx_device_check_accept_bounds), so with c = ln2 k_B T
+// rounded to FP32 and x <= 32 c:  |e - x| <= 2.0e-6 c + 2^-23 x <= 1.8
+// micro-eV for T <= 5000 K.  e -+ M rounds to FP32 within 0.5 (e < 2^24)
+// and truncates to an integer, so with M = 8 the bound lo lies more than
+// 5.7 micro-eV below x and hi + 1 more than 4.7 above it: every dE <= lo
+// passes the exact test and every dE > hi fails it.  Only lo < dE <= hi
+// (and u = 0, where x is infinite but thr may underflow) need the table.
+// c = ln2 k_B T in micro-eV, as a float.
 constexpr float kAcceptMargin = 8.0f;
 __device__ __forceinline__ void accept_bounds(uint32_t u, float c, int& lo, int& hi)
 {

@@ -689,6 +689,61 @@ hipError_t launch_accept_bounds(const double* d_tab, const uint32_t* d_u, int n,
     return hipGetLastError();
 }
 
+// Exhaustive check of the acceptance bounds over every 32-bit draw u (the
+// BCC draws are the even ones, the FCC draws all of them).  For each u the
+// kernel takes (lo, hi) as the sweep kernels do and evaluates the exact
+// test of Eq. (3) on the FP64 table products at dE = lo, lo - 1 (must
+// accept) and hi + 1, hi + 2 (must reject), for those dE in (0, 2^24).
+// out[0] counts draws violating the lower bound, out[1] the upper bound,
+// out[2] holds the largest |(32 - log2 float(u)) - (32 - log2 u)| as the
+// bits of a non-negative double (u > 0), out[3] the widest band hi - lo.
+__global__ __launch_bounds__(256) void accept_bounds_check_kernel(const double* __restrict__ tab,
+                                                                  unsigned long long* __restrict__ out)
+{
+    const float c = (float)tab[kTabLn2kT];
+    unsigned long long bad_lo = 0, bad_hi = 0;
+    double max_err = 0.0;
+    int max_band = 0;
+    auto thr = [&](int e) {
+        return (tab[512 + (e >> 16)] * tab[256 + ((e >> 8) & 255)]) * tab[e & 255];
+    };
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < (1ull << 32); v += stride) {
+        const uint32_t u = (uint32_t)v;
+        int lo, hi;
+        accept_bounds(u, c, lo, hi);
+        max_band = max(max_band, hi - lo);
+        if (u == 0u) continue;   // the kernels always consult the table for u = 0
+        const double du = (double)u;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int a = lo - k, b = hi + 1 + k;
+            if (a > 0 && a < (1 << 24) && !(du < thr(a))) ++bad_lo;
+            if (b > 0 && b < (1 << 24) && (du < thr(b))) ++bad_hi;
+        }
+        const double l = (double)(32.0f - __builtin_amdgcn_logf((float)u));
+        max_err = fmax(max_err, fabs(l - (32.0 - log2(du))));
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        bad_lo += __shfl_xor(bad_lo, o, kWave);
+        bad_hi += __shfl_xor(bad_hi, o, kWave);
+        max_err = fmax(max_err, __shfl_xor(max_err, o, kWave));
+        max_band = max(max_band, __shfl_xor(max_band, o, kWave));
+    }
+    if ((threadIdx.x % kWave) == 0) {
+        if (bad_lo) atomicAdd(&out[0], bad_lo);
+        if (bad_hi) atomicAdd(&out[1], bad_hi);
+        atomicMax(&out[2], (unsigned long long)__double_as_longlong(max_err));
+        atomicMax(&out[3], (unsigned long long)max_band);
+    }
+}
+
+hipError_t launch_accept_bounds_check(const double* d_tab, unsigned long long* d_out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(accept_bounds_check_kernel, dim3(8192), dim3(256), 0, stream, d_tab, d_out);
+    return hipGetLastError();
+}
+
 __global__ void philox_kernel(const uint32_t* __restrict__ ctr, uint32_t k0, uint32_t k1, int n,
                               uint32_t* __restrict__ out)
 {

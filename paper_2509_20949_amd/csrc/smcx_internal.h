@@ -151,6 +151,7 @@ hipError_t launch_species_max(const uint8_t* species, size_t n, unsigned int* d_
 hipError_t launch_thresholds(const double* d_tab, const int32_t* d_dE, int n, double* d_out, hipStream_t stream);
 hipError_t launch_accept_bounds(const double* d_tab, const uint32_t* d_u, int n, int32_t* d_lo, int32_t* d_hi,
                                 hipStream_t stream);
+hipError_t launch_accept_bounds_check(const double* d_tab, unsigned long long* d_out, hipStream_t stream);
 hipError_t launch_philox(const uint32_t* d_ctr, uint32_t k0, uint32_t k1, int n, uint32_t* d_out,
                          hipStream_t stream);
 

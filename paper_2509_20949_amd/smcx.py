@@ -93,6 +93,7 @@ def lib():
     _sig(L, "smcx_device_philox", st, [_P(C.c_uint32), _P(C.c_uint32), i32, _P(C.c_uint32)])
     _sig(L, "smcx_device_accept_bounds", st, [dbl, _P(C.c_uint32), i32, _P(i32), _P(i32)])
     _sig(L, "smcx_sweep_noalloc", st, [pd, vp, _P(i32), dbl, u64, i32, vp, _P(i64), _P(u64)])
+    _sig(L, "smcx_device_check_accept_bounds", st, [dbl, _P(u64), _P(u64), _P(dbl), _P(i32)])
     _sig(L, "smcx_weight_rows", st, [i32, i32, i32, _P(i32), _P(i32), _P(i32), _P(i32), _P(i32), C.c_size_t])
     _lib = L
     return L
@@ -257,6 +258,14 @@ def smcx_device_accept_bounds(T_kelvin: float, u):
     _check(lib().smcx_device_accept_bounds(float(T_kelvin), _ptr(v, C.c_uint32), int(v.size), _ptr(lo, C.c_int32),
                                            _ptr(hi, C.c_int32)))
     return lo, hi
+
+
+def smcx_device_check_accept_bounds(T_kelvin: float):
+    """Exhaustive device check of the acceptance bounds over all 2^32 draws:
+    (violations below, violations above, max log2 error, widest band)."""
+    a, b, e, w = C.c_uint64(), C.c_uint64(), C.c_double(), C.c_int32()
+    _check(lib().smcx_device_check_accept_bounds(float(T_kelvin), C.byref(a), C.byref(b), C.byref(e), C.byref(w)))
+    return a.value, b.value, e.value, w.value
 
 
 def smcx_device_philox(ctr, key) -> np.ndarray:
