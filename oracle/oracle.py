@@ -36,6 +36,7 @@ def _bind(path: str):
     L = C.CDLL(path)
     p = C.POINTER
     L.or_set_threads.argtypes = [C.c_int]
+    L.or_set_fixed_z.argtypes = [C.c_int]
     L.or_get_threads.restype = C.c_int
     L.or_philox4x32_10.argtypes = [p(C.c_uint32), p(C.c_uint32), p(C.c_uint32)]
     L.or_philox4x64_10.argtypes = [p(C.c_uint64), p(C.c_uint64), p(C.c_uint64)]
@@ -103,6 +104,17 @@ def using(path: str):
 def set_threads(n: int) -> None:
     """Worker threads of the oracle (results are identical for any count)."""
     lib().or_set_threads(int(n))
+
+
+@contextlib.contextmanager
+def fixed_z(on: bool = True):
+    """Within the block: the z-slab schedule (block grid shifted along x and y
+    only)."""
+    lib().or_set_fixed_z(1 if on else 0)
+    try:
+        yield
+    finally:
+        lib().or_set_fixed_z(0)
 
 
 def get_threads() -> int:
@@ -263,7 +275,8 @@ def exchange_accept(Ea, Eb, Ta, Tb, seed, k, round_):
 class OracleState:
     """A lattice advanced by the oracle, sweep by sweep."""
 
-    def __init__(self, L, B, epi, sigma, seed, s0=0, lattice=BCC):
+    def __init__(self, L, B, epi, sigma, seed, s0=0, lattice=BCC, fixed_z=False):
+        self.fixed_z = bool(fixed_z)
         self.lattice = int(lattice)
         self.L = _L(L)
         self.B = _L(B)
@@ -280,17 +293,21 @@ class OracleState:
         Ts = np.ascontiguousarray(np.broadcast_to(np.asarray(T, np.float64), (n,)), np.float64)
         Et = np.zeros(n, np.int64) if trace_E else None
         Ct = np.zeros((n, self.S, self.K, self.K), np.uint64) if trace_counts else None
-        rc = lib().or_sweep(
+        with fixed_z(self.fixed_z):
+            rc = self._sweep(n, Ts, Et, Ct)
+        if rc != 0:
+            raise ValueError("oracle rejected the sweep arguments")
+        self.s += n
+        return Et, Ct
+
+    def _sweep(self, n, Ts, Et, Ct):
+        return lib().or_sweep(
             self.lattice, _ptr(self.L, C.c_int32), _ptr(self.B, C.c_int32), self.S, self.K,
             _ptr(self.epi, C.c_int32), C.c_uint64(self.seed), C.c_uint32(self.s), n,
             _ptr(Ts, C.c_double), _ptr(self.sigma, C.c_uint8), _ptr(self.E, C.c_int64),
             _ptr(self.accepted, C.c_uint64),
             _ptr(Et, C.c_int64) if Et is not None else None,
             _ptr(Ct, C.c_uint64) if Ct is not None else None)
-        if rc != 0:
-            raise ValueError("oracle rejected the sweep arguments")
-        self.s += n
-        return Et, Ct
 
 
 def enumerate_configs(L, epi, comp, max_cfg=5_000_000, with_counts=False, lattice=BCC):

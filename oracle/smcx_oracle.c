@@ -48,6 +48,13 @@ static int g_threads = 1;
 void or_set_threads(int n) { g_threads = n < 1 ? 1 : n; }
 int or_get_threads(void) { return g_threads; }
 
+/* Lattice parallelism with ghost layers (Section "Distributed SMC-X"): a
+ * lattice cut into z-slabs keeps its link cells aligned to the slab
+ * boundaries, so the per-sweep origin shift of the block grid is applied
+ * along x and y only.  or_set_fixed_z(1) selects that schedule. */
+static int g_fixed_z = 0;
+void or_set_fixed_z(int on) { g_fixed_z = on != 0; }
+
 /* ------------------------------------------------------------------------ */
 /* Philox (Salmon et al., SC'11, "Parallel random numbers: as easy as 1, 2,  */
 /* 3").  State: four counter words and two key words.  One round multiplies */
@@ -368,6 +375,7 @@ void or_sweep_shift(const int32_t L[3], uint64_t seed, uint32_t s, int32_t shift
     uint32_t r[4];
     or_philox4x32_10(ctr, key, r);
     for (int a = 0; a < 3; ++a) shift[a] = (int32_t)(((uint64_t)r[a] * (uint64_t)L[a]) >> 32);
+    if (g_fixed_z) shift[2] = 0;
 }
 
 /* base (nullable, one entry per cell): the cell whose local coordinates are

@@ -52,6 +52,8 @@ extern "C" {
 /* Threads for the trials of one (colour, sub-colour) set and for pair sums;
  * results are bit-identical for every thread count. */
 void or_set_threads(int n);
+/* 1: the block grid shifts along x and y only (z-slab decomposition). */
+void or_set_fixed_z(int on);
 int or_get_threads(void);
 
 /* Philox4x32-10 and its 4x64-10 sibling (same round structure, wider words). */

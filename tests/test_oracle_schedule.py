@@ -127,3 +127,19 @@ def test_conflict_free_small_blocks(orc, L):
 def test_conflict_free_gpu_block_widths(orc, L):
     for B, s in [((12, 12, 12), 0), ((8, 10, 12), 5)]:
         audit(orc, L, B, seed=99, s=s)
+
+
+def test_fixed_z_schedule(orc):
+    """The z-slab schedule: the block grid shifts along x and y as before and
+    never along z; it stays conflict-free, every site once per sweep."""
+    for s in range(30):
+        free = orc.sweep_shift((64, 64, 64), 5, s)
+        with orc.fixed_z():
+            fixed = orc.sweep_shift((64, 64, 64), 5, s)
+        assert fixed[2] == 0 and fixed[0] == free[0] and fixed[1] == free[1]
+    with orc.fixed_z():
+        for L, B, s in [((12, 11, 16), (4, 4, 4), 3), ((9, 10, 12), (3, 4, 3), 1), ((8, 8, 24), (4, 4, 6), 2)]:
+            audit(orc, L, B, seed=7, s=s)
+            col, sub, blk = orc.schedule(L, B, 7, s)
+            keys = col.astype(np.int64) * 54 + sub
+            assert np.bincount(keys, minlength=432).sum() == W.n_sites(L)
