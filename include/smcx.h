@@ -130,6 +130,37 @@ smcx_status smcx_create(const smcx_desc* desc, const uint8_t* species, const int
 smcx_status smcx_create_device(const smcx_desc* desc, uint8_t* d_species, const int32_t* epi_ueV,
                                double T_kelvin, void* hip_stream, smcx_ctx** out);
 
+/* ---- one z-slab of a larger lattice (lattice parallelism with ghost
+ * layers, Section "Distributed SMC-X") --------------------------------------
+ * smcx_create_slab: a BCC context for cells 0..L[2]-1 along z of a slab
+ * whose first plane is plane z_offset of the whole lattice (its cells keep
+ * their global ids in the random-number counters; L[0], L[1] are the whole
+ * lattice's).  d_buffer (borrowed, 4-byte aligned, updated in place) holds
+ * L[2] + 4 planes of 2*L[0]*L[1] bytes: planes z_offset-2, z_offset-1 of the
+ * lattice (the halo below), the slab's own L[2] planes, then planes
+ * z_offset+L[2], z_offset+L[2]+1 (the halo above); all hold valid species.
+ * The block grid of a slab is not shifted along z, so its blocks stay
+ * aligned to the slab boundaries (x and y shift as usual); with an even
+ * number of blocks per slab the global colouring is the one of a single
+ * lattice of all slabs stacked.  A phase reads the halo planes and may
+ * write the first plane of either halo (the first-neighbour ring of its
+ * edge blocks): z-blocks of even index, including the lowest, run when
+ * colour bit 2 is 0 and may write plane z_offset-1; odd ones, including the
+ * highest, run otherwise and may write plane z_offset+L[2].
+ *   smcx_sweep on a slab context treats the slab as the whole lattice,
+ * periodic along z: before every phase it copies its own wrapped planes
+ * into the halos and afterwards copies a written halo plane back (the
+ * exchange with itself).  smcx_slab_phase enqueues the next n colour phases
+ * without any exchange: the caller brings the halos up to date between
+ * phases (e.g. with the neighbouring slabs' planes) and returns written
+ * halo planes to their owners.  Energy queries, smcx_sro and smcx_get_config
+ * cover the slab's own planes, taken as periodic along z (exact when the
+ * slab is the whole lattice).  Errors: as smcx_create_device; UNSUPPORTED
+ * for FCC. */
+smcx_status smcx_create_slab(const smcx_desc* desc, uint8_t* d_buffer, uint32_t z_offset, const int32_t* epi_ueV,
+                             double T_kelvin, void* hip_stream, smcx_ctx** out);
+smcx_status smcx_slab_phase(smcx_ctx* ctx, int32_t n);
+
 /* Temperature of every following sweep (kelvin, 1..5000). */
 smcx_status smcx_set_temperature(smcx_ctx* ctx, double T_kelvin);
 
@@ -294,7 +325,6 @@ smcx_status smcx_device_philox(const uint32_t* ctr, const uint32_t key[2], int32
  * u > 0, max_band the widest hi - lo.  Every output is nullable; synchronous. */
 smcx_status smcx_device_check_accept_bounds(double T_kelvin, uint64_t* violations_lo, uint64_t* violations_hi,
                                             double* max_log2_error, int32_t* max_band);
-
 
 #ifdef __cplusplus
 }

@@ -192,8 +192,8 @@ smcx_status recompute_energy(smcx_ctx* c, int64_t* E)
     smcx_status st = ctx_hip(c, hipMemsetAsync(c->d_counts, 0, sizeof(unsigned long long) * kMaxS * kMaxK * kMaxK,
                                                c->stream), "hipMemsetAsync");
     if (st) return st;
-    st = ctx_hip(c, launch_pair_counts(c->h_lat.lattice, c->h_lat.species, c->h_lat.L, c->K, c->S, c->d_counts,
-                                       c->stream), "pair_counts launch");
+    st = ctx_hip(c, launch_pair_counts(c->h_lat.lattice, c->d_own, c->h_lat.L, c->K, c->S, c->d_counts, c->stream),
+                 "pair_counts launch");
     if (st) return st;
     unsigned long long h[kMaxS * kMaxK * kMaxK];
     st = ctx_hip(c, hipMemcpyAsync(h, c->d_counts, sizeof(h), hipMemcpyDeviceToHost, c->stream), "hipMemcpyAsync");
@@ -243,7 +243,10 @@ static smcx_status ctx_init(smcx_ctx* c, const smcx_desc* d, const int32_t B[3],
     c->h_lat.drop_last = drop;
     c->h_lat.state = (int64_t*)c->d_state;
     c->h_lat.species = c->d_species;
+    if (!c->d_own) c->d_own = c->d_species;
     c->h_lat.sweep0 = 0;   // single lattice: launch step t is the sweep index
+    c->h_lat.slab = c->slab ? 1 : 0;
+    c->h_lat.z_off = c->z_off;
     c->T_default = T;
     st = upload_tables(c, &T, 1, 0);
     if (st) return st;
@@ -322,6 +325,51 @@ static smcx_status next_event_pair(smcx_ctx* c, hipEvent_t* e0, hipEvent_t* e1)
     return SMCX_OK;
 }
 
+// One colour phase of sweep s (with kernel timing when enabled).
+static smcx_status enqueue_phase(smcx_ctx* c, uint32_t s, int col, int groups)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->profiling) {
+        smcx_status st = next_event_pair(c, &e0, &e1);
+        if (!st) st = ctx_hip(c, hipEventRecord(e0, c->stream), "hipEventRecord");
+        if (st) return st;
+    }
+    hipError_t e = launch_sweep_phase(c->h_lat.lattice, c->d_lat, nullptr, groups, (int)s, col, c->kmax, c->smax,
+                                      c->stream, c->slab);
+    if (e != hipSuccess) return ctx_hip(c, e, "sweep_phase launch");
+    if (c->profiling) {
+        smcx_status st = ctx_hip(c, hipEventRecord(e1, c->stream), "hipEventRecord");
+        if (st) return st;
+        ++c->ev_used;
+    }
+    return SMCX_OK;
+}
+
+// A slab that is the whole z extent of its lattice exchanges halos with
+// itself: before a phase its halo planes receive its own wrapped planes;
+// after it, the ring plane the phase may have written in a halo goes back
+// to the plane it stands for.  Blocks with even z index (the lowest among
+// them) run when colour bit 2 is 0 and may write plane -1; blocks with odd
+// index (the highest) run otherwise and may write plane Lz.  The two never
+// run in one phase, so the plane written back was not changed in place.
+static smcx_status slab_self_halo(smcx_ctx* c, int col, bool after)
+{
+    const size_t P = 2 * (size_t)c->h_lat.L[0] * c->h_lat.L[1];   // bytes per plane
+    const size_t Lz = (size_t)c->h_lat.L[2];
+    uint8_t* b = c->d_species;                                     // plane p at b + p P
+    hipError_t e = hipSuccess;
+    if (!after) {
+        e = hipMemcpyAsync(b, b + Lz * P, 2 * P, hipMemcpyDeviceToDevice, c->stream);   // planes Lz-2, Lz-1
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b + (Lz + 2) * P, b + 2 * P, 2 * P, hipMemcpyDeviceToDevice, c->stream);   // 0, 1
+    } else if (((col >> 2) & 1) == 0) {
+        e = hipMemcpyAsync(b + (Lz + 1) * P, b + P, P, hipMemcpyDeviceToDevice, c->stream);   // plane -1 -> Lz-1
+    } else {
+        e = hipMemcpyAsync(b + 2 * P, b + (Lz + 2) * P, P, hipMemcpyDeviceToDevice, c->stream);   // plane Lz -> 0
+    }
+    return ctx_hip(c, e, "hipMemcpyAsync(halo)");
+}
+
 smcx_status enqueue_sweeps(smcx_ctx* c, int32_t n)
 {
     const int wpg = waves_per_group(c->h_lat.lattice);
@@ -329,24 +377,30 @@ smcx_status enqueue_sweeps(smcx_ctx* c, int32_t n)
     for (int32_t k = 0; k < n; ++k) {
         const uint32_t s = (uint32_t)(c->sweeps + (uint64_t)k);
         for (int col = 0; col < 8; ++col) {
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (c->profiling) {
-                smcx_status st = next_event_pair(c, &e0, &e1);
-                if (!st) st = ctx_hip(c, hipEventRecord(e0, c->stream), "hipEventRecord");
-                if (st) return st;
-            }
-            hipError_t e = launch_sweep_phase(c->h_lat.lattice, c->d_lat, nullptr, groups, (int)s, col, c->kmax, c->smax,
-                                              c->stream);
-            if (e != hipSuccess) return ctx_hip(c, e, "sweep_phase launch");
-            if (c->profiling) {
-                smcx_status st = ctx_hip(c, hipEventRecord(e1, c->stream), "hipEventRecord");
-                if (st) return st;
-                ++c->ev_used;
-            }
+            smcx_status st = c->slab ? slab_self_halo(c, col, false) : SMCX_OK;
+            if (!st) st = enqueue_phase(c, s, col, groups);
+            if (!st && c->slab) st = slab_self_halo(c, col, true);
+            if (st) return st;
         }
     }
     c->sweeps += (uint64_t)n;
     c->attempted += (uint64_t)n * c->N;
+    return SMCX_OK;
+}
+
+smcx_status enqueue_phases(smcx_ctx* c, int32_t n)
+{
+    const int wpg = waves_per_group(c->h_lat.lattice);
+    const int groups = (c->h_lat.blocks_per_colour + wpg - 1) / wpg;
+    for (int32_t k = 0; k < n; ++k) {
+        smcx_status st = enqueue_phase(c, (uint32_t)c->sweeps, c->phase, groups);
+        if (st) return st;
+        if (++c->phase == 8) {
+            c->phase = 0;
+            c->sweeps += 1;
+            c->attempted += c->N;
+        }
+    }
     return SMCX_OK;
 }
 
@@ -374,7 +428,8 @@ const char* smcx_status_string(smcx_status s)
 }
 
 static smcx_status create_common(const smcx_desc* desc, const uint8_t* species, uint8_t* d_species,
-                                 const int32_t* epi, double T, void* stream, smcx_ctx** out)
+                                 const int32_t* epi, double T, void* stream, smcx_ctx** out, bool slab = false,
+                                 uint32_t z_off = 0)
 {
     if (!out) return fail_global(SMCX_E_INVALID, "out is NULL");
     *out = nullptr;
@@ -395,6 +450,11 @@ static smcx_status create_common(const smcx_desc* desc, const uint8_t* species, 
     }
     smcx_ctx* c = new (std::nothrow) smcx_ctx();
     if (!c) return fail_global(SMCX_E_NOMEM, "host allocation failed");
+    c->slab = slab;
+    c->z_off = z_off;
+    // a slab's buffer: 2 halo planes, the slab, 2 halo planes
+    const size_t n_buf = slab ? N + 4 * 2 * (size_t)desc->L[0] * desc->L[1] : N;
+    if (slab) c->d_own = d_species + 2 * 2 * (size_t)desc->L[0] * desc->L[1];
     if (stream || d_species) {
         c->stream = (hipStream_t)stream;
         c->owns_stream = false;
@@ -418,7 +478,7 @@ static smcx_status create_common(const smcx_desc* desc, const uint8_t* species, 
         unsigned int mx = 0;
         st = ctx_hip(c, hipMalloc(&d_max, sizeof(unsigned int)), "hipMalloc");
         if (!st) st = ctx_hip(c, hipMemsetAsync(d_max, 0, sizeof(unsigned int), c->stream), "hipMemsetAsync");
-        if (!st) st = ctx_hip(c, launch_species_max(d_species, N, d_max, c->stream), "species_max launch");
+        if (!st) st = ctx_hip(c, launch_species_max(d_species, n_buf, d_max, c->stream), "species_max launch");
         if (!st) st = ctx_hip(c, hipMemcpyAsync(&mx, d_max, sizeof(mx), hipMemcpyDeviceToHost, c->stream), "copy");
         if (!st) st = ctx_hip(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
         if (d_max) (void)hipFree(d_max);
@@ -457,6 +517,27 @@ smcx_status smcx_create_device(const smcx_desc* desc, uint8_t* d_species, const 
     return create_common(desc, nullptr, d_species, epi_ueV, T_kelvin, hip_stream, out);
 }
 
+smcx_status smcx_create_slab(const smcx_desc* desc, uint8_t* d_buffer, uint32_t z_offset, const int32_t* epi_ueV,
+                             double T_kelvin, void* hip_stream, smcx_ctx** out)
+{
+    if (out) *out = nullptr;
+    if (!desc) return fail_global(SMCX_E_INVALID, "desc is NULL");
+    if (desc->lattice != SMCX_LATTICE_BCC) return fail_global(SMCX_E_UNSUPPORTED, "slabs are BCC only");
+    if (!d_buffer || ((uintptr_t)d_buffer & 3u))
+        return fail_global(SMCX_E_INVALID, "d_buffer is NULL or not 4-byte aligned");
+    return create_common(desc, nullptr, d_buffer, epi_ueV, T_kelvin, hip_stream, out, true, z_offset);
+}
+
+smcx_status smcx_slab_phase(smcx_ctx* c, int32_t n)
+{
+    if (!c) return fail_global(SMCX_E_INVALID, "ctx is NULL");
+    if (!c->slab) return fail(c, SMCX_E_STATE, "smcx_slab_phase needs a slab context");
+    if (n < 0) return fail(c, SMCX_E_INVALID, "n = %d < 0", n);
+    if (c->sweeps + (uint64_t)((c->phase + n + 7) / 8) > 0xffffffffull)
+        return fail(c, SMCX_E_RANGE, "sweep counter would pass 2^32");
+    return enqueue_phases(c, n);
+}
+
 smcx_status smcx_set_temperature(smcx_ctx* c, double T)
 {
     if (!c) return fail_global(SMCX_E_INVALID, "ctx is NULL");
@@ -493,6 +574,7 @@ smcx_status smcx_sweep(smcx_ctx* c, int32_t n)
     if (c->view) return fail(c, SMCX_E_STATE, "batch views are advanced by smcx_batch_run");
     if (n < 0) return fail(c, SMCX_E_INVALID, "n = %d < 0", n);
     if (c->sweeps + (uint64_t)n > 0xffffffffull) return fail(c, SMCX_E_RANGE, "sweep counter would pass 2^32");
+    if (c->phase != 0) return fail(c, SMCX_E_STATE, "a sweep stepped by smcx_slab_phase is unfinished");
     return enqueue_sweeps(c, n);
 }
 
@@ -538,7 +620,7 @@ smcx_status smcx_get_config(smcx_ctx* c, uint8_t* out, size_t n)
 {
     if (!c || !out) return fail(c, SMCX_E_INVALID, "NULL argument");
     if (n < c->N) return fail(c, SMCX_E_INVALID, "buffer of %zu bytes < N = %zu", n, c->N);
-    smcx_status st = ctx_hip(c, hipMemcpyAsync(out, c->h_lat.species, c->N, hipMemcpyDeviceToHost, c->stream),
+    smcx_status st = ctx_hip(c, hipMemcpyAsync(out, c->d_own, c->N, hipMemcpyDeviceToHost, c->stream),
                              "hipMemcpyAsync");
     if (!st) st = ctx_hip(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
     return st;
@@ -566,9 +648,10 @@ smcx_status smcx_set_state(smcx_ctx* c, const uint8_t* species, uint64_t sweep_i
     for (size_t i = 0; i < c->N; ++i)
         if (species[i] >= c->K) return fail(c, SMCX_E_INVALID, "species[%zu] = %d >= K", i, species[i]);
     smcx_status st = ctx_hip(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
-    if (!st) st = ctx_hip(c, hipMemcpy(c->h_lat.species, species, c->N, hipMemcpyHostToDevice), "hipMemcpy");
+    if (!st) st = ctx_hip(c, hipMemcpy(c->d_own, species, c->N, hipMemcpyHostToDevice), "hipMemcpy");
     if (st) return st;
     c->sweeps = sweep_index;
+    c->phase = 0;
     c->attempted = 0;
     int64_t E = 0;
     st = recompute_energy(c, &E);

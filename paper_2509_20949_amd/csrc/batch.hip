@@ -177,6 +177,7 @@ smcx_status smcx_batch_create(int32_t n, const smcx_desc* descs, const uint8_t* 
         v->smax = smax;
         v->epi.assign(epi[r], epi[r] + (size_t)d.n_shells * d.n_species * d.n_species);
         v->d_species = L.species;
+        v->d_own = L.species;
         v->stream = b->stream;
         v->h_lat = L;
         v->d_lat = b->d_lats + r;

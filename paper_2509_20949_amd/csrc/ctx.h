@@ -38,6 +38,12 @@ struct smcx_ctx {
     double ev_total_ms = 0.0;                // harvested kernel time since profiling was enabled
     uint64_t ev_launches = 0;
     bool view = false;                       // replica view owned by a batch
+    // z-slab (smcx_create_slab): the caller's buffer holds 2 halo planes, the
+    // slab's Lz planes and 2 more halo planes; d_own = its first own plane
+    bool slab = false;
+    uint32_t z_off = 0;                      // global z of the slab's first own plane
+    uint8_t* d_own = nullptr;                // the lattice's own sites (= d_species unless a slab)
+    int phase = 0;                           // colour phases of the current sweep already enqueued
     std::string err;
 };
 
@@ -55,5 +61,7 @@ smcx_status recompute_energy(smcx_ctx* c, int64_t* E);
 // Running energy / accepted count of a context (sums over the state slots).
 smcx_status read_state(smcx_ctx* c, int64_t* E, uint64_t* accepted);
 smcx_status write_state(smcx_ctx* c, int64_t E, uint64_t accepted);
+smcx_status enqueue_sweeps(smcx_ctx* c, int32_t n);
+smcx_status enqueue_phases(smcx_ctx* c, int32_t n);
 void ctx_release(smcx_ctx* c);
 }  // namespace smcx

@@ -218,7 +218,9 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int yz, 
 }
 
 // ---------------------------------------------------------------------------
-template <int KMAX, int SMAX>
+// SLAB: the lattice is a z-slab (DevLattice::slab) -- its own instance, so
+// the periodic kernel carries none of the slab's addressing.
+template <int KMAX, int SMAX, bool SLAB>
 __global__ __launch_bounds__(kWave * kWavesPerGroup) __attribute__((amdgpu_waves_per_eu(kSweepWavesPerSimd)))
 void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __restrict__ items, int n_groups,
                         int t, int colour)
@@ -265,7 +267,9 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
     philox4x32_10(sh, D.key[0], D.key[1]);
     const int ox = (int)(((uint64_t)sh[0] * (uint32_t)Lx) >> 32);
     const int oy = (int)(((uint64_t)sh[1] * (uint32_t)Ly) >> 32);
-    const int oz = (int)(((uint64_t)sh[2] * (uint32_t)Lz) >> 32);
+    // a z-slab keeps its blocks aligned to its boundaries: no z shift
+    constexpr bool slab = SLAB;
+    const int oz = slab ? 0 : (int)(((uint64_t)sh[2] * (uint32_t)Lz) >> 32);
 
     const int x0 = block_lo(kx, Lx, D.nb[0]), wx = block_lo(kx + 1, Lx, D.nb[0]) - x0;
     const int y0 = block_lo(ky, Ly, D.nb[1]), wy = block_lo(ky + 1, Ly, D.nb[1]) - y0;
@@ -275,10 +279,16 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
 
     uint8_t* lat = s_lat + wave * kWaveLds;
     uint8_t* __restrict__ g = D.species;
+    // plane of the lattice array that holds local z plane lz of the block:
+    // periodic wrap, or on a slab the plane two further on (the array starts
+    // with the two halo planes below the slab)
+    auto zplane = [&](int lz) -> int { return slab ? gz0 + lz + 2 : wrap_add(gz0 + lz, Lz); };
 
-    // cell ids fit 32 bits and the 24-bit multiplier (the usual case)
+    // cell ids (and, on a slab, global cell ids) fit 32 bits and the 24-bit
+    // multiplier (the usual case)
     const uint32_t LxLy = (uint32_t)Lx * (uint32_t)Ly;
-    const bool narrow = LxLy < (1u << 24) && (uint64_t)LxLy * (uint32_t)Lz < (1ull << 32);
+    const uint64_t zspan = slab ? (uint64_t)Lz + 4 + D.z_off : (uint64_t)Lz;
+    const bool narrow = LxLy < (1u << 24) && (uint64_t)LxLy * zspan < (1ull << 32);
 
     // species bytes -> LDS codes for this lattice's form of the weight rows
     const bool dot_codes = KMAX <= 5 && D.drop_last == kWtabDot;
@@ -317,7 +327,7 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
             for (int u = 0; u < kStageBatch; ++u) {
                 const int it = it0 + u;
                 const int lz = min((it >> 1) - 2, wz + 1);
-                const uint32_t gz = (uint32_t)wrap_add(gz0 + lz, Lz), gy = gyrow[it & 1];
+                const uint32_t gz = (uint32_t)zplane(lz), gy = gyrow[it & 1];
                 const size_t row = narrow ? (size_t)(__umul24(gz, LxLy) + __umul24(gy, (uint32_t)Lx))
                                           : ((size_t)gz * (uint32_t)Ly + gy) * (uint32_t)Lx;
                 const size_t at = 2 * (row + (size_t)(gx0 + lxa));     // byte of corner(lxa)
@@ -355,8 +365,8 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
             for (int u = 0; u < 2 * kStageBatch; ++u) {
                 const int it = it0 + u;
                 const int ly = min((lane >> 4) + 4 * (it & 3) - 2, wy + 1), lz = min((it >> 2) - 2, wz + 1);
-                const int gy = wrap_add(gy0 + ly, Ly), gz = wrap_add(gz0 + lz, Lz);
-                const size_t cell = ((size_t)gz * Ly + gy) * Lx + gx;
+                const int gy = wrap_add(gy0 + ly, Ly);
+                const size_t cell = ((size_t)zplane(lz) * Ly + gy) * Lx + gx;
                 v2[u] = gload<uint16_t>(g + 2 * cell);
             }
 #pragma unroll
@@ -394,7 +404,7 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
         uint32_t bx = (uint32_t)(gx0 + 3 * ix), by = (uint32_t)(gy0 + 3 * iy), bz = (uint32_t)(gz0 + 3 * iz);
         bx = min(bx, bx - (uint32_t)Lx);
         by = min(by, by - (uint32_t)Ly);
-        bz = min(bz, bz - (uint32_t)Lz);
+        bz = slab ? bz + D.z_off : min(bz, bz - (uint32_t)Lz);   // a slab's cells are numbered globally
         const uint64_t cell = narrow ? (uint64_t)(__umul24(bz, LxLy) + __umul24(by, (uint32_t)Lx) + bx)
                                      : ((uint64_t)bz * (uint32_t)Ly + by) * (uint32_t)Lx + bx;
         base_lo = (uint32_t)cell;
@@ -506,7 +516,7 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
             for (int u = 0; u < 4; ++u) {
                 const int h = u & 1, lz = ((it0 + u) >> 1) - 1, lzc = min(lz, wz);
                 const uint32_t zm = (lz >= 0 && lz <= wz ? 5u : 0u) | (lz < wz ? 10u : 0u);
-                const uint64_t zrow = (uint64_t)(uint32_t)wrap_add(gz0 + lzc, Lz) * ((uint64_t)Lx * (uint32_t)Ly);
+                const uint64_t zrow = (uint64_t)(uint32_t)zplane(lzc) * ((uint64_t)Lx * (uint32_t)Ly);
                 const uint32_t pp = ypar[h] ^ ((uint32_t)zrow & 1u);
                 msk[u] = (xm2 >> (4 * pp)) & ym[h] & zm;
                 const int crow = (lzc + 1) * kPP + ylds[h] + cx0 + (int)(pp & (uint32_t)cxp);
@@ -559,8 +569,8 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
                 const bool corner = lx >= 0 && ly >= 0 && lz >= 0;
                 const bool body = lx < wx && ly < wy && lz < wz;
                 if (!corner && !body) continue;
-                const int gy = wrap_add(gy0 + ly, Ly), gz = wrap_add(gz0 + lz, Lz);
-                const size_t cell = ((size_t)gz * Ly + gy) * Lx + gx;
+                const int gy = wrap_add(gy0 + ly, Ly);
+                const size_t cell = ((size_t)zplane(lz) * Ly + gy) * Lx + gx;
                 if (corner && body)
                     gstore<uint16_t>(g + 2 * cell, (uint16_t)(decode(vc[u]) | decode(vb[u]) << 8));
                 else if (corner)
@@ -597,41 +607,50 @@ int kmax_for(int K)
     return 8;
 }
 
-template <int KMAX, int SMAX>
+template <int KMAX, int SMAX, bool SLAB>
 static hipError_t launch_t(const DevLattice* d_lat, const WorkItem* d_items, int n_groups, int t,
                            int colour, hipStream_t stream)
 {
-    hipLaunchKernelGGL((sweep_phase_kernel<KMAX, SMAX>), dim3(xcd_grid(n_groups)), dim3(kWave * kWavesPerGroup), 0,
-                       stream, d_lat, d_items, n_groups, t, colour);
+    hipLaunchKernelGGL((sweep_phase_kernel<KMAX, SMAX, SLAB>), dim3(xcd_grid(n_groups)),
+                       dim3(kWave * kWavesPerGroup), 0, stream, d_lat, d_items, n_groups, t, colour);
     return hipGetLastError();
 }
 
-template <int KMAX>
+template <int KMAX, bool SLAB>
 static hipError_t launch_k(const DevLattice* d_lat, const WorkItem* d_items, int n_groups, int t,
                            int colour, int smax, hipStream_t stream)
 {
     switch (smax) {
-    case 1: return launch_t<KMAX, 1>(d_lat, d_items, n_groups, t, colour, stream);
-    case 2: return launch_t<KMAX, 2>(d_lat, d_items, n_groups, t, colour, stream);
-    case 3: return launch_t<KMAX, 3>(d_lat, d_items, n_groups, t, colour, stream);
+    case 1: return launch_t<KMAX, 1, SLAB>(d_lat, d_items, n_groups, t, colour, stream);
+    case 2: return launch_t<KMAX, 2, SLAB>(d_lat, d_items, n_groups, t, colour, stream);
+    case 3: return launch_t<KMAX, 3, SLAB>(d_lat, d_items, n_groups, t, colour, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <bool SLAB>
+static hipError_t launch_bcc(const DevLattice* d_lat, const WorkItem* d_items, int n_groups, int t, int colour,
+                             int kmax, int smax, hipStream_t stream)
+{
+    switch (kmax) {
+    case 2: return launch_k<2, SLAB>(d_lat, d_items, n_groups, t, colour, smax, stream);
+    case 3: return launch_k<3, SLAB>(d_lat, d_items, n_groups, t, colour, smax, stream);
+    case 4: return launch_k<4, SLAB>(d_lat, d_items, n_groups, t, colour, smax, stream);
+    case 5: return launch_k<5, SLAB>(d_lat, d_items, n_groups, t, colour, smax, stream);
+    case 6: return launch_k<6, SLAB>(d_lat, d_items, n_groups, t, colour, smax, stream);
+    case 8: return launch_k<8, SLAB>(d_lat, d_items, n_groups, t, colour, smax, stream);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_sweep_phase(int lattice, const DevLattice* d_lat, const WorkItem* d_items, int n_groups, int t,
-                              int colour, int kmax, int smax, hipStream_t stream)
+                              int colour, int kmax, int smax, hipStream_t stream, bool slab)
 {
     if (n_groups <= 0) return hipSuccess;
-    if (lattice == 1) return launch_sweep_phase_fcc(d_lat, d_items, n_groups, t, colour, smax, stream);
-    switch (kmax) {
-    case 2: return launch_k<2>(d_lat, d_items, n_groups, t, colour, smax, stream);
-    case 3: return launch_k<3>(d_lat, d_items, n_groups, t, colour, smax, stream);
-    case 4: return launch_k<4>(d_lat, d_items, n_groups, t, colour, smax, stream);
-    case 5: return launch_k<5>(d_lat, d_items, n_groups, t, colour, smax, stream);
-    case 6: return launch_k<6>(d_lat, d_items, n_groups, t, colour, smax, stream);
-    case 8: return launch_k<8>(d_lat, d_items, n_groups, t, colour, smax, stream);
-    }
-    return hipErrorInvalidValue;
+    if (lattice == 1) return slab ? hipErrorInvalidValue
+                                  : launch_sweep_phase_fcc(d_lat, d_items, n_groups, t, colour, smax, stream);
+    return slab ? launch_bcc<true>(d_lat, d_items, n_groups, t, colour, kmax, smax, stream)
+                : launch_bcc<false>(d_lat, d_items, n_groups, t, colour, kmax, smax, stream);
 }
 
 __global__ void species_max_kernel(const uint8_t* __restrict__ g, size_t n, unsigned int* __restrict__ out)

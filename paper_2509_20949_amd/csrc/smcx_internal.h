@@ -66,7 +66,7 @@ void state_sum(const int64_t* h /* kStateWords */, int64_t* E, uint64_t* accepte
 
 // Per-lattice state the kernels read (device memory).
 struct DevLattice {
-    uint8_t* species;        // 2*Lx*Ly*Lz bytes, canonical order
+    uint8_t* species;        // 2*Lx*Ly*Lz bytes, canonical order (slab: 2*Lx*Ly*(Lz+4), see below)
     const double* tabs;      // n_tabs x 768 thresholds
     const int32_t* wtab;     // KMAX*KMAX rows of wrow(KMAX, SMAX) ints
     int64_t* state;          // running energy and accepted count, kStateWords words (see below)
@@ -80,6 +80,9 @@ struct DevLattice {
     int32_t blocks_per_colour;
     int32_t lattice;         // 0 BCC, 1 FCC
     int32_t drop_last;       // form of the weight rows: kWtabFull, kWtabDrop or kWtabDot
+    int32_t slab;            // 1: z-slab of a larger lattice (BCC); species points at 2 halo planes below it,
+                             // 2 more follow it, z is not shifted and not wrapped
+    uint32_t z_off;          // slab: global z of the slab's first plane (random-number cell ids)
 };
 
 // One workgroup's share of a batched phase: kWavesPerGroup consecutive
@@ -141,8 +144,9 @@ void build_thresholds(double T, double* out /* kTab */);
 int build_wtab(const int32_t* epi, int K, int S, int kmax, int smax, int bias, bool dot_ok, int32_t* out);
 
 // Launchers (kernels.hip, kernels_fcc.hip, pair_counts.hip).  Return hipSuccess or the launch error.
+// slab: d_lat describes a z-slab (BCC only; one lattice, no work items).
 hipError_t launch_sweep_phase(int lattice, const DevLattice* d_lat, const WorkItem* d_items, int n_groups,
-                              int t, int colour, int kmax, int smax, hipStream_t stream);
+                              int t, int colour, int kmax, int smax, hipStream_t stream, bool slab = false);
 hipError_t launch_pair_counts(int lattice, const uint8_t* species, const int32_t L[3], int K, int S,
                               unsigned long long* d_counts, hipStream_t stream);
 hipError_t launch_sweep_phase_fcc(const DevLattice* d_lat, const WorkItem* d_items, int n_groups, int t,

@@ -56,6 +56,8 @@ def lib():
     pd = _P(smcx_desc)
     _sig(L, "smcx_create", st, [pd, _P(C.c_uint8), _P(i32), dbl, _P(vp)])
     _sig(L, "smcx_create_device", st, [pd, vp, _P(i32), dbl, vp, _P(vp)])
+    _sig(L, "smcx_create_slab", st, [pd, vp, C.c_uint32, _P(i32), dbl, vp, _P(vp)])
+    _sig(L, "smcx_slab_phase", st, [vp, i32])
     _sig(L, "smcx_set_temperature", st, [vp, dbl])
     _sig(L, "smcx_set_schedule", st, [vp, _P(dbl), i32])
     _sig(L, "smcx_sweep", st, [vp, i32])
@@ -154,6 +156,19 @@ def smcx_sweep_noalloc(desc: smcx_desc, d_species_ptr: int, epi_ueV, T_kelvin: f
                                     int(sweep0), int(n), C.c_void_p(hip_stream or None), C.byref(dE),
                                     C.byref(acc)))
     return dE.value, acc.value
+
+
+def smcx_create_slab(desc: smcx_desc, d_buffer_ptr: int, z_offset: int, epi_ueV, T_kelvin: float,
+                     hip_stream: int = 0):
+    e = np.ascontiguousarray(epi_ueV, dtype=np.int32)
+    out = C.c_void_p()
+    _check(lib().smcx_create_slab(C.byref(desc), C.c_void_p(d_buffer_ptr), int(z_offset), _ptr(e, C.c_int32),
+                                  float(T_kelvin), C.c_void_p(hip_stream or None), C.byref(out)))
+    return out.value
+
+
+def smcx_slab_phase(ctx, n: int):
+    _check(lib().smcx_slab_phase(ctx, int(n)), ctx)
 
 
 def smcx_set_temperature(ctx, T_kelvin: float):
