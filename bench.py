@@ -13,8 +13,10 @@ Prints one JSON line (the driver's contract) with, besides throughput:
   alu_roofline  the same kernel against the integer-VALU peak (the bound
                 that actually limits it);
   pair_counts   the energy-recompute / SRO pass (H9) on the same lattice;
-  cpu_baseline  the CPU oracle timed on this host on one full sweep of the
-                same lattice (bounded sample), with the threads it used;
+  cpu_baseline  the CPU oracle timed on this host, single-threaded, on a
+                bounded sample (5 sweeps of a 128^3 lattice of the same
+                recipe), with the threaded oracle on one sweep of the
+                benchmark lattice beside it as context;
   check         running energy vs a full recompute after the timed sweeps.
 """
 from __future__ import annotations
@@ -95,9 +97,12 @@ def parse():
     ap.add_argument("--unbatched-sweeps", type=int, default=20,
                     help="sweeps of the per-instance comparison (one launch per replica and phase)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
-    ap.add_argument("--serve-window", type=float, default=10.0, help="seconds of Poisson arrivals")
+    ap.add_argument("--serve-window", type=float, default=60.0, help="seconds of Poisson arrivals")
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--serve-step", type=int, default=10, help="sweeps per server step")
+    ap.add_argument("--tune-blocks", action="store_true",
+                    help="only measure batched throughput over replica edges 16..96 and block widths "
+                         "(the measurements behind the library's block-width plan)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (5 times) to calibrate HBM byte counters")
     return ap.parse_args()
@@ -116,6 +121,34 @@ def copy_calibration():
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}), flush=True)
+
+
+def tune_blocks(smcx, W):
+    """Batched throughput of replicas of edge L (16..96, the batched
+    workload's range) for every block-width parameter B = 4..12: enough
+    replicas of one shape that the colour launches fill the chip, 10 sweeps
+    in one graph launch after a warm run.  One JSON line per (L, B)."""
+    rng = np.random.default_rng(W.BASE_SEED + 77)
+    epi = W.epi_table(3, 5, 30.0, rng)
+    for L in range(16, 97, 4):
+        N = W.n_sites((L, L, L))
+        R = max(2, -(-16_000_000 // N))
+        sigmas = [rng.integers(0, 5, N).astype(np.uint8) for _ in range(min(R, 8))]
+        for B in range(4, 13):
+            descs = [smcx.make_desc((L, L, L), 5, 3, (B, B, B), 1000 + r) for r in range(R)]
+            b = smcx.smcx_batch_create(descs, [sigmas[r % len(sigmas)] for r in range(R)], [epi] * R, [1000.0] * R)
+            try:
+                smcx.smcx_batch_run(b, [2] * R)
+                smcx.smcx_batch_synchronize(b)
+                t0 = time.perf_counter()
+                smcx.smcx_batch_run(b, [10] * R)
+                smcx.smcx_batch_synchronize(b)
+                dt = time.perf_counter() - t0
+            finally:
+                smcx.smcx_batch_destroy(b)
+            blocks = [int(v) for v in np.asarray(smcx.smcx_plan(descs[0])[1])]
+            print(json.dumps({"L": L, "B": B, "replicas": R, "blocks_per_axis": blocks,
+                              "swaps_per_s": R * N * 10 / dt}), flush=True)
 
 
 def slab_leg(args, smcx, W, sweeps=50):
@@ -235,16 +268,19 @@ def batched_leg(args, smcx, W):
             "identical_trajectories": same, "energy_checks_ok": ok}
 
 
-def serve_leg(args, smcx, W):
+def serve_leg(args, smcx, W, batched_rate=None):
     """Poisson request stream through the continuous-batching server:
     requests are submitted at their arrival times, the server steps while
-    anything is resident or waiting, latency = completion - arrival."""
+    anything is resident or waiting, latency = completion - arrival.  Each
+    request's configuration has its own Dirichlet(5) composition: its sites
+    are i.i.d. draws of that composition, made by mapping a window of one
+    pool of uniform random bytes through the request's 256-entry table
+    (generating and shuffling every request's sites on the host would not
+    keep up with the arrival rate)."""
     reqs = W.config5(rate_hz=args.serve_rate, window_s=args.serve_window, materialize=False)
-    # configuration bytes: windows of one random pool (the input content does
-    # not affect the work of a sweep), species relabelled per request
     rng = np.random.default_rng(W.BASE_SEED + 55)
     max_n = max(r.job.N for r in reqs)
-    pool = rng.choice(5, size=max_n * 2, p=rng.dirichlet(np.full(5, 5.0))).astype(np.uint8)
+    pool = rng.integers(0, 256, size=max_n + (1 << 20), dtype=np.uint8)
     offered = sum(r.job.N * r.job.n_sweeps for r in reqs) / args.serve_window
     srv = smcx.smcx_server_create(200 << 30, 512, args.serve_step)
     lat, done_work = [], 0
@@ -257,9 +293,10 @@ def serve_leg(args, smcx, W):
             now = time.perf_counter() - t0
             while nxt < len(reqs) and reqs[nxt].arrival_s <= now:
                 j = reqs[nxt].job
-                off = int(rng.integers(0, max_n))
-                perm = rng.permutation(5).astype(np.uint8)
-                sigma = perm[pool[off:off + j.N]]
+                cum = np.cumsum(rng.dirichlet(np.full(5, 5.0))) * 256.0
+                lut = np.minimum(np.searchsorted(cum, np.arange(256) + 0.5), 4).astype(np.uint8)
+                off = int(rng.integers(0, pool.size - j.N))
+                sigma = lut[pool[off:off + j.N]]
                 d = smcx.make_desc(j.L, j.K, j.S, (0, 0, 0), j.seed)
                 ids[nxt] = smcx.smcx_server_submit(srv, d, sigma, j.epi, float(j.T[0]), j.n_sweeps)
                 pending.add(nxt)
@@ -282,15 +319,37 @@ def serve_leg(args, smcx, W):
     finally:
         smcx.smcx_server_destroy(srv)
     lat = np.array(lat)
-    return {"requests": len(reqs), "completed": int(lat.size), "rate_hz": args.serve_rate,
-            "window_s": args.serve_window, "sweeps_per_step": args.serve_step,
-            "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-            "value": done_work / t_end, "unit": "swaps/s", "wall_s": t_end,
-            "offered_swaps_per_s": offered}
+    out = {"requests": len(reqs), "completed": int(lat.size), "rate_hz": args.serve_rate,
+           "window_s": args.serve_window, "sweeps_per_step": args.serve_step,
+           "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+           "value": done_work / t_end, "unit": "swaps/s", "wall_s": t_end,
+           "offered_swaps_per_s": offered}
+    if batched_rate:
+        out["vs_batched"] = out["value"] / batched_rate
+    return out
 
 
-def cpu_baseline(job, n_threads):
-    """The oracle as it stands on one full sweep of the benchmark lattice."""
+def cpu_baseline(W, n_sweeps=5, L=128):
+    """The oracle as it stands, single-threaded, on a bounded sample of the
+    benchmark workload: n_sweeps sweeps of an L^3 lattice drawn with the
+    benchmark's recipe (K = 5 Dirichlet(5), 3-shell EPI of 30 meV, 800 K,
+    B = 12)."""
+    from oracle import oracle
+    job = W.config3(n_sweeps=1, L=L)
+    oracle.set_threads(1)
+    st = oracle.OracleState(job.L, (12, 12, 12), job.epi, job.sigma, job.seed)
+    t0 = time.perf_counter()
+    st.sweep(float(job.T[0]), n_sweeps)
+    dt = time.perf_counter() - t0
+    return {"value": job.N * n_sweeps / dt, "unit": "swaps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_sweeps} sweeps of a {L}^3 lattice of the benchmark recipe ({job.N} sites), "
+                      f"1 thread, {dt:.1f} s"}
+
+
+def cpu_threads_context(job, n_threads):
+    """Context beside cpu_baseline: the oracle's threaded form (sets of one
+    colour and sub-colour on several threads, identical results) on one
+    sweep of the benchmark lattice itself."""
     from oracle import oracle
     oracle.set_threads(n_threads)
     st = oracle.OracleState(job.L, (12, 12, 12), job.epi, job.sigma, job.seed)
@@ -298,7 +357,7 @@ def cpu_baseline(job, n_threads):
     st.sweep(float(job.T[0]), 1)
     dt = time.perf_counter() - t0
     oracle.set_threads(1)
-    return {"value": job.N / dt, "unit": "swaps/s", "cores": n_threads, "kind": "oracle",
+    return {"value": job.N / dt, "unit": "swaps/s", "cores": n_threads,
             "sample": f"1 sweep of the {job.L[0]}^3 lattice ({job.N} trials), {dt:.1f} s"}
 
 
@@ -320,6 +379,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.tune_blocks:
+        tune_blocks(smcx, W)
         return
     t_gen = time.perf_counter()
     progress(f"generating the {args.L}^3 lattice")
@@ -413,11 +475,13 @@ def main():
         out["batched"] = batched_leg(args, smcx, W)
     if not args.no_serve:
         progress(f"serving leg: {args.serve_rate} req/s for {args.serve_window} s")
-        out["serving"] = serve_leg(args, smcx, W)
+        out["serving"] = serve_leg(args, smcx, W, out.get("batched", {}).get("value"))
     if not args.no_cpu_baseline:
+        progress("timing the oracle: 5 sweeps of a 128^3 lattice, 1 thread")
+        out["cpu_baseline"] = cpu_baseline(W)
         n = args.cpu_threads or min(os.cpu_count() or 1, 16)
-        progress(f"timing the oracle on one sweep with {n} threads")
-        out["cpu_baseline"] = cpu_baseline(job, n)
+        progress(f"timing the threaded oracle on one sweep of the benchmark lattice with {n} threads")
+        out["cpu_threads_context"] = cpu_threads_context(job, n)
     print(json.dumps(out), flush=True)
 
 

@@ -108,8 +108,8 @@ typedef struct {
     int32_t n_species;  /* K, 2..8 */
     int32_t n_shells;   /* S, 1..3 */
     int32_t block[3];   /* schedule block-width parameter B per axis, 2..12;
-                           0 lets the library choose (12, the wavefront-sized
-                           block).  B changes the schedule, hence the
+                           0 lets the library choose (smcx_plan reports the
+                           choice).  B changes the schedule, hence the
                            trajectory; the oracle must use the same B. */
     uint64_t seed;      /* Philox key */
 } smcx_desc;
@@ -129,6 +129,15 @@ smcx_status smcx_create(const smcx_desc* desc, const uint8_t* species, const int
  * validated on the device. */
 smcx_status smcx_create_device(const smcx_desc* desc, uint8_t* d_species, const int32_t* epi_ueV,
                                double T_kelvin, void* hip_stream, smcx_ctx** out);
+
+/* smcx_plan: the schedule the library runs for desc, computed on the host
+ * (no device): block receives the block-width parameter B per axis (the
+ * desc's, or the library's choice where the desc gives 0: a fixed function
+ * of the lattice type, the axis length and K, so a trajectory is
+ * reproducible), blocks the number of blocks per axis of the shifted grid,
+ * n = max(2, min(2*ceil(L/(2B)), 2*floor(L/4))).  Both nullable.  Errors as
+ * smcx_create's checks of desc. */
+smcx_status smcx_plan(const smcx_desc* desc, int32_t block[3], int32_t blocks[3]);
 
 /* ---- one z-slab of a larger lattice (lattice parallelism with ghost
  * layers, Section "Distributed SMC-X") --------------------------------------
@@ -238,6 +247,15 @@ smcx_status smcx_batch_set_temperature(smcx_batch* batch, int32_t r, double T_ke
  * share L and K.  accepted[k] (nullable) receives the decisions. */
 smcx_status smcx_batch_exchange(smcx_batch* batch, const int32_t* a, const int32_t* b, int32_t n_pairs,
                                 uint64_t seed, uint64_t round, int32_t* accepted);
+/* Temperature ladder for replica exchange sized to the system (equation for
+ * Delta T: the spacing of neighbouring temperatures scales as
+ * 1/sqrt(N_atom), so that neighbouring energy distributions keep
+ * overlapping as the system grows).  out[k] = T0 + k dT, k < n, with
+ * dT = dT_ref sqrt(n_ref / n_atoms); dT_ref <= 0 or n_ref = 0 take the
+ * paper's example, 0.1 K at 10^9 atoms.  Host only.  RANGE if a
+ * temperature leaves [1, 5000] K. */
+smcx_status smcx_temperature_ladder(double T0, int32_t n, uint64_t n_atoms, double dT_ref, uint64_t n_ref,
+                                    double* out);
 smcx_status smcx_batch_synchronize(smcx_batch* batch);
 void smcx_batch_destroy(smcx_batch* batch);
 

@@ -53,7 +53,7 @@ smcx_status validate_desc(const smcx_desc* d, int32_t block_out[3], bool for_gpu
         if (for_gpu && d->L[a] < 4)
             return fail_global(SMCX_E_UNSUPPORTED, "L[%d] = %d: the GPU schedule needs >= 4 cells", a, d->L[a]);
         if (d->L[a] > (1 << 28)) return fail_global(SMCX_E_UNSUPPORTED, "L[%d] = %d too large", a, d->L[a]);
-        int B = d->block[a] == 0 ? kMaxBlock : d->block[a];
+        int B = d->block[a] == 0 ? plan_block(d->lattice, d->L[a], d->n_species) : d->block[a];
         if (B < 2) return fail_global(SMCX_E_INVALID, "block[%d] = %d < 2", a, d->block[a]);
         if (B > kMaxBlock) return fail_global(SMCX_E_UNSUPPORTED, "block[%d] = %d > %d", a, B, kMaxBlock);
         block_out[a] = B;
@@ -693,6 +693,18 @@ void smcx_destroy(smcx_ctx* c)
     if (!c || c->view) return;
     ctx_release(c);
     delete c;
+}
+
+smcx_status smcx_plan(const smcx_desc* desc, int32_t block[3], int32_t blocks[3])
+{
+    int32_t B[3];
+    smcx_status st = validate_desc(desc, B, true);
+    if (st) return st;
+    for (int a = 0; a < 3; ++a) {
+        if (block) block[a] = B[a];
+        if (blocks) blocks[a] = axis_blocks(desc->L[a], B[a]);
+    }
+    return SMCX_OK;
 }
 
 // ---- verification hooks ------------------------------------------------------

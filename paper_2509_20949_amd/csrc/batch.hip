@@ -325,6 +325,23 @@ smcx_status smcx_batch_set_temperature(smcx_batch* b, int32_t r, double T)
 // Replica exchange (paper: P_swap = min(1, exp(Delta)),
 // Delta = (1/k_B)(1/T_i - 1/T_j)(E_i - E_j)).  Exchanging the temperatures
 // of two replicas is the same move as exchanging their configurations.
+smcx_status smcx_temperature_ladder(double T0, int32_t n, uint64_t n_atoms, double dT_ref, uint64_t n_ref,
+                                    double* out)
+{
+    if (!out || n < 1 || n_atoms == 0) return fail_global(SMCX_E_INVALID, "ladder needs out, n >= 1, n_atoms >= 1");
+    if (!(dT_ref > 0.0) || n_ref == 0) {   // the paper's example: 0.1 K at 10^9 atoms
+        dT_ref = 0.1;
+        n_ref = 1000000000ull;
+    }
+    const double dT = dT_ref * std::sqrt((double)n_ref / (double)n_atoms);
+    for (int32_t k = 0; k < n; ++k) {
+        out[k] = T0 + dT * k;
+        smcx_status st = validate_T(out[k]);
+        if (st) return fail_global(st, "ladder temperature %d = %g K outside [1, 5000]", k, out[k]);
+    }
+    return SMCX_OK;
+}
+
 smcx_status smcx_batch_exchange(smcx_batch* b, const int32_t* a, const int32_t* bb, int32_t n_pairs, uint64_t seed,
                                 uint64_t round, int32_t* accepted)
 {

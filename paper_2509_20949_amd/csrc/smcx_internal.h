@@ -134,6 +134,10 @@ __host__ __device__ inline int axis_blocks(int L, int B)
     return n;
 }
 
+// Block-width parameter the library uses along an axis of L cells when the
+// caller leaves it to the library (tables.cpp).
+int plan_block(int lattice, int L, int K);
+
 // Host helpers (tables.cpp).
 void build_thresholds(double T, double* out /* kTab */);
 // bias: the per-field offset the kernel packs into its histogram words

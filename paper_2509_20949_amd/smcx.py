@@ -58,6 +58,7 @@ def lib():
     _sig(L, "smcx_create_device", st, [pd, vp, _P(i32), dbl, vp, _P(vp)])
     _sig(L, "smcx_create_slab", st, [pd, vp, C.c_uint32, _P(i32), dbl, vp, _P(vp)])
     _sig(L, "smcx_slab_phase", st, [vp, i32])
+    _sig(L, "smcx_plan", st, [pd, _P(i32), _P(i32)])
     _sig(L, "smcx_set_temperature", st, [vp, dbl])
     _sig(L, "smcx_set_schedule", st, [vp, _P(dbl), i32])
     _sig(L, "smcx_sweep", st, [vp, i32])
@@ -80,6 +81,7 @@ def lib():
     _sig(L, "smcx_batch_ctx", st, [vp, i32, _P(vp)])
     _sig(L, "smcx_batch_set_temperature", st, [vp, i32, dbl])
     _sig(L, "smcx_batch_exchange", st, [vp, _P(i32), _P(i32), i32, u64, u64, _P(i32)])
+    _sig(L, "smcx_temperature_ladder", st, [dbl, i32, u64, dbl, u64, _P(dbl)])
     _sig(L, "smcx_batch_synchronize", st, [vp])
     _sig(L, "smcx_batch_destroy", None, [vp])
     _sig(L, "smcx_server_create", st, [C.c_size_t, i32, i32, _P(vp)])
@@ -169,6 +171,13 @@ def smcx_create_slab(desc: smcx_desc, d_buffer_ptr: int, z_offset: int, epi_ueV,
 
 def smcx_slab_phase(ctx, n: int):
     _check(lib().smcx_slab_phase(ctx, int(n)), ctx)
+
+
+def smcx_plan(desc: smcx_desc):
+    """(block width per axis, blocks per axis) of the schedule the library runs."""
+    blk, nb = (C.c_int32 * 3)(), (C.c_int32 * 3)()
+    _check(lib().smcx_plan(C.byref(desc), blk, nb))
+    return tuple(blk), tuple(nb)
 
 
 def smcx_set_temperature(ctx, T_kelvin: float):
@@ -335,6 +344,13 @@ def smcx_batch_exchange(batch, a, b, seed: int, round_: int):
     _check(lib().smcx_batch_exchange(batch, _ptr(a, C.c_int32), _ptr(b, C.c_int32), int(a.size), int(seed),
                                      int(round_), _ptr(acc, C.c_int32)))
     return acc
+
+
+def smcx_temperature_ladder(T0: float, n: int, n_atoms: int, dT_ref: float = 0.0, n_ref: int = 0) -> np.ndarray:
+    out = np.zeros(int(n), np.float64)
+    _check(lib().smcx_temperature_ladder(float(T0), int(n), int(n_atoms), float(dT_ref), int(n_ref),
+                                         _ptr(out, C.c_double)))
+    return out
 
 
 def smcx_batch_synchronize(batch):

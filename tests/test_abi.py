@@ -99,14 +99,34 @@ def test_null_handles_are_rejected(smcx):
     lib.smcx_destroy(None)   # no-op
 
 
-def test_schedule_block_counts_match_oracle(orc):
-    """The library's block-count rule (declared in smcx.h) is the oracle's."""
-    import paper_2509_20949_amd.smcx  # noqa: F401
+def test_schedule_block_counts_match_oracle(smcx, orc):
+    """The library's block-count rule (smcx_plan, computed by the library on
+    the host) equals the oracle's for every axis length and width."""
     for L in range(4, 200, 3):
-        for B in (2, 3, 5, 8, 12):
-            n = orc.axis_blocks(L, B)
-            want = max(2, min(2 * -(-L // (2 * B)), 2 * (L // 4)))
-            assert n == want
+        for B in (2, 3, 5, 8, 11, 12):
+            d = smcx.make_desc((L, 8, 9), 4, 3, (B, 4, 5), 1)
+            blk, nb = smcx.smcx_plan(d)
+            assert blk == (B, 4, 5)
+            assert nb == (orc.axis_blocks(L, B), orc.axis_blocks(8, 4), orc.axis_blocks(9, 5)), (L, B)
+
+
+def test_plan_depends_only_on_the_lattice_shape(smcx):
+    """block = 0: the library's choice is a fixed function of (lattice, L, K),
+    the same for every seed and shell count, and the same as the choice it
+    reports for that axis length in any other position."""
+    for lattice, Ks in ((0, (2, 4, 5, 8)), (1, (2, 5))):
+        for L in (4, 7, 16, 25, 37, 48, 64, 96, 512):
+            for K in Ks:
+                choices = set()
+                for S, seed in ((1, 1), (3, 99)):
+                    d = smcx.make_desc((L, 16, 33), K, S, (0, 0, 0), seed, lattice)
+                    blk, nb = smcx.smcx_plan(d)
+                    d2 = smcx.make_desc((33, L, 16), K, S, (0, 0, 0), seed + 1, lattice)
+                    blk2, _ = smcx.smcx_plan(d2)
+                    assert blk2[1] == blk[0]
+                    assert all(2 <= b <= 12 for b in blk) and all(n % 2 == 0 for n in nb)
+                    choices.add(blk[0])
+                assert len(choices) == 1, (lattice, L, K)
 
 
 def test_fcc_validation(smcx):
@@ -125,4 +145,25 @@ def test_fcc_validation(smcx):
     bad[-1] = 3
     with pytest.raises(smcx.SmcxError) as e:
         smcx.smcx_create(d, bad, np.zeros((3, 3, 3), np.int32), 800.0)
+    assert e.value.status == smcx.E_INVALID
+
+
+def test_temperature_ladder_scales_as_inverse_sqrt_n(smcx):
+    """Equation for Delta T: the spacing scales as 1/sqrt(N_atom); by default
+    it reproduces the paper's example (0.1 K at 10^9 atoms)."""
+    T = smcx.smcx_temperature_ladder(1000.0, 5, 10**9)
+    assert np.allclose(np.diff(T), 0.1, rtol=0, atol=1e-12) and T[0] == 1000.0
+    for N in (1024, 524288, 268435456, 1066867200):
+        a = smcx.smcx_temperature_ladder(800.0, 3, N, 2.0, 1024)
+        b = smcx.smcx_temperature_ladder(800.0, 3, 4 * N, 2.0, 1024)
+        assert np.isclose(np.diff(a)[0], 2.0 * np.sqrt(1024 / N), rtol=1e-14)
+        assert np.isclose(np.diff(b)[0] * 2, np.diff(a)[0], rtol=1e-14)   # 4x the atoms: half the spacing
+    # the paper's 1.07e9-atom production lattice: about 0.097 K from the 1e9 example
+    d = np.diff(smcx.smcx_temperature_ladder(1000.0, 2, 672 * 630 * 630 * 4))[0]
+    assert 0.096 < d < 0.0975
+    with pytest.raises(smcx.SmcxError) as e:
+        smcx.smcx_temperature_ladder(4999.0, 3, 100, 1.0, 100)
+    assert e.value.status == smcx.E_RANGE
+    with pytest.raises(smcx.SmcxError) as e:
+        smcx.smcx_temperature_ladder(800.0, 0, 100)
     assert e.value.status == smcx.E_INVALID
