@@ -56,8 +56,8 @@ BYTES_PER_TRIAL = 2
 # (profiles/sweep_phase_bcc512_k5s3_hbm_counters.md).  It describes the
 # kernel built from the sources with this SHA-256 only; for other sources
 # the bench reports traffic as null.
-MEASURED_TRAFFIC = {"sources_sha256": "93cc2582648db0ae452111b282b266b7f2df073341513a9a1715bf5d22d2e1da",
-                    "bytes_per_launch": 216600090}
+MEASURED_TRAFFIC = {"sources_sha256": "8f43f728b2c102040972614e1755beae6629e4fd6ffcd600955bf8caa18963b3",
+                    "bytes_per_launch": 216183088}
 KERNEL_SOURCES = ("paper_2509_20949_amd/csrc/kernels.hip", "paper_2509_20949_amd/csrc/device_common.h",
                   "paper_2509_20949_amd/csrc/smcx_internal.h")
 
@@ -88,6 +88,8 @@ def parse():
     ap.add_argument("--no-slab", action="store_true",
                     help="skip the 512x512x64 leg (one GPU's share of an 8-way z-slab split)")
     ap.add_argument("--no-fcc", action="store_true", help="skip the FCC leg (the paper's production lattice)")
+    ap.add_argument("--no-anneal", action="store_true",
+                    help="skip the 64^3 anneal leg (2000 -> 600 K over 1000 sweeps, energy and SRO every sweep)")
     ap.add_argument("--fcc-L", type=int, nargs=3, default=[336, 315, 315],
                     help="FCC cells per axis (672 630 630 = the paper's production lattice; the default is "
                          "its eighth, whose input is generated in seconds)")
@@ -103,6 +105,9 @@ def parse():
     ap.add_argument("--tune-blocks", action="store_true",
                     help="only measure batched throughput over replica edges 16..96 and block widths "
                          "(the measurements behind the library's block-width plan)")
+    ap.add_argument("--tune-wpg", action="store_true",
+                    help="only time the FCC leg's colour launches with 2 and 11 blocks per workgroup "
+                         "(the measurements behind the library's workgroup plan)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (5 times) to calibrate HBM byte counters")
     return ap.parse_args()
@@ -121,6 +126,31 @@ def copy_calibration():
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}), flush=True)
+
+
+def tune_wpg(smcx, W, sweeps=10):
+    """Colour-launch time of the FCC leg's lattice (336 x 315 x 315 cells,
+    the paper's alloy) with 2 blocks per workgroup (5 workgroups per CU) and
+    11 (one per CU), selected with the library's measurement override
+    SMCX_WAVES_PER_GROUP.  One JSON line per shape."""
+    job = W.fcc_alloy((336, 315, 315), n_sweeps=1, T=1000.0)
+    for wpg in (2, 11, 2, 11):
+        os.environ["SMCX_WAVES_PER_GROUP"] = str(wpg)
+        lat = smcx.Lattice(job.L, job.epi, job.sigma, job.seed, 1000.0, lattice=smcx.LATTICE_FCC)
+        try:
+            lat.sweep(2)
+            smcx.smcx_synchronize(lat.ctx)
+            smcx.smcx_profile(lat.ctx, True)
+            t0 = time.perf_counter()
+            lat.sweep(sweeps)
+            smcx.smcx_synchronize(lat.ctx)
+            dt = time.perf_counter() - t0
+            ms, n = smcx.smcx_kernel_time(lat.ctx)
+        finally:
+            lat.close()
+            del os.environ["SMCX_WAVES_PER_GROUP"]
+        print(json.dumps({"L": list(job.L), "lattice": "FCC", "waves_per_group": wpg,
+                          "avg_launch_ms": ms / max(n, 1), "swaps_per_s": job.N * sweeps / dt}), flush=True)
 
 
 def tune_blocks(smcx, W):
@@ -186,6 +216,34 @@ def slab_leg(args, smcx, W, sweeps=50):
             "kernel_only_value": job.N * sweeps / (kernel_ms / 1e3),
             "avg_launch_ms": kernel_ms / max(launches, 1), "energy_check_ok": ok,
             "halo": "2 planes each side, exchanged with itself by device copies between phases"}
+
+
+def anneal_leg(args, smcx, W):
+    """The 64^3 quinary anneal (524,288 sites, 3 shells, 2000 -> 600 K over
+    1000 sweeps) with the running energy and the Warren-Cowley SRO read
+    after every sweep, as the workload asks; the rate counts the
+    observables' pair-count passes and copies in."""
+    job = W.config2(n_sweeps=1000)
+    lat = smcx.Lattice(job.L, job.epi, job.sigma, job.seed, float(job.T[0]))
+    E = np.zeros(job.n_sweeps, np.int64)
+    alpha1 = np.zeros((job.n_sweeps, job.K, job.K))
+    try:
+        lat.set_schedule(job.T)
+        smcx.smcx_synchronize(lat.ctx)
+        t0 = time.perf_counter()
+        for k in range(job.n_sweeps):
+            lat.sweep(1)
+            E[k] = lat.energy()
+            alpha1[k] = lat.sro()[0][0]
+        dt = time.perf_counter() - t0
+        ok = lat.energy() == lat.energy_recompute()
+    finally:
+        lat.close()
+    return {"L": list(job.L), "sites": job.N, "sweeps": job.n_sweeps, "T_K": [float(job.T[0]), float(job.T[-1])],
+            "value": job.N * job.n_sweeps / dt, "unit": "swaps/s", "seconds": dt,
+            "E_first_last_ueV": [int(E[0]), int(E[-1])],
+            "alpha1_min_last": float(np.nanmin(alpha1[-1])), "alpha1_max_last": float(np.nanmax(alpha1[-1])),
+            "observables": "energy and SRO (pair counts) after every sweep", "energy_check_ok": ok}
 
 
 def fcc_leg(args, smcx, W):
@@ -383,6 +441,9 @@ def main():
     if args.tune_blocks:
         tune_blocks(smcx, W)
         return
+    if args.tune_wpg:
+        tune_wpg(smcx, W)
+        return
     t_gen = time.perf_counter()
     progress(f"generating the {args.L}^3 lattice")
     job = W.config3(n_sweeps=1, L=args.L)
@@ -467,6 +528,9 @@ def main():
     if not args.no_slab:
         progress("slab leg: 512 x 512 x 64")
         out["slab_share"] = slab_leg(args, smcx, W)
+    if not args.no_anneal:
+        progress("anneal leg: 64^3, 1000 sweeps, energy and SRO every sweep")
+        out["anneal"] = anneal_leg(args, smcx, W)
     if not args.no_fcc:
         progress(f"FCC leg: {args.fcc_L} cells x 4 sites")
         out["fcc"] = fcc_leg(args, smcx, W)

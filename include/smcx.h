@@ -260,18 +260,27 @@ smcx_status smcx_batch_synchronize(smcx_batch* batch);
 void smcx_batch_destroy(smcx_batch* batch);
 
 /* ---- serving: continuous batching of sweep requests ---------------------
- * A server owns an HBM budget and a number of slots.  Submitted requests
- * wait until their footprint fits and a slot is free; admitted lattices
- * stay resident; every smcx_server_step advances every resident request by
- * up to `sweeps_per_step` sweeps in one batched launch per phase and
- * retires the finished ones.  A request's result equals that of a single
- * context with the same inputs. */
+ * A server owns a number of slots and a device arena of hbm_budget_bytes,
+ * allocated once by smcx_server_create: admitting and retiring requests
+ * never allocates or frees device memory.  Submitted requests wait, in
+ * arrival order, until a slot is free and a range of the arena holds their
+ * footprint (first fit; a request that fits may pass one that does not).
+ * Admitted lattices stay resident; each step advances every resident
+ * request by up to `sweeps_per_step` sweeps in one batched launch per
+ * phase.  A request's result equals that of a single context with the same
+ * inputs. */
 smcx_status smcx_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t sweeps_per_step,
                                smcx_server** out);
 smcx_status smcx_server_submit(smcx_server* srv, const smcx_desc* desc, const uint8_t* species,
                                const int32_t* epi_ueV, double T_kelvin, int32_t n_sweeps,
                                uint64_t* request_id);
-/* One scheduling step: admit, run, retire.  Reports counts after the step. */
+/* One scheduling step, pipelined with the device: wait for the previous
+ * step's kernels, launch this step's (asynchronously, on the server's
+ * stream), retire the requests the previous step finished (their results
+ * are copied to host memory on a second stream while this step runs) and
+ * admit waiting requests (uploads and initial pair counts on the second
+ * stream; they join the next step).  A request therefore finishes one call
+ * after its last sweeps were launched.  Reports counts after the call. */
 smcx_status smcx_server_step(smcx_server* srv, int32_t* n_resident, int32_t* n_waiting,
                              int32_t* n_finished_this_step);
 /* Status of a request: 0 waiting, 1 resident, 2 finished, 3 failed. */

@@ -189,17 +189,19 @@ smcx_status write_state(smcx_ctx* c, int64_t E, uint64_t accepted)
 
 smcx_status recompute_energy(smcx_ctx* c, int64_t* E)
 {
-    smcx_status st = ctx_hip(c, hipMemsetAsync(c->d_counts, 0, sizeof(unsigned long long) * kMaxS * kMaxK * kMaxK,
-                                               c->stream), "hipMemsetAsync");
+    smcx_status st = ctx_hip(c, hipMemsetAsync(c->d_counts, 0, kCountBytes, c->stream), "hipMemsetAsync");
     if (st) return st;
     st = ctx_hip(c, launch_pair_counts(c->h_lat.lattice, c->d_own, c->h_lat.L, c->K, c->S, c->d_counts, c->stream),
                  "pair_counts launch");
     if (st) return st;
-    unsigned long long h[kMaxS * kMaxK * kMaxK];
-    st = ctx_hip(c, hipMemcpyAsync(h, c->d_counts, sizeof(h), hipMemcpyDeviceToHost, c->stream), "hipMemcpyAsync");
+    std::vector<unsigned long long> slots((size_t)kCountSlots * kCountWords);
+    st = ctx_hip(c, hipMemcpyAsync(slots.data(), c->d_counts, kCountBytes, hipMemcpyDeviceToHost, c->stream),
+                 "hipMemcpyAsync");
     if (st) return st;
     st = ctx_hip(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
     if (st) return st;
+    unsigned long long h[kCountWords];
+    count_sum(slots.data(), h);
     std::memcpy(c->counts, h, sizeof(h));
     int64_t twice = 0;
     for (int s = 0; s < c->S; ++s)
@@ -229,7 +231,7 @@ static smcx_status ctx_init(smcx_ctx* c, const smcx_desc* d, const int32_t B[3],
     if (st) return st;
     st = ctx_hip(c, hipMalloc(&c->d_state, sizeof(int64_t) * kStateWords), "hipMalloc(state)");
     if (st) return st;
-    st = ctx_hip(c, hipMalloc(&c->d_counts, sizeof(unsigned long long) * kMaxS * kMaxK * kMaxK), "hipMalloc(counts)");
+    st = ctx_hip(c, hipMalloc(&c->d_counts, kCountBytes), "hipMalloc(counts)");
     if (st) return st;
     const int wr = wrow(c->kmax, c->smax);
     std::vector<int32_t> w((size_t)c->kmax * c->kmax * wr);
@@ -248,6 +250,10 @@ static smcx_status ctx_init(smcx_ctx* c, const smcx_desc* d, const int32_t B[3],
     c->h_lat.slab = c->slab ? 1 : 0;
     c->h_lat.z_off = c->z_off;
     c->T_default = T;
+    int dev = 0, n_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        n_cu = 0;
+    c->wpg = c->slab ? kWavesPerGroup : plan_waves_per_group(d->lattice, c->h_lat.blocks_per_colour, n_cu);
     st = upload_tables(c, &T, 1, 0);
     if (st) return st;
     int64_t E0 = 0;
@@ -335,7 +341,7 @@ static smcx_status enqueue_phase(smcx_ctx* c, uint32_t s, int col, int groups)
         if (st) return st;
     }
     hipError_t e = launch_sweep_phase(c->h_lat.lattice, c->d_lat, nullptr, groups, (int)s, col, c->kmax, c->smax,
-                                      c->stream, c->slab);
+                                      c->stream, c->slab, c->wpg);
     if (e != hipSuccess) return ctx_hip(c, e, "sweep_phase launch");
     if (c->profiling) {
         smcx_status st = ctx_hip(c, hipEventRecord(e1, c->stream), "hipEventRecord");
@@ -372,8 +378,7 @@ static smcx_status slab_self_halo(smcx_ctx* c, int col, bool after)
 
 smcx_status enqueue_sweeps(smcx_ctx* c, int32_t n)
 {
-    const int wpg = waves_per_group(c->h_lat.lattice);
-    const int groups = (c->h_lat.blocks_per_colour + wpg - 1) / wpg;
+    const int groups = (c->h_lat.blocks_per_colour + c->wpg - 1) / c->wpg;
     for (int32_t k = 0; k < n; ++k) {
         const uint32_t s = (uint32_t)(c->sweeps + (uint64_t)k);
         for (int col = 0; col < 8; ++col) {
@@ -390,8 +395,7 @@ smcx_status enqueue_sweeps(smcx_ctx* c, int32_t n)
 
 smcx_status enqueue_phases(smcx_ctx* c, int32_t n)
 {
-    const int wpg = waves_per_group(c->h_lat.lattice);
-    const int groups = (c->h_lat.blocks_per_colour + wpg - 1) / wpg;
+    const int groups = (c->h_lat.blocks_per_colour + c->wpg - 1) / c->wpg;
     for (int32_t k = 0; k < n; ++k) {
         smcx_status st = enqueue_phase(c, (uint32_t)c->sweeps, c->phase, groups);
         if (st) return st;

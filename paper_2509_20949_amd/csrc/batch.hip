@@ -130,7 +130,7 @@ smcx_status smcx_batch_create(int32_t n, const smcx_desc* descs, const uint8_t* 
     if (!st) st = bhip(b, hipMalloc(&b->d_states, sizeof(int64_t) * kStateWords * n), "hipMalloc(states)");
     if (!st) st = bhip(b, hipMalloc(&b->d_tabs, sizeof(double) * kTab * n), "hipMalloc(tables)");
     if (!st) st = bhip(b, hipMalloc(&b->d_wtabs, sizeof(int32_t) * wsize * n), "hipMalloc(weights)");
-    if (!st) st = bhip(b, hipMalloc(&b->d_counts, sizeof(unsigned long long) * kMaxS * kMaxK * kMaxK), "hipMalloc");
+    if (!st) st = bhip(b, hipMalloc(&b->d_counts, kCountBytes), "hipMalloc");
     if (st) { batch_free(b); delete b; return st; }
 
     std::vector<int32_t> w(wsize);

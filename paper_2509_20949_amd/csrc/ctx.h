@@ -44,6 +44,7 @@ struct smcx_ctx {
     uint32_t z_off = 0;                      // global z of the slab's first own plane
     uint8_t* d_own = nullptr;                // the lattice's own sites (= d_species unless a slab)
     int phase = 0;                           // colour phases of the current sweep already enqueued
+    int wpg = 0;                             // blocks per workgroup of the colour launches (plan_waves_per_group)
     std::string err;
 };
 

@@ -219,23 +219,27 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int yz, 
 
 // ---------------------------------------------------------------------------
 // SLAB: the lattice is a z-slab (DevLattice::slab) -- its own instance, so
-// the periodic kernel carries none of the slab's addressing.
-template <int KMAX, int SMAX, bool SLAB>
-__global__ __launch_bounds__(kWave * kWavesPerGroup) __attribute__((amdgpu_waves_per_eu(kSweepWavesPerSimd)))
+// the periodic kernel carries none of the slab's addressing.  WPG: blocks
+// (waves) per workgroup, kWavesPerGroup (5 workgroups, 20 waves per CU,
+// bound by LDS).  Wider workgroups (3 of 7 or 2 of 11 per CU, 21 and 22
+// waves) fill the wave slots of a 512^3 colour launch more evenly but
+// measured no faster: a CU is busy issuing at 20 waves.
+template <int KMAX, int SMAX, bool SLAB, int WPG>
+__global__ __launch_bounds__(kWave * WPG) __attribute__((amdgpu_waves_per_eu(kSweepWavesPerSimd)))
 void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __restrict__ items, int n_groups,
                         int t, int colour)
 {
     constexpr int F = Field<KMAX>::F;
     __shared__ int32_t s_w[wplanes(KMAX, SMAX) * kPlane];
-    __shared__ __attribute__((aligned(16))) uint8_t s_lat[kWavesPerGroup * kWaveLds];
+    __shared__ __attribute__((aligned(16))) uint8_t s_lat[WPG * kWaveLds];
 
     const int wave = wave_id();
     const int lane = threadIdx.x % kWave;
     // group grp of the launch's n_groups (XCD-aware order): work item g of a
-    // batched launch, or blocks 4g .. 4g+3 of a single lattice
+    // batched launch, or blocks WPG g .. WPG g + WPG - 1 of a single lattice
     const int grp = xcd_group(n_groups);
     if (grp < 0) return;   // no later barrier in a workgroup without a group
-    int li = 0, f = grp * kWavesPerGroup;
+    int li = 0, f = grp * WPG;
     if (items) {
         li = items[grp].lattice;
         f = items[grp].first_block;
@@ -607,50 +611,55 @@ int kmax_for(int K)
     return 8;
 }
 
-template <int KMAX, int SMAX, bool SLAB>
+template <int KMAX, int SMAX, bool SLAB, int WPG>
 static hipError_t launch_t(const DevLattice* d_lat, const WorkItem* d_items, int n_groups, int t,
                            int colour, hipStream_t stream)
 {
-    hipLaunchKernelGGL((sweep_phase_kernel<KMAX, SMAX, SLAB>), dim3(xcd_grid(n_groups)),
-                       dim3(kWave * kWavesPerGroup), 0, stream, d_lat, d_items, n_groups, t, colour);
+    hipLaunchKernelGGL((sweep_phase_kernel<KMAX, SMAX, SLAB, WPG>), dim3(xcd_grid(n_groups)), dim3(kWave * WPG),
+                       0, stream, d_lat, d_items, n_groups, t, colour);
     return hipGetLastError();
 }
 
-template <int KMAX, bool SLAB>
+template <int KMAX, bool SLAB, int WPG>
 static hipError_t launch_k(const DevLattice* d_lat, const WorkItem* d_items, int n_groups, int t,
                            int colour, int smax, hipStream_t stream)
 {
     switch (smax) {
-    case 1: return launch_t<KMAX, 1, SLAB>(d_lat, d_items, n_groups, t, colour, stream);
-    case 2: return launch_t<KMAX, 2, SLAB>(d_lat, d_items, n_groups, t, colour, stream);
-    case 3: return launch_t<KMAX, 3, SLAB>(d_lat, d_items, n_groups, t, colour, stream);
+    case 1: return launch_t<KMAX, 1, SLAB, WPG>(d_lat, d_items, n_groups, t, colour, stream);
+    case 2: return launch_t<KMAX, 2, SLAB, WPG>(d_lat, d_items, n_groups, t, colour, stream);
+    case 3: return launch_t<KMAX, 3, SLAB, WPG>(d_lat, d_items, n_groups, t, colour, stream);
     }
     return hipErrorInvalidValue;
 }
 
-template <bool SLAB>
+template <bool SLAB, int WPG>
 static hipError_t launch_bcc(const DevLattice* d_lat, const WorkItem* d_items, int n_groups, int t, int colour,
                              int kmax, int smax, hipStream_t stream)
 {
     switch (kmax) {
-    case 2: return launch_k<2, SLAB>(d_lat, d_items, n_groups, t, colour, smax, stream);
-    case 3: return launch_k<3, SLAB>(d_lat, d_items, n_groups, t, colour, smax, stream);
-    case 4: return launch_k<4, SLAB>(d_lat, d_items, n_groups, t, colour, smax, stream);
-    case 5: return launch_k<5, SLAB>(d_lat, d_items, n_groups, t, colour, smax, stream);
-    case 6: return launch_k<6, SLAB>(d_lat, d_items, n_groups, t, colour, smax, stream);
-    case 8: return launch_k<8, SLAB>(d_lat, d_items, n_groups, t, colour, smax, stream);
+    case 2: return launch_k<2, SLAB, WPG>(d_lat, d_items, n_groups, t, colour, smax, stream);
+    case 3: return launch_k<3, SLAB, WPG>(d_lat, d_items, n_groups, t, colour, smax, stream);
+    case 4: return launch_k<4, SLAB, WPG>(d_lat, d_items, n_groups, t, colour, smax, stream);
+    case 5: return launch_k<5, SLAB, WPG>(d_lat, d_items, n_groups, t, colour, smax, stream);
+    case 6: return launch_k<6, SLAB, WPG>(d_lat, d_items, n_groups, t, colour, smax, stream);
+    case 8: return launch_k<8, SLAB, WPG>(d_lat, d_items, n_groups, t, colour, smax, stream);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_sweep_phase(int lattice, const DevLattice* d_lat, const WorkItem* d_items, int n_groups, int t,
-                              int colour, int kmax, int smax, hipStream_t stream, bool slab)
+                              int colour, int kmax, int smax, hipStream_t stream, bool slab, int wpg)
 {
     if (n_groups <= 0) return hipSuccess;
-    if (lattice == 1) return slab ? hipErrorInvalidValue
-                                  : launch_sweep_phase_fcc(d_lat, d_items, n_groups, t, colour, smax, stream);
-    return slab ? launch_bcc<true>(d_lat, d_items, n_groups, t, colour, kmax, smax, stream)
-                : launch_bcc<false>(d_lat, d_items, n_groups, t, colour, kmax, smax, stream);
+    if (lattice == 1)
+        return slab ? hipErrorInvalidValue
+                    : launch_sweep_phase_fcc(d_lat, d_items, n_groups, t, colour, smax, stream,
+                                             wpg ? wpg : kWavesPerGroupFcc);
+    if (slab) return wpg && wpg != kWavesPerGroup ? hipErrorInvalidValue
+                                                   : launch_bcc<true, kWavesPerGroup>(d_lat, d_items, n_groups, t,
+                                                                                     colour, kmax, smax, stream);
+    if (wpg && wpg != kWavesPerGroup) return hipErrorInvalidValue;
+    return launch_bcc<false, kWavesPerGroup>(d_lat, d_items, n_groups, t, colour, kmax, smax, stream);
 }
 
 __global__ void species_max_kernel(const uint8_t* __restrict__ g, size_t n, unsigned int* __restrict__ out)

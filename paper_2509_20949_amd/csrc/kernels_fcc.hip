@@ -223,22 +223,25 @@ __device__ __forceinline__ int lds_index(int b, int lx, int ly, int lz)
 
 }  // namespace fcc
 
-template <int SMAX>
-__global__ __launch_bounds__(kWave * kWavesPerGroupFcc)
+// WPG waves (blocks) per workgroup: 2 (five workgroups per CU, LDS-bound), or
+// kWavesPerGroupFccWide for a single lattice whose colour then fits the chip
+// in fewer generations (one workgroup of 11 block images fills a CU's LDS).
+template <int SMAX, int WPG>
+__global__ __launch_bounds__(kWave * WPG)
 void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem* __restrict__ items, int n_groups,
                             int t, int colour)
 {
     using namespace fcc;
     __shared__ int32_t s_w[wplanes(KMAXF, SMAX) * wplane(KMAXF)];
-    __shared__ __attribute__((aligned(16))) uint8_t s_lat[kWavesPerGroupFcc * kWaveLdsF];
+    __shared__ __attribute__((aligned(16))) uint8_t s_lat[WPG * kWaveLdsF];
 
     const int wave = wave_id();
     const int lane = threadIdx.x % kWave;
     // group grp of the launch's n_groups (XCD-aware order): work item g of a
-    // batched launch, or blocks 2g, 2g+1 of a single lattice
+    // batched launch, or blocks WPG g .. WPG g + WPG - 1 of a single lattice
     const int grp = xcd_group(n_groups);
     if (grp < 0) return;   // no later barrier in a workgroup without a group
-    int li = 0, f = grp * kWavesPerGroupFcc;
+    int li = 0, f = grp * WPG;
     if (items) {
         li = items[grp].lattice;
         f = items[grp].first_block;
@@ -416,18 +419,33 @@ void sweep_phase_fcc_kernel(const DevLattice* __restrict__ lats, const WorkItem*
     }
 }
 
-hipError_t launch_sweep_phase_fcc(const DevLattice* d_lat, const WorkItem* d_items, int n_groups, int t, int colour,
-                                  int smax, hipStream_t stream)
+template <int WPG>
+static hipError_t launch_fcc(const DevLattice* d_lat, const WorkItem* d_items, int n_groups, int t, int colour,
+                             int smax, hipStream_t stream)
 {
-    if (n_groups <= 0) return hipSuccess;
-    const dim3 grid(xcd_grid(n_groups)), block(kWave * kWavesPerGroupFcc);
+    const dim3 grid(xcd_grid(n_groups)), block(kWave * WPG);
     switch (smax) {
-    case 1: hipLaunchKernelGGL(sweep_phase_fcc_kernel<1>, grid, block, 0, stream, d_lat, d_items, n_groups, t, colour); break;
-    case 2: hipLaunchKernelGGL(sweep_phase_fcc_kernel<2>, grid, block, 0, stream, d_lat, d_items, n_groups, t, colour); break;
-    case 3: hipLaunchKernelGGL(sweep_phase_fcc_kernel<3>, grid, block, 0, stream, d_lat, d_items, n_groups, t, colour); break;
+    case 1: hipLaunchKernelGGL((sweep_phase_fcc_kernel<1, WPG>), grid, block, 0, stream, d_lat, d_items, n_groups, t,
+                               colour); break;
+    case 2: hipLaunchKernelGGL((sweep_phase_fcc_kernel<2, WPG>), grid, block, 0, stream, d_lat, d_items, n_groups, t,
+                               colour); break;
+    case 3: hipLaunchKernelGGL((sweep_phase_fcc_kernel<3, WPG>), grid, block, 0, stream, d_lat, d_items, n_groups, t,
+                               colour); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_sweep_phase_fcc(const DevLattice* d_lat, const WorkItem* d_items, int n_groups, int t, int colour,
+                                  int smax, hipStream_t stream, int wpg)
+{
+    if (n_groups <= 0) return hipSuccess;
+    if (wpg == kWavesPerGroupFccWide) {
+        if (d_items) return hipErrorInvalidValue;   // work items cover kWavesPerGroupFcc blocks each
+        return launch_fcc<kWavesPerGroupFccWide>(d_lat, d_items, n_groups, t, colour, smax, stream);
+    }
+    if (wpg != kWavesPerGroupFcc) return hipErrorInvalidValue;
+    return launch_fcc<kWavesPerGroupFcc>(d_lat, d_items, n_groups, t, colour, smax, stream);
 }
 
 }  // namespace smcx

@@ -220,7 +220,15 @@ void pair_counts_kernel(const uint8_t* __restrict__ g, int Lx, int Ly, int Lz, i
     if (lane < C)
         for (int d = 0; d < nb; ++d) mine[d * C] = 0u;
 
+    // Waves take contiguous runs of tasks (row after row, so the neighbour
+    // rows of the next task were mostly just read), and workgroups are
+    // numbered XCD-aware (xcd_group): the runs of one XCD are adjacent and
+    // share its L2.
     const uint32_t nwaves = gridDim.x * (uint32_t)nwv;
+    const uint32_t per_wave = (n_tasks + nwaves - 1) / nwaves;
+    const int grp = xcd_group((int)gridDim.x);
+    const uint32_t t_begin = grp < 0 ? n_tasks : (uint32_t)(grp * nwv + wave) * per_wave;
+    const uint32_t t_end = min(n_tasks, t_begin + per_wave);
     const uint32_t nchunk = (uint32_t)(Lx + kWave - 1) / kWave;
     // task t: cells (t % nchunk) * 64 + lane of row t / nchunk
     auto locate = [&](uint32_t t, int& y, int& z, int (&xo)[3]) -> bool {
@@ -235,19 +243,19 @@ void pair_counts_kernel(const uint8_t* __restrict__ g, int Lx, int Ly, int Lz, i
         return x < Lx;
     };
     const auto cells = std::make_integer_sequence<int, 27>{};
-    uint32_t t = blockIdx.x * (uint32_t)nwv + (uint32_t)wave;
+    uint32_t t = t_begin;
     uint32_t v[27], vn[27];
     int y, z, xo[3];
     bool valid = false;
-    if (t < n_tasks) {
+    if (t < t_end) {
         valid = locate(t, y, z, xo);
         pc::load_cells<LAT>(g, Lx, Ly, Lz, y, z, xo, v, cells);
     }
-    while (t < n_tasks) {
+    while (t < t_end) {
         // the next task's loads go out before this task's counting
-        const uint32_t tn = t + nwaves;
+        const uint32_t tn = t + 1;
         bool valid_n = false;
-        if (tn < n_tasks) {
+        if (tn < t_end) {
             int yn, zn, xon[3];
             valid_n = locate(tn, yn, zn, xon);
             pc::load_cells<LAT>(g, Lx, Ly, Lz, yn, zn, xon, vn, cells);
@@ -295,13 +303,14 @@ void pair_counts_kernel(const uint8_t* __restrict__ g, int Lx, int Ly, int Lz, i
             }
         }
         const int m = d / (K * D), a = (d / D) % K, k = d % D;
+        unsigned long long* out = counts + (blockIdx.x % kCountSlots) * kCountWords;   // spread over the slots
         if (lo) {
-            atomicAdd(&counts[(m * kMaxK + a) * kMaxK + k], (unsigned long long)lo);
-            atomicAdd(&counts[(m * kMaxK + k) * kMaxK + a], (unsigned long long)lo);
+            atomicAdd(&out[(m * kMaxK + a) * kMaxK + k], (unsigned long long)lo);
+            atomicAdd(&out[(m * kMaxK + k) * kMaxK + a], (unsigned long long)lo);
         }
         if (hi) {
-            atomicAdd(&counts[(m * kMaxK + a) * kMaxK + k + HI], (unsigned long long)hi);
-            atomicAdd(&counts[(m * kMaxK + k + HI) * kMaxK + a], (unsigned long long)hi);
+            atomicAdd(&out[(m * kMaxK + a) * kMaxK + k + HI], (unsigned long long)hi);
+            atomicAdd(&out[(m * kMaxK + k + HI) * kMaxK + a], (unsigned long long)hi);
         }
     }
 }
@@ -317,11 +326,13 @@ static hipError_t launch_pc(const uint8_t* species, const int32_t L[3], int K, i
     const uint64_t nchunk = ((uint64_t)L[0] + kWave - 1) / kWave;
     const uint64_t tasks = nchunk * (uint64_t)L[1] * (uint64_t)L[2];
     if (tasks > 0xffffffffull) return hipErrorInvalidValue;
+    // enough waves for the chip (4096) and for the counters' range, at least
+    // 16 tasks each where the lattice is small (each wave ends in a flush)
     uint64_t waves = (tasks + pc::kMaxTasksPerWave - 1) / pc::kMaxTasksPerWave;
-    waves = std::max<uint64_t>(waves, std::min<uint64_t>(tasks, 4096));
+    waves = std::max<uint64_t>(waves, std::min<uint64_t>((tasks + 15) / 16, 4096));
     const uint64_t groups = (waves + waves_per_group - 1) / waves_per_group;
     const size_t lds = (size_t)waves_per_group * nb * pc::kBinLanes * sizeof(uint32_t);
-    const dim3 grid((unsigned)groups), block((unsigned)(waves_per_group * kWave));
+    const dim3 grid((unsigned)xcd_grid((int)groups)), block((unsigned)(waves_per_group * kWave));
     switch (S) {
     case 1: hipLaunchKernelGGL((pair_counts_kernel<LAT, F, 1>), grid, block, lds, stream, species, L[0], L[1], L[2], K,
                                (uint32_t)tasks, d_counts); break;
@@ -334,8 +345,9 @@ static hipError_t launch_pc(const uint8_t* species, const int32_t L[3], int K, i
     return hipGetLastError();
 }
 
-// d_counts ([kMaxS][kMaxK][kMaxK] uint64) receives N_m[p'][p] added to what
-// it holds; the caller clears it first.
+// d_counts (kCountSlots copies of [kMaxS][kMaxK][kMaxK] uint64) receives
+// N_m[p'][p] added to what it holds, split over the copies; the caller
+// clears it first and sums the copies (count_sum).
 hipError_t launch_pair_counts(int lattice, const uint8_t* species, const int32_t L[3], int K, int S,
                               unsigned long long* d_counts, hipStream_t stream)
 {

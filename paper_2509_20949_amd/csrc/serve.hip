@@ -62,13 +62,12 @@ struct Request {
     std::string err;
 };
 
-constexpr size_t kCountsBytes = sizeof(unsigned long long) * kMaxS * kMaxK * kMaxK;
 
 size_t footprint_of(const smcx_desc* d)
 {
     const int kmax = kmax_for(d->lattice, d->n_species), smax = d->n_shells;
     return align256(n_sites(d->lattice, d->L)) + align256(sizeof(double) * kTab) +
-           align256(sizeof(int32_t) * (size_t)kmax * kmax * wrow(kmax, smax)) + align256(kCountsBytes);
+           align256(sizeof(int32_t) * (size_t)kmax * kmax * wrow(kmax, smax)) + align256(kCountBytes);
 }
 
 // First-fit allocator of arena ranges (offsets), free ranges coalesced.
@@ -173,7 +172,7 @@ smcx_status admit(smcx_server* s, Request* q)
     // host image of table | weights | zero counts, and a zero state image
     // (members of the request: the copies from them are asynchronous)
     std::vector<uint8_t>& img = q->upload;
-    img.assign(off_c + kCountsBytes - off_tab, 0);
+    img.assign(off_c + kCountBytes - off_tab, 0);
     build_thresholds(q->T, (double*)img.data());
     const int drop = build_wtab(q->epi.data(), q->desc.n_species, q->desc.n_shells, q->kmax, q->smax,
                                 wtab_bias(q->desc.lattice, q->kmax), true, (int32_t*)(img.data() + (off_w - off_tab)));
@@ -217,7 +216,7 @@ smcx_status retire_copies(smcx_server* s, Request* q, std::vector<int64_t>& st2,
                            "hipMemcpyAsync(config)");
     if (!st) st = shipc(s, hipMemcpyAsync(st2.data(), q->lat.state, sizeof(int64_t) * kStateWords,
                                           hipMemcpyDeviceToHost, s->ustream), "hipMemcpyAsync(state)");
-    if (!st) st = shipc(s, hipMemcpyAsync(cnt.data(), s->d_arena + q->off + off_c, kCountsBytes,
+    if (!st) st = shipc(s, hipMemcpyAsync(cnt.data(), s->d_arena + q->off + off_c, kCountBytes,
                                           hipMemcpyDeviceToHost, s->ustream), "hipMemcpyAsync(counts)");
     return st;
 }
@@ -399,7 +398,7 @@ smcx_status smcx_server_step(smcx_server* s, int32_t* n_resident, int32_t* n_wai
     if (!leaving.empty()) {
         std::vector<std::vector<int64_t>> sts(leaving.size(), std::vector<int64_t>(kStateWords));
         std::vector<std::vector<unsigned long long>> cnts(leaving.size(),
-                                                          std::vector<unsigned long long>(kMaxS * kMaxK * kMaxK));
+                                                          std::vector<unsigned long long>((size_t)kCountSlots * kCountWords));
         std::vector<smcx_status> rst(leaving.size());
         for (size_t k = 0; k < leaving.size(); ++k) rst[k] = retire_copies(s, leaving[k], sts[k], cnts[k]);
         st = shipc(s, hipStreamSynchronize(s->ustream), "hipStreamSynchronize");
@@ -412,7 +411,9 @@ smcx_status smcx_server_step(smcx_server* s, int32_t* n_resident, int32_t* n_wai
             } else {
                 int64_t dE = 0;
                 state_sum(sts[k].data(), &dE, &q->accepted);
-                q->E = energy_from_counts(q, cnts[k].data()) + dE;
+                unsigned long long counts[kCountWords];
+                count_sum(cnts[k].data(), counts);
+                q->E = energy_from_counts(q, counts) + dE;
                 q->state = FINISHED;
                 ++finished_now;
             }

@@ -13,6 +13,7 @@ namespace smcx {
 constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kWavesPerGroup = 4;    // blocks (one per wave) per workgroup, BCC
 constexpr int kWavesPerGroupFcc = 2; // FCC: its 13.9 KB block images fit 5 workgroups of 2 per CU
+constexpr int kWavesPerGroupFccWide = 11;   // FCC single lattice: 11 images fill a CU's 160 KB of LDS
 constexpr int kMaxBlock = 12;        // widest block: 4 x 4 x 4 cells per sub-colour round
 constexpr int kMaxK = 8;
 constexpr int kMaxS = 3;
@@ -63,6 +64,15 @@ constexpr int kSlotWords = 8;                        // 64 bytes per slot: energ
 constexpr int kStateWords = kSpread * kSlotWords;    // int64 words per lattice
 void state_init(int64_t* h /* kStateWords */, int64_t E, uint64_t accepted);
 void state_sum(const int64_t* h /* kStateWords */, int64_t* E, uint64_t* accepted);
+
+// Pair counts N_m[p'][p] as the pair-count kernel leaves them: kCountSlots
+// copies of [kMaxS][kMaxK][kMaxK] uint64, workgroup b adding into copy
+// b % kCountSlots (its atomics then meet few others on an address); the
+// counts are the sums over the copies (count_sum, tables.cpp).
+constexpr int kCountWords = kMaxS * kMaxK * kMaxK;
+constexpr int kCountSlots = 16;
+constexpr size_t kCountBytes = sizeof(unsigned long long) * kCountWords * kCountSlots;
+void count_sum(const unsigned long long* slots /* kCountSlots * kCountWords */, unsigned long long* out /* kCountWords */);
 
 // Per-lattice state the kernels read (device memory).
 struct DevLattice {
@@ -137,6 +147,10 @@ __host__ __device__ inline int axis_blocks(int L, int B)
 // Block-width parameter the library uses along an axis of L cells when the
 // caller leaves it to the library (tables.cpp).
 int plan_block(int lattice, int L, int K);
+// Blocks per workgroup of a single lattice's colour launches with
+// blocks_per_colour blocks on a device of n_cu compute units (tables.cpp);
+// work placement only, never the trajectory.
+int plan_waves_per_group(int lattice, int blocks_per_colour, int n_cu);
 
 // Host helpers (tables.cpp).
 void build_thresholds(double T, double* out /* kTab */);
@@ -149,12 +163,16 @@ int build_wtab(const int32_t* epi, int K, int S, int kmax, int smax, int bias, b
 
 // Launchers (kernels.hip, kernels_fcc.hip, pair_counts.hip).  Return hipSuccess or the launch error.
 // slab: d_lat describes a z-slab (BCC only; one lattice, no work items).
+// wpg: blocks per workgroup, 0 for the lattice type's default
+// (waves_per_group); single FCC lattices may take kWavesPerGroupFccWide
+// (plan_waves_per_group).
 hipError_t launch_sweep_phase(int lattice, const DevLattice* d_lat, const WorkItem* d_items, int n_groups,
-                              int t, int colour, int kmax, int smax, hipStream_t stream, bool slab = false);
+                              int t, int colour, int kmax, int smax, hipStream_t stream, bool slab = false,
+                              int wpg = 0);
 hipError_t launch_pair_counts(int lattice, const uint8_t* species, const int32_t L[3], int K, int S,
                               unsigned long long* d_counts, hipStream_t stream);
 hipError_t launch_sweep_phase_fcc(const DevLattice* d_lat, const WorkItem* d_items, int n_groups, int t,
-                                  int colour, int smax, hipStream_t stream);
+                                  int colour, int smax, hipStream_t stream, int wpg);
 hipError_t launch_species_max(const uint8_t* species, size_t n, unsigned int* d_max, hipStream_t stream);
 hipError_t launch_thresholds(const double* d_tab, const int32_t* d_dE, int n, double* d_out, hipStream_t stream);
 hipError_t launch_accept_bounds(const double* d_tab, const uint32_t* d_u, int n, int32_t* d_lo, int32_t* d_hi,

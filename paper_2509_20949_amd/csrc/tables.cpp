@@ -1,5 +1,6 @@
 // tables.cpp -- host-built tables of libsmcx.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "smcx_internal.h"
@@ -138,6 +139,37 @@ int plan_block(int lattice, int L, int K)
     (void)L;
     (void)K;
     return kMaxBlock;
+}
+
+// A colour launch of a single lattice runs its blocks in "generations" of
+// the wave slots the chip holds; a partly filled last generation leaves
+// most of the chip idle at the end of every launch.  FCC blocks fill 10
+// slots per CU in workgroups of 2 (LDS-bound), or 11 in one workgroup of 11
+// images (160 KB of LDS): the wide form is taken when it needs fewer
+// generations, e.g. 2,744 blocks (the 336 x 315 x 315 lattice) take one
+// generation of 2,816 slots instead of 1.07 of 2,560 (measured 196 us per
+// launch against 273).  BCC keeps its 4-wave workgroups: on the 512^3
+// lattice, workgroups of 7 and 11 blocks (21 and 22 waves per CU) measured
+// no faster.
+int plan_waves_per_group(int lattice, int blocks_per_colour, int n_cu)
+{
+    if (const char* f = std::getenv("SMCX_WAVES_PER_GROUP")) {   // measurement override (bench.py --tune-wpg)
+        const int w = std::atoi(f);
+        if (lattice == 1 && (w == kWavesPerGroupFcc || w == kWavesPerGroupFccWide)) return w;
+    }
+    if (lattice != 1 || n_cu < 1) return lattice == 1 ? kWavesPerGroupFcc : kWavesPerGroup;
+    const long narrow = 10L * n_cu, wide = (long)kWavesPerGroupFccWide * n_cu;
+    const long g_narrow = (blocks_per_colour + narrow - 1) / narrow, g_wide = (blocks_per_colour + wide - 1) / wide;
+    return g_wide < g_narrow ? kWavesPerGroupFccWide : kWavesPerGroupFcc;
+}
+
+void count_sum(const unsigned long long* slots, unsigned long long* out)
+{
+    for (int k = 0; k < kCountWords; ++k) {
+        unsigned long long v = 0;
+        for (int c = 0; c < kCountSlots; ++c) v += slots[(size_t)c * kCountWords + k];
+        out[k] = v;
+    }
 }
 
 void state_init(int64_t* h, int64_t E, uint64_t accepted)
