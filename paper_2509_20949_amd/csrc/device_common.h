@@ -41,15 +41,18 @@ __device__ __forceinline__ void keep(uint32_t& h) { asm("" : "+v"(h)); }
 constexpr int wplane(int kmax) { return ((kmax * kmax + 31) / 32) * 32; }
 constexpr int wplanes(int kmax, int smax) { return wrow_entries(kmax, smax); }
 
-// Fill the LDS planes (PS dwords apart, PS >= KMAX*KMAX) from the
-// row-major table of wrow(KMAX, SMAX) ints per row.
-template <int KMAX, int SMAX, int PS = wplane(KMAX)>
+// Fill the LDS planes (PS dwords apart) from the row-major table of
+// wrow(KMAX, SMAX) ints per row.  Row (a, b) goes to plane position
+// a*KMAX + b (PS >= KMAX*KMAX), or with ROW8 to a*8 + b (PS >= 64), which
+// spares the sweep a multiply when it forms the position from two codes.
+template <int KMAX, int SMAX, int PS = wplane(KMAX), bool ROW8 = false>
 __device__ __forceinline__ void load_wplanes(int32_t* s_w, const int32_t* wtab)
 {
     constexpr int WR = wrow(KMAX, SMAX);
     for (int k = threadIdx.x; k < wplanes(KMAX, SMAX) * PS; k += blockDim.x) {
-        const int f = k / PS, row = k - f * PS;
-        s_w[k] = row < KMAX * KMAX ? wtab[row * WR + f] : 0;
+        const int f = k / PS, pos = k - f * PS;
+        const int a = ROW8 ? pos >> 3 : pos / KMAX, b = ROW8 ? pos & 7 : pos - a * KMAX;
+        s_w[k] = a < KMAX && b < KMAX ? wtab[(a * KMAX + b) * WR + f] : 0;
     }
 }
 
@@ -95,6 +98,28 @@ template <class T> __device__ __forceinline__ void gstore(uint8_t* p, T v)
     *(__attribute__((address_space(1))) T*)p = v;
 }
 
+// Raw buffer resource over the n bytes from p (stride 0; the third word is
+// the gfx9 32-bit data format).  The hardware checks every buffer access
+// against n: loads past it return 0, stores past it are dropped.  The
+// staging and write-back of the sweep kernels address a lattice plane by
+// a resource whose base is that plane (scalar registers) and a 32-bit
+// per-lane offset, so their rows need no 64-bit vector arithmetic.
+constexpr int kRsrcWord3 = 0x00020000;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t byte_rsrc(uint8_t* p, uint64_t n)
+{
+    // min(n, 2^32 - 1), on the scalar unit (it has no 64-bit ordered compare)
+    const uint32_t nr = (uint32_t)(n >> 32) != 0u ? 0xffffffffu : (uint32_t)n;
+    return __builtin_amdgcn_make_buffer_rsrc(p, 0, (int)nr, kRsrcWord3);
+}
+__device__ __forceinline__ uint32_t bload32(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void bstore16(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t v)
+{
+    __builtin_amdgcn_raw_buffer_store_b16((uint16_t)v, r, (int)off, 0, 0);
+}
+
 // Bounds of the Metropolis test (Eq. (3)) for an acceptance draw u.
 // The exact test accepts an uphill change dE iff u < thr(dE), thr the FP64
 // table product, equal to 2^32 exp(-dE / k_B T) to a relative 1e-12.  Let x
@@ -109,12 +134,26 @@ template <class T> __device__ __forceinline__ void gstore(uint8_t* p, T v)
 // passes the exact test and every dE > hi fails it.  Only lo < dE <= hi
 // (and u = 0, where x is infinite but thr may underflow) need the table.
 // c = ln2 k_B T in micro-eV, as a float.
+// The sweep kernels compare float(dE) with the edges elo = e - M and
+// ehi = e + M: for an integer dE in (0, 2^24), float(dE) is exact, and
+// float(dE) <= elo iff dE <= lo = floor(elo), likewise for hi.  (u = 0:
+// e = +inf.)
 constexpr float kAcceptMargin = 8.0f;
+__device__ __forceinline__ void accept_edges(uint32_t u, float c, float& elo, float& ehi)
+{
+    const float e = (32.0f - __builtin_amdgcn_logf((float)u)) * c;
+    elo = e - kAcceptMargin;
+    ehi = e + kAcceptMargin;
+}
+// The same bounds as integers, lo = floor(elo) and hi = floor(ehi) (at most
+// 1e9; e >= 0, and the truncation is the floor wherever the bound is
+// positive, the only place it is used).
 __device__ __forceinline__ void accept_bounds(uint32_t u, float c, int& lo, int& hi)
 {
-    const float e = fminf((32.0f - __builtin_amdgcn_logf((float)u)) * c, 1.0e9f);   // u = 0: +inf -> 1e9
-    lo = (int)(e - kAcceptMargin);   // truncation: floor where positive
-    hi = (int)(e + kAcceptMargin);
+    float elo, ehi;
+    accept_edges(u, c, elo, ehi);
+    lo = (int)fminf(elo, 1.0e9f);
+    hi = (int)fminf(ehi, 1.0e9f);
 }
 
 // XCD-aware workgroup order of a sweep launch.  Workgroups are

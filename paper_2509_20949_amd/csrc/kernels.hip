@@ -46,14 +46,15 @@ template <int SUB> __device__ __forceinline__ constexpr int s1base() { return SU
 // of 4 waves per CU.
 constexpr int kSweepWavesPerSimd = 5;
 // Rows whose loads a lane issues together when staging a block (registers
-// bound it: three words per row on the fast path).
+// bound it: one aligned word per row once the two loads are joined).
 constexpr int kStageBatch = 16;
 
-// Weight planes of the BCC kernel: 64 rows each, so that the row a*KMAX + b
-// of any two 3-bit codes (a lane without a site may decode a stale halo
-// byte) stays inside its plane without clamping.
+// Weight planes of the BCC kernel: row (a, b) at position 8a + b of a
+// 64-entry plane, so that the position of any two 3-bit codes (a lane
+// without a site may decode a stale halo byte) stays inside its plane and
+// is formed from the codes by a mask, a shift and a shift-add.
 constexpr int kPlane = 64;
-static_assert(7 * kMaxK + 7 < kPlane, "weight plane too narrow");
+static_assert(8 * 7 + 7 < kPlane && kMaxK <= 8, "weight plane too narrow");
 
 // Shell offsets inside one sublattice array.
 __device__ __forceinline__ constexpr int s2off(int k)
@@ -68,46 +69,41 @@ __device__ __forceinline__ constexpr int s3off(int k)
          : k == 8 ? kP + kPP : k == 9 ? kP - kPP : k == 10 ? -kP + kPP : -kP - kPP;
 }
 
-// Packed species histogram of the neighbours of the site at LDS byte `a`
-// with sublattice SUB, one 32-bit word per shell, added to h.  Each shell is
-// summed in a few short chains of shift-adds (kept apart by keep(), so each
-// step stays one v_lshl_add) that are joined at the end: short dependency
-// chains for latency, one instruction per neighbour for throughput.
-template <int SMAX, int SUB>
-__device__ __forceinline__ void histogram(const uint8_t* lat, int a, uint32_t (&h)[kMaxS])
+// Add +1 (NEG: -1) in the field of code c to h: one shift-add.
+template <bool NEG> __device__ __forceinline__ void count1(uint32_t& h, uint32_t c)
 {
-    const int b1 = a + s1base<SUB>();
-    uint32_t p0 = h[0], p1 = 0u;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const uint32_t c = lat[b1 + (e & 1) + ((e >> 1) & 1) * kP + ((e >> 2) & 1) * kPP];
-        uint32_t& acc = (e & 1) ? p1 : p0;
-        acc += 1u << (c & 31);
-        keep(acc);
-    }
-    h[0] = p0 + p1;
+    h += (NEG ? 0xffffffffu : 1u) << (c & 31u);
+    keep(h);
+}
+
+// Counts of the second and third shells of the site at LDS byte a (its own
+// sublattice), added to h[1] and h[2]; the codes of the 6 second and 12
+// third neighbours are returned in r2 and r3 (index k: offsets s2off(k),
+// s3off(k)).
+template <int SMAX, bool NEG>
+__device__ __forceinline__ void count_outer(const uint8_t* lat, int a, uint32_t (&h)[kMaxS], uint32_t (&r2)[6],
+                                            uint32_t (&r3)[12])
+{
     if constexpr (SMAX >= 2) {
-        uint32_t q0 = h[1], q1 = 0u;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            const uint32_t c = lat[a + s2off(k)];
-            uint32_t& acc = (k & 1) ? q1 : q0;
-            acc += 1u << (c & 31);
-            keep(acc);
+            r2[k] = lat[a + s2off(k)];
+            count1<NEG>(h[1], r2[k]);
         }
-        h[1] = q0 + q1;
     }
     if constexpr (SMAX >= 3) {
-        uint32_t r0 = h[2], r1 = 0u, r2 = 0u;
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            const uint32_t c = lat[a + s3off(k)];
-            uint32_t& acc = (k % 3 == 0) ? r0 : ((k % 3 == 1) ? r1 : r2);
-            acc += 1u << (c & 31);
-            keep(acc);
+            r3[k] = lat[a + s3off(k)];
+            count1<NEG>(h[2], r3[k]);
         }
-        h[2] = r0 + r1 + r2;
     }
+}
+
+// First-shell offset (from the site) of neighbour e = ex + 2 ey + 4 ez.
+template <int SUB> __device__ __forceinline__ constexpr int s1off(int e)
+{
+    return s1base<SUB>() + (e & 1) + ((e >> 1) & 1) * kP + ((e >> 2) & 1) * kPP;
 }
 
 // acc + sum over shells s < SMAX and fields p < NF of field(s, p) * w[s*KMAX + p],
@@ -137,54 +133,127 @@ __device__ __forceinline__ uint32_t weigh(const uint32_t (&hi)[kMaxS], const uin
     return acc;
 }
 
+// Codes a trial hands to the next one (registers), so that the next trial
+// reads neither its own site, nor its partner, nor 7 of its 8 first
+// neighbours from LDS.  The next site is the other sublattice's site of the
+// lane's cell: after a corner trial at corner(x, y, z) the body trial at
+// body(x, y, z), whose first shell is corner(x + ex, y + ey, z + ez); after a
+// body trial at body(x, y, z) the corner trial of the next residue class
+// when that is corner(x + 1, y, z), whose first shell is body(x + ex,
+// y - 1 + ey, z - 1 + ez).  Of these 8 cells one is the trial's own site
+// (its new code), 6 are second or third neighbours of it that the trial
+// reads, and one more cell of its sublattice it loads for the next trial
+// (corner(x + 1, y + 1, z + 1), or body(x + 1, y - 1, z - 1)).  Nothing in
+// the trial's round changes those 7 (only sites of its residue class and
+// their partners, of the other sublattice, change).  The next site itself
+// is a first neighbour of the trial's site: only this lane's trial can have
+// swapped it.  Between the two trials no other lane changes any of these
+// cells (a lane's cells lie within one cell of its own sites, lanes are
+// three cells apart).
+struct Carry {
+    uint32_t s1[8];   // first-shell codes of the next site, index e = ex + 2 ey + 4 ez
+    uint32_t own;     // code of the next site
+};
 // One trial: site at LDS byte ai (sublattice SUB) with its 32-bit draw u.
 // The partner is the first neighbour whose x step is the top bit of u and
-// whose y and z steps (shared by the whole round) give yz = ey*kP + ez*kPP;
-// the acceptance draw is u << 1.  Adds the accepted energy change to the
-// lane's dEsum and the wave's accepted count to nacc (the same in every
-// lane); updates the LDS image in place.
-template <int KMAX, int SMAX, int SUB, int MODE>
-__device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int yz, bool valid,
+// whose y and z steps (shared by the whole round) give yz = ey*kP + ez*kPP
+// (eyz = 2 ey + 4 ez); the acceptance draw is u << 1.  CIN: the site's code
+// and its first shell come from the previous trial (cy); otherwise they are
+// loaded.  COUT: cy is set for the next trial.
+// Adds the accepted energy change to the lane's dEsum and the wave's
+// accepted count to nacc (the same in every lane); updates the LDS image in
+// place.
+template <int KMAX, int SMAX, int SUB, int MODE, bool CIN, bool COUT>
+__device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int yz, int eyz, bool valid,
                                       const int32_t* wtab, const double* tab, float ln2kT, int64_t& dEsum,
-                                      uint32_t& nacc)
+                                      uint32_t& nacc, Carry& cy)
 {
     constexpr int F = Field<KMAX>::F;
     constexpr bool DOT = MODE == kWtabDot;
+    // 5-bit fields (and the byte-dot form) hold bias + n_i - n_j without
+    // borrows: one packed difference per shell.  4-bit fields (KMAX = 8)
+    // count the two neighbourhoods apart.
+    constexpr bool DIFF = DOT || F == 5;
     const uint32_t u_acc = u << 1;
-    int e_lo, e_hi;
-    accept_bounds(u_acc, ln2kT, e_lo, e_hi);   // depends on the draw only: off the critical path
-    const int aj = ai + s1base<SUB>() + (int)(u >> 31) + yz;
-    const uint32_t ci = lat[ai];
-    const uint32_t cj = lat[aj];
+    float elo, ehi;
+    accept_edges(u_acc, ln2kT, elo, ehi);   // depends on the draw only: off the critical path
+    const uint32_t ex = u >> 31;
+    const int aj = ai + s1base<SUB>() + (int)ex + yz;
+
+    // the site, its first shell, and the partner (first-shell cell ex + eyz)
+    uint32_t s1[8];
+    uint32_t ci;
+    if constexpr (CIN) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s1[e] = cy.s1[e];
+        ci = cy.own;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s1[e] = lat[ai + s1off<SUB>(e)];
+        ci = lat[ai];
+    }
+    // Seven v_cndmask on the bits of e_j = ex + eyz.  (eyz is wave-uniform;
+    // held in a vector register, its selects stay in the trial's basic block
+    // instead of becoming branches, which would keep the loads below from
+    // being issued ahead.)
+    uint32_t e_j = (uint32_t)eyz;
+    asm volatile("" : "+v"(e_j));
+    e_j |= ex;
+    const uint32_t x0 = e_j & 1u ? s1[1] : s1[0], x1 = e_j & 1u ? s1[3] : s1[2];
+    const uint32_t x2 = e_j & 1u ? s1[5] : s1[4], x3 = e_j & 1u ? s1[7] : s1[6];
+    const uint32_t y0 = e_j & 2u ? x1 : x0, y1 = e_j & 2u ? x3 : x2;
+    const uint32_t cj = e_j & 4u ? y1 : y0;
+
+    // Row (a, b) of the weight planes, a = ci >> 5 and b = cj >> 5, at byte
+    // 4 (8a + b) of a plane.  (Lanes without a site in this round may decode
+    // stale halo bytes: their row still lies inside the planes, and their
+    // result is discarded.)
+    const uint32_t row4 = (ci & 0xe0u) + ((cj >> 5) << 2);
+    const int32_t* w = (const int32_t*)((const uint8_t*)wtab + row4);
 
     // Species histograms of both neighbourhoods (the partner is counted in
     // the first shell of i and i in that of j; the constant term undoes it).
+    // In the difference form j's chains subtract and are added to i's
+    // (fields then hold bias + n_i - n_j).
     uint32_t hi[kMaxS], hj[kMaxS];
     constexpr uint32_t bias = DOT ? 0x20202020u
                             : F == 5 ? 0x10u * (1u | 1u << 5 | 1u << 10 | 1u << 15 | 1u << 20 | 1u << 25) : 0u;
 #pragma unroll
     for (int s = 0; s < kMaxS; ++s) { hi[s] = bias; hj[s] = 0u; }
-    histogram<SMAX, SUB>(lat, ai, hi);
-    histogram<SMAX, 1 - SUB>(lat, aj, hj);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) count1<false>(hi[0], s1[e]);
+    uint32_t r2[6], r3[12], q2[6], q3[12];
+    count_outer<SMAX, false>(lat, ai, hi, r2, r3);
+    // the cell of this sublattice the next trial's first shell needs besides
+    // these: corner(x + 1, y + 1, z + 1) or body(x + 1, y - 1, z - 1)
+    const uint32_t fresh = COUT ? (uint32_t)lat[ai + (SUB == 0 ? 1 + kP + kPP : 1 - kP - kPP)] : 0u;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) count1<DIFF>(hj[0], lat[aj + s1off<1 - SUB>(e)]);
+    count_outer<SMAX, DIFF>(lat, aj, hj, q2, q3);
+    if constexpr (DIFF) {
+#pragma unroll
+        for (int s = 0; s < kMaxS; ++s) { hi[s] += hj[s]; hj[s] = 0u; }
+    }
 
-    // (lanes without a site in this round may decode stale halo bytes: their
-    // row still lies inside the planes, and their result is discarded)
-    const uint32_t a = decode(ci), b = decode(cj);
-    const int32_t* w = wtab + (a * KMAX + b);   // row (a, b) of the weight planes
     uint32_t acc;
     if constexpr (DOT) {
         // bytes 32 + n_i - n_j (bit 31, the last species, masked off) dotted
-        // with the three base-256 digits of the folded weights
+        // with the three base-256 digits of the folded weights, in one
+        // chain: ((A2 * 256 + A1) * 256 + constant) + A0
         constexpr int PS = kPlane;
-        int32_t A0 = w[3 * SMAX * PS], A1 = 0, A2 = 0;   // A0 starts at the row constant
+        int32_t d[kMaxS];
 #pragma unroll
-        for (int s = 0; s < SMAX; ++s) {
-            const int32_t d = (int32_t)((hi[s] - hj[s]) & 0x7fffffffu);
-            A0 = __builtin_amdgcn_sdot4(d, w[(3 * s + 0) * PS], A0, false);
-            A1 = __builtin_amdgcn_sdot4(d, w[(3 * s + 1) * PS], A1, false);
-            A2 = __builtin_amdgcn_sdot4(d, w[(3 * s + 2) * PS], A2, false);
-        }
-        acc = (uint32_t)A0 + ((uint32_t)A1 << 8) + ((uint32_t)A2 << 16);
+        for (int s = 0; s < SMAX; ++s) d[s] = (int32_t)(hi[s] & 0x7fffffffu);
+        int32_t X = 0;
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) X = __builtin_amdgcn_sdot4(d[s], w[(3 * s + 2) * PS], X, false);
+        X = (int32_t)((uint32_t)X << 8);
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) X = __builtin_amdgcn_sdot4(d[s], w[(3 * s + 1) * PS], X, false);
+        X = (int32_t)(((uint32_t)X << 8) + (uint32_t)w[3 * SMAX * PS]);
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) X = __builtin_amdgcn_sdot4(d[s], w[(3 * s + 0) * PS], X, false);
+        acc = (uint32_t)X;
     } else {
         // With kWtabDrop the rows fold in the last species, whose count
         // differences follow from the others (both sites have the same
@@ -196,10 +265,13 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int yz, 
 
     // Metropolis decision, Eq. (3): the exact test on the FP64 byte tables,
     // evaluated only when a lane's dE falls between its bounds (a
-    // wave-uniform branch, taken by a few percent of the rounds).
+    // wave-uniform branch, taken by a few percent of the rounds).  float(dE)
+    // is exact wherever `up` holds.
+    const float fdE = (float)dE;
     const bool up = (dE > 0) & (dE < (1 << 24));
-    const bool near = up & (((dE > e_lo) & (dE <= e_hi)) | (u_acc == 0u));
-    bool up_ok = up & (dE <= e_lo);
+    const bool sure = fdE <= elo;
+    const bool near = up & ((!sure & (fdE <= ehi)) | (u_acc == 0u));
+    bool up_ok = up & sure;
     if (__ballot(near)) {
         const int e = dE < 1 ? 1 : (dE > (1 << 24) - 1 ? (1 << 24) - 1 : dE);
         const uint8_t* tb = (const uint8_t*)tab;   // global memory (L2-resident)
@@ -211,10 +283,37 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int yz, 
     // Both bytes are stored by every lane (unchanged unless accepted): no
     // two lanes of a round touch the same byte, and a branch-free trial
     // keeps the whole round in one basic block for the scheduler.
-    lat[ai] = (uint8_t)(accept ? cj : ci);
+    const uint32_t ci_new = accept ? cj : ci;
+    lat[ai] = (uint8_t)ci_new;
     lat[aj] = (uint8_t)(accept ? ci : cj);
     dEsum += (int64_t)(accept ? dE : 0);
     nacc += (uint32_t)__popcll(__ballot(accept));   // wave-uniform: counted on the scalar unit
+
+    if constexpr (COUT) {
+        // the next site is first-shell cell kNext of this site; it changed
+        // iff it was the partner of an accepted swap
+        constexpr int kNext = SUB == 0 ? 7 : 1;
+        cy.own = accept && e_j == (uint32_t)kNext ? ci : s1[kNext];
+        if constexpr (SUB == 0) {   // next: body(x, y, z); its first shell corner(x + ex, y + ey, z + ez)
+            cy.s1[0] = ci_new;
+            cy.s1[1] = r2[0];   // +x
+            cy.s1[2] = r2[2];   // +y
+            cy.s1[3] = r3[0];   // +x +y
+            cy.s1[4] = r2[4];   // +z
+            cy.s1[5] = r3[4];   // +x +z
+            cy.s1[6] = r3[8];   // +y +z
+            cy.s1[7] = fresh;   // +x +y +z
+        } else {                    // next: corner(x + 1, y, z); its first shell body(x + ex, y - 1 + ey, z - 1 + ez)
+            cy.s1[0] = r3[11];  // -y -z
+            cy.s1[1] = fresh;   // +x -y -z
+            cy.s1[2] = r2[5];   // -z
+            cy.s1[3] = r3[5];   // +x -z
+            cy.s1[4] = r2[3];   // -y
+            cy.s1[5] = r3[1];   // +x -y
+            cy.s1[6] = ci_new;  // the site itself
+            cy.s1[7] = r2[0];   // +x
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -250,7 +349,7 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
     // Weight planes in LDS; the threshold tables of sweep s stay in global
     // memory (read only for the few draws whose decision needs them), which
     // leaves LDS for five workgroups per CU.
-    load_wplanes<KMAX, SMAX, kPlane>(s_w, D.wtab);
+    load_wplanes<KMAX, SMAX, kPlane, true>(s_w, D.wtab);
     __syncthreads();
     int ti = (int)(s - D.tab_s0);
     ti = ti < 0 ? 0 : (ti >= D.n_tabs ? D.n_tabs - 1 : ti);
@@ -302,56 +401,85 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
         }
         return encode4(v, F);
     };
+    // The same map as a byte table for v_perm_b32, code_hi:code_lo = codes
+    // of species 7..0 (species >= KMAX never occur: table byte 0).
+    uint32_t code_lo = 0u, code_hi = 0u;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const uint32_t c = v < KMAX ? encode((uint32_t)v) & 0xffu : 0u;
+        if (v < 4) code_lo |= c << (8 * v);
+        else code_hi |= c << (8 * (v - 4));
+    }
+    // v_perm_b32 reads at most one scalar operand: hold one word in a vector
+    // register for the whole staging rather than copying it there per row
+    asm volatile("" : "+v"(code_lo));
+
+    // A plane of the lattice (or the slab buffer) and its byte count from
+    // there to the end of the buffer: the resource of the plane's rows.
+    const uint64_t plane_bytes = 2ull * LxLy;
+    const uint64_t buf_bytes = plane_bytes * (uint64_t)(slab ? Lz + 4 : Lz);
+    const bool plane32 = plane_bytes < (1ull << 31);   // a row's byte offsets fit 31 bits
 
     // ---- stage block + halo: local cells -2..w+1 on each axis ----
     // Fast path (the block's x-range does not cross the periodic boundary):
-    // 8 lanes per row, each reading two cells (corner, body, corner, body
-    // bytes) from the dword at byte `at & ~3` and the one at `(at + 2) & ~3`
-    // (the same dword when the cells start on a dword boundary; rows of an
-    // odd-length lattice alternate).  All 32 rows of a lane are loaded
-    // before any is written to LDS, so the loads are in flight together.
-    // Lanes and rows outside the halo load a clamped in-range address and
-    // store nothing.  The lattice base is 4-byte aligned.
-    if (gx0 >= 3 && gx0 + wx + 4 <= Lx) {
-        const int lx0 = 2 * (lane & 7) - 2;       // cells lx0, lx0 + 1
-        const bool lane_ok = lx0 <= wx + 1;
-        const bool c0 = lx0 >= -1, c1 = lx0 + 1 <= wx + 1, b0 = lx0 <= wx, b1 = lx0 + 1 <= wx;
-        const int lxa = lane_ok ? lx0 : -2;        // an in-range address for every lane
-        // row r = (lane >> 3) + 8 it: ly = (lane >> 3) - 2 + 8 (it & 1), lz = (it >> 1) - 2
-        uint32_t gyrow[2];
+    // 8 lanes per row, each taking cells lx0, lx0 + 1 (lx0 = 2 (lane & 7) - 2),
+    // i.e. the bytes corner, body, corner, body at byte `at` of the row; it
+    // loads the aligned dwords at `at & ~3` and 4 bytes on and aligns them.
+    // Lane row lr = lane >> 3 takes rows ly = lr - 2 + 8 h (h = 0, 1) of each
+    // plane lz = -2 .. 13.  Per lane, the in-plane byte offsets and LDS
+    // positions of its two rows are set up once; a row adds only its plane,
+    // which is wave-uniform (the buffer resource's base, scalar registers).
+    // All 16 loads of a batch are issued before any LDS write.  Rows, planes
+    // and cells past the halo (w < 12) load an in-range cell and write it to
+    // image positions past w + 1, which no trial with a site and no
+    // write-back reads; only positions outside the 15^3 arrays (corner -2,
+    // body 13) are not written.  Every load stays inside the row's plane.
+    if (plane32 && gx0 >= 3 && gx0 + wx + 4 <= Lx) {
+        const int c8 = lane & 7, lr = lane >> 3;
+        const int lx0 = 2 * c8 - 2;
+        const int lxa = lx0 <= wx + 1 ? lx0 : -2;   // cells the lane loads
+        uint32_t yoff[2];
+        int cl[2];
+        bool mc0[2], mc1[2], mb0[2], mb1[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int ly = min((lane >> 3) - 2 + 8 * h, wy + 1);
-            gyrow[h] = (uint32_t)wrap_add(gy0 + ly, Ly);
+            const int ly = lr - 2 + 8 * h;
+            const uint32_t gy = (uint32_t)wrap_add(gy0 + min(ly, wy + 1), Ly);
+            yoff[h] = 2u * (gy * (uint32_t)Lx + (uint32_t)(gx0 + lxa));
+            cl[h] = (ly + 1) * kP + (lx0 + 1);      // corner(lx0, ly, -1), less a plane
+            mc0[h] = ly >= -1 && c8 >= 1;
+            mc1[h] = ly >= -1;
+            mb0[h] = ly <= 12;
+            mb1[h] = ly <= 12 && c8 <= 6;
         }
 #pragma unroll
         for (int it0 = 0; it0 < 32; it0 += kStageBatch) {
-            uint32_t q0[kStageBatch], q1[kStageBatch], al[kStageBatch];
+            uint32_t v[kStageBatch];
 #pragma unroll
             for (int u = 0; u < kStageBatch; ++u) {
-                const int it = it0 + u;
-                const int lz = min((it >> 1) - 2, wz + 1);
-                const uint32_t gz = (uint32_t)zplane(lz), gy = gyrow[it & 1];
-                const size_t row = narrow ? (size_t)(__umul24(gz, LxLy) + __umul24(gy, (uint32_t)Lx))
-                                          : ((size_t)gz * (uint32_t)Ly + gy) * (uint32_t)Lx;
-                const size_t at = 2 * (row + (size_t)(gx0 + lxa));     // byte of corner(lxa)
-                q0[u] = gload<uint32_t>(g + (at & ~(size_t)3));
-                q1[u] = gload<uint32_t>(g + ((at + 2) & ~(size_t)3));
-                al[u] = (uint32_t)at & 2u;
+                const int it = it0 + u, h = it & 1, lz = (it >> 1) - 2;
+                const uint64_t zb = plane_bytes * (uint32_t)zplane(min(lz, wz + 1));
+                const uint64_t base = zb & ~(uint64_t)3;
+                const __amdgpu_buffer_rsrc_t r = byte_rsrc(g + base, buf_bytes - base);
+                const uint32_t at = yoff[h] + ((uint32_t)zb & 2u);
+                const uint32_t A = at & ~3u;
+                v[u] = __builtin_amdgcn_perm(code_hi, code_lo,
+                                             __builtin_amdgcn_alignbyte(bload32(r, A + 4), bload32(r, A), at));
             }
 #pragma unroll
             for (int u = 0; u < kStageBatch; ++u) {
-                const int it = it0 + u;
-                const int ly = (lane >> 3) - 2 + 8 * (it & 1), lz = (it >> 1) - 2;
-                if (!lane_ok || ly > wy + 1 || lz > wz + 1) continue;
-                const uint32_t v = encode(__builtin_amdgcn_alignbyte(q1[u], q0[u], al[u]));
-                const int crow = (lz + 1) * kPP + (ly + 1) * kP + (lx0 + 1);
-                const int brow = kArr + (lz + 2) * kPP + (ly + 2) * kP + (lx0 + 2);
-                const bool cy = ly >= -1 && lz >= -1, by = ly <= wy && lz <= wz;
-                if (cy && c0) lat[crow] = (uint8_t)v;
-                if (cy && c1) lat[crow + 1] = (uint8_t)(v >> 16);
-                if (by && b0) lat[brow] = (uint8_t)(v >> 8);
-                if (by && b1) lat[brow + 1] = (uint8_t)(v >> 24);
+                const int it = it0 + u, h = it & 1, lz = (it >> 1) - 2;
+                uint8_t* p = lat + cl[h] + (lz + 1) * kPP;   // corner(lx0, ly, lz)
+                uint8_t* q = p + (kArr + kPP + kP + 1);      // body(lx0, ly, lz)
+                const uint32_t w8 = v[u] >> 8;
+                if (lz >= -1) {
+                    if (mc0[h]) p[0] = (uint8_t)v[u];
+                    if (mc1[h]) p[1] = (uint8_t)(v[u] >> 16);
+                }
+                if (lz <= 12) {
+                    if (mb0[h]) q[0] = (uint8_t)w8;
+                    if (mb1[h]) q[1] = (uint8_t)(w8 >> 16);
+                }
             }
         }
     } else {
@@ -434,15 +562,27 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
         constexpr int MODE = decltype(mode_tag)::value;
         // rounds of residue class m (corner then body) with draws uc, ub and
         // the four partner bits of sub-colours 2m, 2m+1 in b4
+        // Carries (three shells only: they hand on second and third
+        // neighbours): corner -> body of every class, and body -> corner of
+        // the next class when that is one cell on in x (rx = 1, 2).
+        constexpr bool CARRY = SMAX == 3;
+        Carry cy;
         auto rounds = [&](int m, uint32_t uc, uint32_t ub, uint32_t b4) {
             const int rx = m % 3, ry = (m / 3) % 3, rz = m / 9;
             const bool valid = (3 * ix < wx - rx) & (3 * iy < wy - ry) & (3 * iz < wz - rz);
             const int ac = lane_c + (rz * kPP + ry * kP + rx);
             const int yz0 = (int)(b4 & 1u) * kP + (int)((b4 >> 1) & 1u) * kPP;
             const int yz1 = (int)((b4 >> 2) & 1u) * kP + (int)((b4 >> 3) & 1u) * kPP;
-            trial<KMAX, SMAX, 0, MODE>(lat, ac, uc, yz0, valid, s_w, g_tab, ln2kT, dEsum, nacc);
+            const int eyz0 = (int)(b4 & 3u) * 2, eyz1 = (int)((b4 >> 2) & 3u) * 2;
+            if (CARRY && rx != 0)   // wave-uniform
+                trial<KMAX, SMAX, 0, MODE, CARRY, CARRY>(lat, ac, uc, yz0, eyz0, valid, s_w, g_tab, ln2kT, dEsum,
+                                                         nacc, cy);
+            else
+                trial<KMAX, SMAX, 0, MODE, false, CARRY>(lat, ac, uc, yz0, eyz0, valid, s_w, g_tab, ln2kT, dEsum,
+                                                         nacc, cy);
             __builtin_amdgcn_wave_barrier();
-            trial<KMAX, SMAX, 1, MODE>(lat, ac + kBodyFromCorner, ub, yz1, valid, s_w, g_tab, ln2kT, dEsum, nacc);
+            trial<KMAX, SMAX, 1, MODE, CARRY, CARRY>(lat, ac + kBodyFromCorner, ub, yz1, eyz1, valid, s_w, g_tab,
+                                                     ln2kT, dEsum, nacc, cy);
             __builtin_amdgcn_wave_barrier();
         };
         uint32_t w[4] = {base_lo, base_hi, s, (uint32_t)colour};
@@ -472,79 +612,49 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
             all_rounds(std::integral_constant<int, kWtabFull>{});
     }
 
-    // ---- write back: corner cells 0..w, body cells -1..w-1 ----
-    // Fast path (no periodic wrap along x): 8 lanes per row, each owning one
-    // aligned dword of the row's span (corner(-1) .. body(w)); it stores the
-    // dword whole, or only its bytes that belong to the corner box [0, w]^3
-    // or the body box [-1, w-1]^3 where the span or a box ends.  Lane
-    // (lrow, c) = (lane >> 3, lane & 7) takes rows ly = lrow - 1 + 8h
-    // (h = 0, 1), lz = -1 .. w.  The cells its dword holds depend only on
-    // the parity p of the row's first cell index in the lattice: cells lxa
-    // and lxa + 1, lxa = 2c - 2 + p.  The per-lane x and y parts (store
-    // masks, LDS offsets, lattice offsets) are set up once; a row adds its
-    // wave-uniform z part.  Rows go in batches of four: the 16 LDS reads of
-    // a batch are issued before any is used.  Rows and cells outside the
-    // boxes read in-image LDS bytes and store nothing.
-    if (gx0 >= 1 && gx0 + wx < Lx) {
-        const int lrow = lane >> 3, c8 = lane & 7;
-        uint32_t xm2 = 0u;                           // store masks for p = 0 (bits 0-3) and 1 (bits 4-7)
+    // ---- write back ----
+    // A trial changes only corner cells 0..w and body cells -1..w-1 of the
+    // block (its sites and their first neighbours).  Fast path (no periodic
+    // wrap along x): every cell of the box -1..w on each axis is written
+    // whole (corner and body byte, one 16-bit store), the cells no trial
+    // could change with the value staged from them.  That is the value they
+    // still hold: no block of the same colour changes them (same-colour
+    // blocks are one block of width >= 2 apart along some axis, and their
+    // changes reach one cell beyond their own cells), and the cells of the
+    // box are distinct (L >= w + 2 on each axis: at least 2 blocks of width
+    // >= 2).  16 lanes per row (lx = (lane & 15) - 1) and 4 rows per
+    // instruction: lane row lys = lane >> 4 takes rows ly = 4 yg + lys - 1
+    // (yg = 0..3) of each plane lz = -1..w.  Per lane, the in-plane byte
+    // offsets and LDS positions of its four rows are set up once; lanes past
+    // the box read a clamped in-image cell and store nothing.
+    if (plane32 && gx0 >= 1 && gx0 + wx < Lx) {
+        const int lx = (lane & 15) - 1, lys = lane >> 4;
+        const int lxc = min(lx, wx);
+        uint32_t yo[4];
+        int cw[4];
+        bool ok[4];
 #pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            const int lxa = 2 * c8 - 2 + p;
-            xm2 |= ((uint32_t)(lxa >= 0 && lxa <= wx)               // corner(lxa)
-                  | (uint32_t)(lxa >= -1 && lxa < wx) << 1         // body(lxa)
-                  | (uint32_t)(lxa + 1 >= 0 && lxa + 1 <= wx) << 2 // corner(lxa + 1)
-                  | (uint32_t)(lxa + 1 < wx) << 3) << (4 * p);     // body(lxa + 1)
+        for (int yg = 0; yg < 4; ++yg) {
+            const int ly = 4 * yg + lys - 1, lyc = min(ly, wy);
+            ok[yg] = lx <= wx && ly <= wy;
+            const uint32_t gy = (uint32_t)wrap_add(gy0 + lyc, Ly);
+            yo[yg] = 2u * (gy * (uint32_t)Lx + (uint32_t)(gx0 + lxc));
+            cw[yg] = (lyc + 1) * kP + (lxc + 1);   // corner(lxc, lyc, -1), less a plane
         }
-        // corner byte of cell lxa sits at x offset max(lxa, -1) + 1 (lxa = -2
-        // only for c = 0, p = 0, and that byte is never stored), body at lxa + 2
-        const int cx0 = max(2 * c8 - 2, -1) + 1, cxp = c8 > 0 ? 1 : 0, bx0 = 2 * c8;
-        uint32_t ym[2], ypar[2];
-        int ylds[2];
-        uint64_t yb[2];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int ly = lrow - 1 + 8 * h, lyc = min(ly, wy);
-            ym[h] = (ly >= 0 && ly <= wy ? 5u : 0u) | (ly < wy ? 10u : 0u);
-            const uint64_t yrow = (uint64_t)(uint32_t)wrap_add(gy0 + lyc, Ly) * (uint32_t)Lx + (uint32_t)gx0;
-            ypar[h] = (uint32_t)yrow & 1u;
-            yb[h] = 2 * yrow + 4u * (uint32_t)c8 - 4u;   // byte of this lane's dword, less the z part and 2p
-            ylds[h] = (lyc + 1) * kP;
-        }
-        const int nit = 2 * (wz + 2);               // rows with lz <= wz
-        for (int it0 = 0; it0 < nit; it0 += 4) {
-            uint32_t e[4][4];
-            uint8_t* dst[4];
-            uint32_t msk[4];
+        for (int lz = -1; lz <= kMaxBlock; ++lz) {
+            if (lz > wz) continue;   // (wave-uniform)
+            const uint64_t zb = plane_bytes * (uint32_t)zplane(lz);
+            const __amdgpu_buffer_rsrc_t r = byte_rsrc(g + zb, buf_bytes - zb);
+            uint32_t e[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int h = u & 1, lz = ((it0 + u) >> 1) - 1, lzc = min(lz, wz);
-                const uint32_t zm = (lz >= 0 && lz <= wz ? 5u : 0u) | (lz < wz ? 10u : 0u);
-                const uint64_t zrow = (uint64_t)(uint32_t)zplane(lzc) * ((uint64_t)Lx * (uint32_t)Ly);
-                const uint32_t pp = ypar[h] ^ ((uint32_t)zrow & 1u);
-                msk[u] = (xm2 >> (4 * pp)) & ym[h] & zm;
-                const int crow = (lzc + 1) * kPP + ylds[h] + cx0 + (int)(pp & (uint32_t)cxp);
-                const int brow = kArr + (lzc + 2) * kPP + kP + ylds[h] + bx0 + (int)pp;
-                e[u][0] = lat[crow];
-                e[u][1] = lat[brow];
-                e[u][2] = lat[crow + 1];
-                e[u][3] = lat[brow + 1];
-                dst[u] = g + (2 * zrow + yb[h] + 2 * pp);
+            for (int yg = 0; yg < 4; ++yg) {
+                const uint8_t* p = lat + cw[yg] + (lz + 1) * kPP;   // corner(lxc, lyc, lz)
+                e[yg] = (uint32_t)p[0] | (uint32_t)p[kArr + kPP + kP + 1] << 8;
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint32_t m = msk[u];
-                if (!m) continue;
-                uint8_t* q = dst[u];
-                if (m == 15u) {
-                    gstore<uint32_t>(q, decode(e[u][0]) | decode(e[u][1]) << 8 | decode(e[u][2]) << 16 |
-                                            decode(e[u][3]) << 24);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        if (m >> k & 1u) gstore<uint8_t>(q + k, (uint8_t)decode(e[u][k]));
-                }
-            }
+            for (int yg = 0; yg < 4; ++yg)
+                if (ok[yg]) bstore16(r, yo[yg], (e[yg] >> 5) & 0x0707u);
         }
     } else {
         // a periodic wrap along x: one cell (two bytes) per lane, rows
@@ -719,9 +829,11 @@ hipError_t launch_accept_bounds(const double* d_tab, const uint32_t* d_u, int n,
 
 // Exhaustive check of the acceptance bounds over every 32-bit draw u (the
 // BCC draws are the even ones, the FCC draws all of them).  For each u the
-// kernel takes (lo, hi) as the sweep kernels do and evaluates the exact
-// test of Eq. (3) on the FP64 table products at dE = lo, lo - 1 (must
-// accept) and hi + 1, hi + 2 (must reject), for those dE in (0, 2^24).
+// kernel forms the edges as the sweep kernels do; the largest dE they accept
+// without the table is lo = floor(elo) and the smallest they reject without
+// it is hi + 1, hi = floor(ehi).  It evaluates the exact test of Eq. (3) on
+// the FP64 table products at dE = lo, lo - 1 (must accept) and hi + 1,
+// hi + 2 (must reject), for those dE in (0, 2^24).
 // out[0] counts draws violating the lower bound, out[1] the upper bound,
 // out[2] holds the largest |(32 - log2 float(u)) - (32 - log2 u)| as the
 // bits of a non-negative double (u > 0), out[3] the widest band hi - lo.
@@ -738,8 +850,9 @@ __global__ __launch_bounds__(256) void accept_bounds_check_kernel(const double* 
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < (1ull << 32); v += stride) {
         const uint32_t u = (uint32_t)v;
-        int lo, hi;
-        accept_bounds(u, c, lo, hi);
+        float elo, ehi;
+        accept_edges(u, c, elo, ehi);
+        const int lo = (int)fminf(floorf(elo), 1.0e9f), hi = (int)fminf(floorf(ehi), 1.0e9f);
         max_band = max(max_band, hi - lo);
         if (u == 0u) continue;   // the kernels always consult the table for u = 0
         const double du = (double)u;

@@ -28,9 +28,8 @@ constexpr int kMaxS = 3;
 constexpr int kP = 15;               // row pitch (cells)
 constexpr int kPP = 231;             // plane pitch (15 rows + 6 bytes of padding)
 constexpr int kArr = 3460;           // bytes per sublattice array (last byte 14*231 + 14*15 + 14)
-// Bytes per wave: the two arrays and 4 bytes of slack, which the write-back
-// of the last row may read past the body array (a byte it never stores).
-constexpr int kWaveLds = 2 * kArr + 4;
+// Bytes per wave: the two arrays.
+constexpr int kWaveLds = 2 * kArr;
 static_assert(kPP >= 15 * kP && kArr > 14 * kPP + 14 * kP + 14, "LDS array too small");
 
 // Threshold tables: T0 | T1 | T2, 256 doubles each, then ln(2) k_B T in
