@@ -37,11 +37,12 @@
  *   m = ((l_z%3)*3 + l_y%3)*3 + l_x%3 (sub-colour q = 2m + b) takes the
  *   32-bit word w = word 2*(m & 1) + b of Philox4x32-10(key, (g & 0xffffffff,
  *   g >> 32, s, c + 256*(m >> 1))), g = the cell at local coordinates
- *   3*floor(l/3) of the same block.  Its partner is the first neighbour
- *   with +a/2 along x iff bit 31 of w is set, along y iff bit 2q and along
- *   z iff bit 2q+1 of R is set (-a/2 otherwise), R = the 128 bits of
- *   Philox4x32-10(key, (0, 0, s, 32 + c)) (bit t = bit t%32 of word t/32);
- *   its acceptance draw is u = w << 1 (mod 2^32).
+ *   3*floor(l/3) of the same block, as its acceptance draw u.  The partner
+ *   of every trial of one (sweep, colour, sub-colour q) set is the first
+ *   neighbour with +a/2 along x iff bit q of X is set, along y iff bit 2q
+ *   and along z iff bit 2q+1 of R is set (-a/2 otherwise), X and R the 128
+ *   bits of Philox4x32-10(key, (0, 0, s, 40 + c)) and of
+ *   Philox4x32-10(key, (0, 0, s, 32 + c)) (bit t = bit t%32 of word t/32).
  *   FCC: site b of a cell takes u = word b of Philox4x32-10(key, (cell &
  *   0xffffffff, cell >> 32, s, c)) as its acceptance draw.  The partner of
  *   every trial of one (sweep, colour, sub-colour q) set is drawn once from
@@ -344,8 +345,8 @@ smcx_status smcx_device_thresholds(double T_kelvin, const int32_t* dE, int32_t n
 smcx_status smcx_device_accept_bounds(double T_kelvin, const uint32_t* u, int32_t n, int32_t* lo, int32_t* hi);
 smcx_status smcx_device_philox(const uint32_t* ctr, const uint32_t key[2], int32_t n, uint32_t* out);
 /* smcx_device_check_accept_bounds: the claim above, checked on the device
- * for every 32-bit draw u at temperature T (the BCC draws are the even ones,
- * the FCC draws all of them): violations_lo counts draws whose bound lo or
+ * for every 32-bit draw u at temperature T (the acceptance draws of both
+ * lattices are whole 32-bit words): violations_lo counts draws whose bound lo or
  * lo - 1 (where in (0, 2^24)) fails the table test, violations_hi those
  * whose hi + 1 or hi + 2 passes it; max_log2_error receives the largest
  * |(32 - log2 float(u)) - (32 - log2 u)| of the device's FP32 logarithm over

@@ -439,20 +439,21 @@ void or_schedule(int lat, const int32_t L[3], const int32_t B[3], uint64_t seed,
  *   (sub-colour q = 2m + b) takes the 32-bit word 2*(m & 1) + b of
  *   Philox4x32-10(key = seed, counter = (g lo, g hi, s, c + 256*(m >> 1))),
  *   g = the cell's base cell (see schedule_full): one call serves the four
- *   trials of residues 2k and 2k+1 of one base cell.
- *   Partner: first-neighbour vector number dir (bit a set = +1 on axis a).
- *   Bit 0 (x) is the word's top bit; bits 1 (y) and 2 (z) are shared by all
- *   trials of one (sweep, colour, sub-colour) set: bits 2q and 2q+1 of the
- *   128-bit string R_c = Philox4x32-10(key, (0, 0, s, 32 + c)), bit t being
- *   bit t%32 of word t/32.  Every trial still proposes the swap of one
- *   fixed pair, chosen without looking at the configuration, so each trial
- *   is a Metropolis step reversible with respect to Eq. (1); over the set
- *   draw and the word, dir is uniform on 0..7.
- *   Acceptance draw: the word shifted left by one (its low 31 bits, times
- *   two), compared as in or_accept. */
+ *   trials of residues 2k and 2k+1 of one base cell.  The word is the
+ *   trial's acceptance draw, compared as in or_accept.
+ *   Partner: first-neighbour vector number dir (bit a set = +1 on axis a),
+ *   shared by all trials of one (sweep, colour, sub-colour) set, as for
+ *   FCC: bit 0 (x) is bit q of the 128-bit string X_c =
+ *   Philox4x32-10(key, (0, 0, s, 40 + c)); bits 1 (y) and 2 (z) are bits 2q
+ *   and 2q+1 of R_c = Philox4x32-10(key, (0, 0, s, 32 + c)), bit t of a
+ *   string being bit t%32 of word t/32.  Every trial still proposes the
+ *   swap of one fixed pair, chosen without looking at the configuration, so
+ *   each trial is a Metropolis step reversible with respect to Eq. (1); over
+ *   the set draws dir is uniform on 0..7. */
 static int set_bit(const uint32_t R[4], int t) { return (int)((R[t >> 5] >> (t & 31)) & 1u); }
 
-static void bcc_draw(const uint32_t key[2], uint32_t s, int c, int q, int64_t g, const uint32_t R[4],
+/* R: R_c (words 0..3) and X_c (words 4..7) of the trial's colour */
+static void bcc_draw(const uint32_t key[2], uint32_t s, int c, int q, int64_t g, const uint32_t R[8],
                      uint32_t ctr[4], int* word, int* dir, uint32_t* u_acc)
 {
     int m = q >> 1, b = q & 1;
@@ -463,15 +464,16 @@ static void bcc_draw(const uint32_t key[2], uint32_t s, int c, int q, int64_t g,
     uint32_t r[4];
     or_philox4x32_10(ctr, key, r);
     *word = 2 * (m & 1) + b;
-    uint32_t u = r[*word];
-    *dir = (int)(u >> 31) | set_bit(R, 2 * q) << 1 | set_bit(R, 2 * q + 1) << 2;
-    *u_acc = u << 1;
+    *dir = set_bit(R + 4, q) | set_bit(R, 2 * q) << 1 | set_bit(R, 2 * q + 1) << 2;
+    *u_acc = r[*word];
 }
 
-static void bcc_set_bits(const uint32_t key[2], uint32_t s, int c, uint32_t R[4])
+static void bcc_set_bits(const uint32_t key[2], uint32_t s, int c, uint32_t R[8])
 {
     uint32_t ctr[4] = {0u, 0u, s, 32u + (uint32_t)c};
     or_philox4x32_10(ctr, key, R);
+    uint32_t cx[4] = {0u, 0u, s, 40u + (uint32_t)c};
+    or_philox4x32_10(cx, key, R + 4);
 }
 
 int or_bcc_draws(const int32_t L[3], const int32_t B[3], uint64_t seed, uint32_t s, uint32_t* ctr,
@@ -484,7 +486,7 @@ int or_bcc_draws(const int32_t L[3], const int32_t B[3], uint64_t seed, uint32_t
     uint8_t* sub = (uint8_t*)malloc(N);
     int64_t* base = (int64_t*)malloc(sizeof(int64_t) * ncell);
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
-    uint32_t R[8][4];
+    uint32_t R[8][8];
     schedule_full(0, L, B, seed, s, colour, sub, NULL, base);
     for (int c = 0; c < 8; ++c) bcc_set_bits(key, s, c, R[c]);
     for (int64_t i = 0; i < N; ++i) {
@@ -595,7 +597,7 @@ int or_sweep(int lat, const int32_t L[3], const int32_t B[3], int S, int K, cons
     uint8_t* sub = (uint8_t*)malloc(N);
     int64_t* base = lat == 0 ? (int64_t*)malloc(sizeof(int64_t) * (N / 2)) : NULL;
     int64_t* order = (int64_t*)malloc(sizeof(int64_t) * N);
-    uint32_t R[8][4];
+    uint32_t R[8][8];
     int64_t start[8 * 27 * 4 + 1];
     int partner_sub[8 * 27 * 4];
     uint32_t partner_signs[8 * 27 * 4];

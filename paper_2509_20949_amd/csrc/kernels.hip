@@ -154,17 +154,16 @@ struct Carry {
     uint32_t s1[8];   // first-shell codes of the next site, index e = ex + 2 ey + 4 ez
     uint32_t own;     // code of the next site
 };
-// One trial: site at LDS byte ai (sublattice SUB) with its 32-bit draw u.
-// The partner is the first neighbour whose x step is the top bit of u and
-// whose y and z steps (shared by the whole round) give yz = ey*kP + ez*kPP
-// (eyz = 2 ey + 4 ez); the acceptance draw is u << 1.  CIN: the site's code
-// and its first shell come from the previous trial (cy); otherwise they are
-// loaded.  COUT: cy is set for the next trial.
+// One trial: site at LDS byte ai (sublattice SUB) with its 32-bit
+// acceptance draw u.  The partner is first-shell neighbour e = ex + 2 ey +
+// 4 ez, the direction shared by the whole round (wave-uniform).  CIN: the
+// site's code and its first shell come from the previous trial (cy);
+// otherwise they are loaded.  COUT: cy is set for the next trial.
 // Adds the accepted energy change to the lane's dEsum and the wave's
 // accepted count to nacc (the same in every lane); updates the LDS image in
 // place.
 template <int KMAX, int SMAX, int SUB, int MODE, bool CIN, bool COUT>
-__device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int yz, int eyz, bool valid,
+__device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int e, bool valid,
                                       const int32_t* wtab, const double* tab, float ln2kT, int64_t& dEsum,
                                       uint32_t& nacc, Carry& cy)
 {
@@ -174,13 +173,12 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int yz, 
     // borrows: one packed difference per shell.  4-bit fields (KMAX = 8)
     // count the two neighbourhoods apart.
     constexpr bool DIFF = DOT || F == 5;
-    const uint32_t u_acc = u << 1;
+    const uint32_t u_acc = u;
     float elo, ehi;
     accept_edges(u_acc, ln2kT, elo, ehi);   // depends on the draw only: off the critical path
-    const uint32_t ex = u >> 31;
-    const int aj = ai + s1base<SUB>() + (int)ex + yz;
+    const int aj = ai + s1base<SUB>() + (e & 1) + ((e >> 1) & 1) * kP + ((e >> 2) & 1) * kPP;
 
-    // the site, its first shell, and the partner (first-shell cell ex + eyz)
+    // the site, its first shell, and the partner (first-shell cell e)
     uint32_t s1[8];
     uint32_t ci;
     if constexpr (CIN) {
@@ -192,13 +190,12 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int yz, 
         for (int e = 0; e < 8; ++e) s1[e] = lat[ai + s1off<SUB>(e)];
         ci = lat[ai];
     }
-    // Seven v_cndmask on the bits of e_j = ex + eyz.  (eyz is wave-uniform;
-    // held in a vector register, its selects stay in the trial's basic block
-    // instead of becoming branches, which would keep the loads below from
-    // being issued ahead.)
-    uint32_t e_j = (uint32_t)eyz;
+    // Seven v_cndmask on the bits of e.  (e is wave-uniform; held in a
+    // vector register, its selects stay in the trial's basic block instead
+    // of becoming branches, which would keep the loads below from being
+    // issued ahead.)
+    uint32_t e_j = (uint32_t)e;
     asm volatile("" : "+v"(e_j));
-    e_j |= ex;
     const uint32_t x0 = e_j & 1u ? s1[1] : s1[0], x1 = e_j & 1u ? s1[3] : s1[2];
     const uint32_t x2 = e_j & 1u ? s1[5] : s1[4], x3 = e_j & 1u ? s1[7] : s1[6];
     const uint32_t y0 = e_j & 2u ? x1 : x0, y1 = e_j & 2u ? x3 : x2;
@@ -518,12 +515,13 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
     // ---- 27 residue classes x 2 sublattices = 54 rounds ----
     // Lane (ix, iy, iz) takes local cell (rx + 3 ix, ry + 3 iy, rz + 3 iz) of
     // residue class m = (rz*3 + ry)*3 + rx; lanes past the block edge only
-    // compute.  Random words: one Philox call per lane and residue pair
+    // compute.  Acceptance draws: one Philox call per lane and residue pair
     // (2k, 2k+1), counter (base cell, s, colour + 256 k), the base cell being
     // the lane's cell of class 0; class 2k takes words 0 (corner) and 1
-    // (body), class 2k+1 words 2 and 3.  The y and z steps of every partner
-    // of sub-colour q = 2m + b are bits 2q and 2q+1 of one Philox call
-    // (0, 0, s, 32 + colour), the same for all blocks of the colour.
+    // (body), class 2k+1 words 2 and 3.  The partner direction of sub-colour
+    // q = 2m + b, the same for all blocks of the colour: x step bit q of the
+    // Philox call (0, 0, s, 40 + colour), y and z steps bits 2q and 2q+1 of
+    // the call (0, 0, s, 32 + colour).
     int ix, iy, iz;
     lane_cell(lane, ix, iy, iz);
     const int lane_c = (3 * iz + 1) * kPP + (3 * iy + 1) * kP + (3 * ix + 1);
@@ -542,7 +540,7 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
         base_lo = (uint32_t)cell;
         base_hi = (uint32_t)(cell >> 32);
     }
-    uint64_t yz_lo, yz_hi;   // the 128 partner bits, wave-uniform
+    uint64_t yz_lo, yz_hi, x_bits;   // partner steps, wave-uniform
     {
         uint32_t R[4] = {0u, 0u, s, 32u + (uint32_t)colour};
         philox4x32_10(R, k0, k1);
@@ -551,6 +549,10 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
                 (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(R[1]) << 32;
         yz_hi = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(R[2]) |
                 (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(R[3]) << 32;
+        uint32_t X[4] = {0u, 0u, s, 40u + (uint32_t)colour};
+        philox4x32_10(X, k0, k1);
+        x_bits = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(X[0]) |
+                 (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(X[1]) << 32;
     }
     int64_t dEsum = 0;
     uint32_t nacc = 0;
@@ -560,8 +562,9 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
     // each instance stays branch-free.
     auto all_rounds = [&](auto mode_tag) {
         constexpr int MODE = decltype(mode_tag)::value;
-        // rounds of residue class m (corner then body) with draws uc, ub and
-        // the four partner bits of sub-colours 2m, 2m+1 in b4
+        // rounds of residue class m (corner then body) with draws uc, ub, the
+        // y/z steps of sub-colours 2m, 2m+1 in b4 (bits 0-1, 2-3) and their x
+        // steps in bits 2m, 2m+1 of x_bits
         // Carries (three shells only: they hand on second and third
         // neighbours): corner -> body of every class, and body -> corner of
         // the next class when that is one cell on in x (rx = 1, 2).
@@ -571,18 +574,16 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
             const int rx = m % 3, ry = (m / 3) % 3, rz = m / 9;
             const bool valid = (3 * ix < wx - rx) & (3 * iy < wy - ry) & (3 * iz < wz - rz);
             const int ac = lane_c + (rz * kPP + ry * kP + rx);
-            const int yz0 = (int)(b4 & 1u) * kP + (int)((b4 >> 1) & 1u) * kPP;
-            const int yz1 = (int)((b4 >> 2) & 1u) * kP + (int)((b4 >> 3) & 1u) * kPP;
-            const int eyz0 = (int)(b4 & 3u) * 2, eyz1 = (int)((b4 >> 2) & 3u) * 2;
+            const uint32_t xb = (uint32_t)(x_bits >> (2 * m));
+            const int e0 = (int)(xb & 1u) | (int)(b4 & 3u) << 1;
+            const int e1 = (int)((xb >> 1) & 1u) | (int)((b4 >> 2) & 3u) << 1;
             if (CARRY && rx != 0)   // wave-uniform
-                trial<KMAX, SMAX, 0, MODE, CARRY, CARRY>(lat, ac, uc, yz0, eyz0, valid, s_w, g_tab, ln2kT, dEsum,
-                                                         nacc, cy);
+                trial<KMAX, SMAX, 0, MODE, CARRY, CARRY>(lat, ac, uc, e0, valid, s_w, g_tab, ln2kT, dEsum, nacc, cy);
             else
-                trial<KMAX, SMAX, 0, MODE, false, CARRY>(lat, ac, uc, yz0, eyz0, valid, s_w, g_tab, ln2kT, dEsum,
-                                                         nacc, cy);
+                trial<KMAX, SMAX, 0, MODE, false, CARRY>(lat, ac, uc, e0, valid, s_w, g_tab, ln2kT, dEsum, nacc, cy);
             __builtin_amdgcn_wave_barrier();
-            trial<KMAX, SMAX, 1, MODE, CARRY, CARRY>(lat, ac + kBodyFromCorner, ub, yz1, eyz1, valid, s_w, g_tab,
-                                                     ln2kT, dEsum, nacc, cy);
+            trial<KMAX, SMAX, 1, MODE, CARRY, CARRY>(lat, ac + kBodyFromCorner, ub, e1, valid, s_w, g_tab, ln2kT,
+                                                     dEsum, nacc, cy);
             __builtin_amdgcn_wave_barrier();
         };
         uint32_t w[4] = {base_lo, base_hi, s, (uint32_t)colour};
@@ -828,7 +829,7 @@ hipError_t launch_accept_bounds(const double* d_tab, const uint32_t* d_u, int n,
 }
 
 // Exhaustive check of the acceptance bounds over every 32-bit draw u (the
-// BCC draws are the even ones, the FCC draws all of them).  For each u the
+// acceptance draws of both lattices).  For each u the
 // kernel forms the edges as the sweep kernels do; the largest dE they accept
 // without the table is lo = floor(elo) and the smallest they reject without
 // it is hi + 1, hi = floor(ehi).  It evaluates the exact test of Eq. (3) on

@@ -116,7 +116,7 @@ def test_device_accept_bounds_agree_with_table_test(smcx, orc, T):
     between stays a few micro-eV wide."""
     note(f"accept bounds T={T}")
     rng = np.random.default_rng(int(T) + 7)
-    # even draws (BCC: u << 1) and any 32-bit word (FCC)
+    # any 32-bit word (the acceptance draw of both lattices), even and odd
     u = np.concatenate([rng.integers(1, 1 << 31, 40000) * 2, rng.integers(1, 1 << 32, 40000),
                         [1, 2, 3, 4, 5, 6, 8, 1 << 31, (1 << 32) - 1, (1 << 32) - 2, (1 << 32) - 4, 3 << 30,
                          (1 << 24) - 1, (1 << 24) + 1]]).astype(np.uint32)

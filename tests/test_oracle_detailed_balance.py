@@ -10,8 +10,8 @@ For each pair this checks three things.
   Cartesian pair sum, and the reverse move's change is its negative.
 * The exact acceptance probability over the whole draw space satisfies
   a(s -> s') / a(s' -> s) = exp(-(E(s') - E(s)) / k_B T) to within the
-  draw resolution.  BCC draws are the even 32-bit words; FCC draws are all
-  32-bit words.  The probability is found by bisection on the oracle's test,
+  draw resolution, 2^-32 (the acceptance draw of both lattices is a whole
+  32-bit word).  The probability is found by bisection on the oracle's test,
   which is monotone in the draw.
 * Pairs are checked on random quinary configurations at 1 K to 5000 K.
 """
@@ -36,16 +36,15 @@ def cartesian_energy(M, epi, sigma):
     return twice // 2
 
 
-def acceptance_probability(orc, dE, tab, even):
-    """Fraction of draws u (even u only when `even`) that the oracle accepts
-    for an energy change dE: the test is u < threshold, so the accepted
-    draws are a prefix; bisection finds its length."""
-    step = 2 if even else 1
-    n = (1 << 32) // step
+def acceptance_probability(orc, dE, tab):
+    """Fraction of the 2^32 draws u that the oracle accepts for an energy
+    change dE: the test is u < threshold, so the accepted draws are a
+    prefix; bisection finds its length."""
+    n = 1 << 32
     lo, hi = 0, n                       # accepted count in [lo, hi]
     while lo < hi:
-        mid = (lo + hi) // 2            # is draw number `mid` accepted?
-        if orc.accept(dE, mid * step, tab):
+        mid = (lo + hi) // 2            # is draw `mid` accepted?
+        if orc.accept(dE, mid, tab):
             lo = mid + 1
         else:
             hi = mid
@@ -61,7 +60,6 @@ def test_single_trial_detailed_balance(orc, lattice, L, T):
     M = multiplicity(L, lattice, S)
     N = M.shape[1]
     tab = orc.thresholds(T)
-    even = lattice == 0
     nfirst = 8 if lattice == 0 else 12
     checked = 0
     for _ in range(6):
@@ -78,9 +76,9 @@ def test_single_trial_detailed_balance(orc, lattice, L, T):
                 swapped[i], swapped[j] = sigma[j], sigma[i]
                 assert dE == cartesian_energy(M, epi, swapped) - E0
                 assert orc.delta_energy(L, epi, swapped, j, int(i), lattice) == -dE
-                a_fwd = acceptance_probability(orc, dE, tab, even)
-                a_rev = acceptance_probability(orc, -dE, tab, even)
-                resolution = 2.0 ** -31 if even else 2.0 ** -32
+                a_fwd = acceptance_probability(orc, dE, tab)
+                a_rev = acceptance_probability(orc, -dE, tab)
+                resolution = 2.0 ** -32
                 x = -dE / (KB * T)
                 # pi(s) a(s->s') - pi(s') a(s'->s), scaled by pi(s) (both
                 # probabilities are 1 for downhill moves)

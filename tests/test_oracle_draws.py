@@ -1,17 +1,20 @@
-"""Pins of the BCC trial draws (reading: the paper fixes neither the random
+"""Pins of the BCC trial draws (reading; the paper fixes neither the random
 numbers nor how a swap partner is chosen beyond its being a nearest
 neighbour).
 
 Each trial takes one 32-bit word of a Philox4x32-10 call keyed by the lane's
-base cell; the partner's x step comes from the word's top bit, its y and z
-steps from one draw per (sweep, colour, sub-colour) set.  Checked here by
-enumeration over whole lattices, not by restating the formulas:
+base cell as its acceptance draw; the partner direction is drawn once per
+(sweep, colour, sub-colour) set (x step from one per-colour draw, y and z
+steps from another).  Checked here by enumeration over whole lattices, not
+by restating the formulas:
   * no two trials of a sweep share a random word, and no trial counter
-    equals the per-colour partner-bit counter or the shift counter;
-  * inside one set every partner has the same y and z steps;
-  * the first-neighbour direction is uniform over the 8 (chi-square over
-    sites and sweeps), its x step independent of its y and z steps;
-  * the acceptance draw is even and uniform on [0, 2^32) (chi-square);
+    equals a per-colour partner-bit counter or the shift counter;
+  * inside one set every partner has the same direction;
+  * the direction, counted once per set, is uniform over the 8 first
+    neighbours (chi-square over sets and sweeps), its x step independent of
+    its y and z steps;
+  * the acceptance draw is uniform on [0, 2^32) (chi-square, and its low
+    bit balanced);
   * the partner is a first neighbour of the site (Cartesian distance).
 """
 import numpy as np
@@ -36,10 +39,10 @@ def test_draw_words_unique(orc, L, B):
         # one call serves at most 4 trials, through distinct words
         _, per_call = np.unique(ctr, axis=0, return_counts=True)
         assert per_call.max() <= 4
-        # never the counter of the partner-bit draw (0, 0, s, 32 + c) or of
-        # the origin shift (0, 0, s, 8)
+        # never the counter of a partner-bit draw (0, 0, s, 32 + c) and
+        # (0, 0, s, 40 + c) or of the origin shift (0, 0, s, 8)
         low = (ctr[:, 0] == 0) & (ctr[:, 1] == 0)
-        assert not np.any(low & (((ctr[:, 3] >= 32) & (ctr[:, 3] < 40)) | (ctr[:, 3] == 8)))
+        assert not np.any(low & (((ctr[:, 3] >= 32) & (ctr[:, 3] < 48)) | (ctr[:, 3] == 8)))
 
 
 def test_partner_steps_shared_per_set(orc):
@@ -48,19 +51,29 @@ def test_partner_steps_shared_per_set(orc):
         col, sub, _ = orc.schedule(L, B, 99, s)
         _, _, dirs, _ = orc.bcc_draws(L, B, 99, s)
         key = col.astype(np.int64) * 54 + sub
-        yz = dirs >> 1
         for k in np.unique(key):
-            assert np.unique(yz[key == k]).size == 1, (s, k)
+            assert np.unique(dirs[key == k]).size == 1, (s, k)
         # and different sets do not all agree
-        assert np.unique(yz).size == 4
+        assert np.unique(dirs).size == 8
+
+
+def set_directions(orc, L, B, seed, sweeps):
+    """The direction of every (sweep, colour, sub-colour) set, once per set."""
+    out = []
+    for s in sweeps:
+        col, sub, _ = orc.schedule(L, B, seed, s)
+        _, _, dirs, _ = orc.bcc_draws(L, B, seed, s)
+        key = col.astype(np.int64) * 54 + sub
+        _, first = np.unique(key, return_index=True)
+        out.append(dirs[first])
+    return np.concatenate(out).astype(np.int64)
 
 
 def test_direction_uniform_and_x_independent(orc):
     L, B = (6, 6, 6), (12, 12, 12)
+    d = set_directions(orc, L, B, 7, range(120))     # 120 sweeps x 8 colours x 54 sets
     hist = np.zeros((2, 4), np.int64)
-    for s in range(300):
-        _, _, dirs, _ = orc.bcc_draws(L, B, 7, s)
-        np.add.at(hist, (dirs & 1, dirs >> 1), 1)
+    np.add.at(hist, (d & 1, d >> 1), 1)
     chi2, dof = chi2_uniform(hist.ravel())
     assert chi2 < dof + 6 * np.sqrt(2 * dof), hist
     # independence of the x step from the (y, z) steps: 2 x 4 contingency
@@ -70,13 +83,15 @@ def test_direction_uniform_and_x_independent(orc):
     assert chi2 < 3 + 6 * np.sqrt(6), hist
 
 
-def test_acceptance_draw_even_and_uniform(orc):
+def test_acceptance_draw_uniform(orc):
     L, B = (10, 10, 10), (12, 12, 12)
     us = np.concatenate([orc.bcc_draws(L, B, 31, s)[3] for s in range(20)])
-    assert np.all(us % 2 == 0)
     counts = np.bincount((us >> 26).astype(np.int64), minlength=64)
     chi2, dof = chi2_uniform(counts)
     assert chi2 < dof + 6 * np.sqrt(2 * dof)
+    # all 32 bits are drawn: the low bit too is balanced
+    odd = int(np.count_nonzero(us & 1))
+    assert abs(odd - us.size / 2) < 6 * np.sqrt(us.size / 4)
 
 
 def test_partner_is_a_first_neighbour(orc):
