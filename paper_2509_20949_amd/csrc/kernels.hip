@@ -133,6 +133,58 @@ __device__ __forceinline__ uint32_t weigh(const uint32_t (&hi)[kMaxS], const uin
     return acc;
 }
 
+// The partner part of a three-shell trial for the direction E (a
+// compile-time value; the trial switches on its wave-uniform direction):
+// half of the partner's neighbourhood is cells the site's own counts
+// already hold.  In half-cell units j = i + s, s_a = +-1 the signs of E.
+// j's first shell is i + (0 or 2 s_a per axis): i, the site's second
+// neighbours i + 2 s_a along the three axes, its third neighbours in the
+// three planes with the same signs, and the far cell i + 2 s (loaded).  j's
+// second and third shells hold the site's first-shell cells k with one or
+// two direction bits flipped (popcount(k ^ E) = 1 or 2) and 3 and 9 cells
+// beyond (loaded).  With T0, T1 the site's first-shell counts over indices
+// of even and odd popcount, those two sets are T[par E ^ 1] less cell
+// E ^ 7 and T[par E] less cell E (the partner).  Sets cj (the partner's
+// code) and j's counts hj (+1 per neighbour, or -1 with NEG).
+template <int SUB, int E, bool NEG>
+__device__ __forceinline__ void partner3(const uint8_t* lat, int ai, const uint32_t (&s1)[8], uint32_t ci,
+                                         const uint32_t (&r2)[6], const uint32_t (&r3)[12], uint32_t T0,
+                                         uint32_t T1, uint32_t& cj, uint32_t (&hj)[kMaxS])
+{
+    constexpr int ex = E & 1, ey = (E >> 1) & 1, ez = (E >> 2) & 1;
+    constexpr int dx = ex ? 1 : -1, dy = ey ? kP : -kP, dz = ez ? kPP : -kPP;
+    constexpr bool odd = (ex + ey + ez) & 1;
+    const int aj = ai + s1off<SUB>(E);
+    cj = s1[E];
+    uint32_t t_same = odd ? T1 : T0, t_other = odd ? T0 : T1;
+    count1<true>(t_same, s1[E]);        // j's third-shell cells among the site's first shell
+    count1<true>(t_other, s1[E ^ 7]);   // j's second-shell cells among them
+    // j's first shell
+    count1<NEG>(hj[0], ci);
+    count1<NEG>(hj[0], r2[ex ? 0 : 1]);
+    count1<NEG>(hj[0], r2[ey ? 2 : 3]);
+    count1<NEG>(hj[0], r2[ez ? 4 : 5]);
+    count1<NEG>(hj[0], r3[(ex ? 0 : 2) + (ey ? 0 : 1)]);
+    count1<NEG>(hj[0], r3[4 + (ex ? 0 : 2) + (ez ? 0 : 1)]);
+    count1<NEG>(hj[0], r3[8 + (ey ? 0 : 2) + (ez ? 0 : 1)]);
+    count1<NEG>(hj[0], lat[ai + dx + dy + dz]);
+    // j's second and third shells
+    hj[1] = NEG ? 0u - t_other : t_other;
+    hj[2] = NEG ? 0u - t_same : t_same;
+    count1<NEG>(hj[1], lat[aj + dx]);
+    count1<NEG>(hj[1], lat[aj + dy]);
+    count1<NEG>(hj[1], lat[aj + dz]);
+    count1<NEG>(hj[2], lat[aj + dx + dy]);
+    count1<NEG>(hj[2], lat[aj + dx - dy]);
+    count1<NEG>(hj[2], lat[aj - dx + dy]);
+    count1<NEG>(hj[2], lat[aj + dx + dz]);
+    count1<NEG>(hj[2], lat[aj + dx - dz]);
+    count1<NEG>(hj[2], lat[aj - dx + dz]);
+    count1<NEG>(hj[2], lat[aj + dy + dz]);
+    count1<NEG>(hj[2], lat[aj + dy - dz]);
+    count1<NEG>(hj[2], lat[aj - dy + dz]);
+}
+
 // Codes a trial hands to the next one (registers), so that the next trial
 // reads neither its own site, nor its partner, nor 7 of its 8 first
 // neighbours from LDS.  The next site is the other sublattice's site of the
@@ -190,24 +242,6 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int e, b
         for (int e = 0; e < 8; ++e) s1[e] = lat[ai + s1off<SUB>(e)];
         ci = lat[ai];
     }
-    // Seven v_cndmask on the bits of e.  (e is wave-uniform; held in a
-    // vector register, its selects stay in the trial's basic block instead
-    // of becoming branches, which would keep the loads below from being
-    // issued ahead.)
-    uint32_t e_j = (uint32_t)e;
-    asm volatile("" : "+v"(e_j));
-    const uint32_t x0 = e_j & 1u ? s1[1] : s1[0], x1 = e_j & 1u ? s1[3] : s1[2];
-    const uint32_t x2 = e_j & 1u ? s1[5] : s1[4], x3 = e_j & 1u ? s1[7] : s1[6];
-    const uint32_t y0 = e_j & 2u ? x1 : x0, y1 = e_j & 2u ? x3 : x2;
-    const uint32_t cj = e_j & 4u ? y1 : y0;
-
-    // Row (a, b) of the weight planes, a = ci >> 5 and b = cj >> 5, at byte
-    // 4 (8a + b) of a plane.  (Lanes without a site in this round may decode
-    // stale halo bytes: their row still lies inside the planes, and their
-    // result is discarded.)
-    const uint32_t row4 = (ci & 0xe0u) + ((cj >> 5) << 2);
-    const int32_t* w = (const int32_t*)((const uint8_t*)wtab + row4);
-
     // Species histograms of both neighbourhoods (the partner is counted in
     // the first shell of i and i in that of j; the constant term undoes it).
     // In the difference form j's chains subtract and are added to i's
@@ -217,16 +251,55 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int e, b
                             : F == 5 ? 0x10u * (1u | 1u << 5 | 1u << 10 | 1u << 15 | 1u << 20 | 1u << 25) : 0u;
 #pragma unroll
     for (int s = 0; s < kMaxS; ++s) { hi[s] = bias; hj[s] = 0u; }
+    uint32_t r2[6], r3[12];
+    uint32_t cj;
+    if constexpr (SMAX < 3) {
+        // the partner by seven v_cndmask on the bits of e (held in a vector
+        // register, e's selects stay in the trial's basic block instead of
+        // becoming branches, which would keep the loads below from being
+        // issued ahead)
+        uint32_t ev = (uint32_t)e;
+        asm volatile("" : "+v"(ev));
+        const uint32_t x0 = ev & 1u ? s1[1] : s1[0], x1 = ev & 1u ? s1[3] : s1[2];
+        const uint32_t x2 = ev & 1u ? s1[5] : s1[4], x3 = ev & 1u ? s1[7] : s1[6];
+        const uint32_t y0 = ev & 2u ? x1 : x0, y1 = ev & 2u ? x3 : x2;
+        cj = ev & 4u ? y1 : y0;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) count1<false>(hi[0], s1[e]);
-    uint32_t r2[6], r3[12], q2[6], q3[12];
-    count_outer<SMAX, false>(lat, ai, hi, r2, r3);
+        for (int k = 0; k < 8; ++k) count1<false>(hi[0], s1[k]);
+        count_outer<SMAX, false>(lat, ai, hi, r2, r3);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) count1<DIFF>(hj[0], lat[aj + s1off<1 - SUB>(k)]);
+        uint32_t q2[6], q3[12];
+        count_outer<SMAX, DIFF>(lat, aj, hj, q2, q3);
+    } else {
+        uint32_t T0 = 0u, T1 = 0u;   // the site's first shell, indices of even / odd popcount
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (__builtin_popcount(k) & 1) count1<false>(T1, s1[k]);
+            else count1<false>(T0, s1[k]);
+        }
+        hi[0] += T0 + T1;
+        count_outer<3, false>(lat, ai, hi, r2, r3);
+        switch (e) {   // wave-uniform
+        case 0: partner3<SUB, 0, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hj); break;
+        case 1: partner3<SUB, 1, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hj); break;
+        case 2: partner3<SUB, 2, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hj); break;
+        case 3: partner3<SUB, 3, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hj); break;
+        case 4: partner3<SUB, 4, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hj); break;
+        case 5: partner3<SUB, 5, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hj); break;
+        case 6: partner3<SUB, 6, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hj); break;
+        default: partner3<SUB, 7, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hj); break;
+        }
+    }
+    // Row (a, b) of the weight planes, a = ci >> 5 and b = cj >> 5, at byte
+    // 4 (8a + b) of a plane.  (Lanes without a site in this round may decode
+    // stale halo bytes: their row still lies inside the planes, and their
+    // result is discarded.)
+    const uint32_t row4 = (ci & 0xe0u) + ((cj >> 5) << 2);
+    const int32_t* w = (const int32_t*)((const uint8_t*)wtab + row4);
     // the cell of this sublattice the next trial's first shell needs besides
     // these: corner(x + 1, y + 1, z + 1) or body(x + 1, y - 1, z - 1)
     const uint32_t fresh = COUT ? (uint32_t)lat[ai + (SUB == 0 ? 1 + kP + kPP : 1 - kP - kPP)] : 0u;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) count1<DIFF>(hj[0], lat[aj + s1off<1 - SUB>(e)]);
-    count_outer<SMAX, DIFF>(lat, aj, hj, q2, q3);
     if constexpr (DIFF) {
 #pragma unroll
         for (int s = 0; s < kMaxS; ++s) { hi[s] += hj[s]; hj[s] = 0u; }
@@ -290,7 +363,7 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int e, b
         // the next site is first-shell cell kNext of this site; it changed
         // iff it was the partner of an accepted swap
         constexpr int kNext = SUB == 0 ? 7 : 1;
-        cy.own = accept && e_j == (uint32_t)kNext ? ci : s1[kNext];
+        cy.own = accept && e == kNext ? ci : s1[kNext];
         if constexpr (SUB == 0) {   // next: body(x, y, z); its first shell corner(x + ex, y + ey, z + ez)
             cy.s1[0] = ci_new;
             cy.s1[1] = r2[0];   // +x
