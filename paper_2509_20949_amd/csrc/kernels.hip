@@ -69,11 +69,16 @@ __device__ __forceinline__ constexpr int s3off(int k)
          : k == 8 ? kP + kPP : k == 9 ? kP - kPP : k == 10 ? -kP + kPP : -kP - kPP;
 }
 
-// Add +1 (NEG: -1) in the field of code c to h: one shift-add.
+// Add +1 (NEG: -1) in the field of code c to h: one v_lshl_add_u32, whose
+// shift takes the low 5 bits of c.  Written out, so that no mask of c is
+// materialised: the compiler folds c & 31 into the shift only when both sit
+// in one basic block, and codes the direction-specialised partner parts
+// count are loaded before the switch on the direction.  (The instruction
+// also keeps each count a chain of shift-adds, as keep() does.)
 template <bool NEG> __device__ __forceinline__ void count1(uint32_t& h, uint32_t c)
 {
-    h += (NEG ? 0xffffffffu : 1u) << (c & 31u);
-    keep(h);
+    if constexpr (NEG) asm("v_lshl_add_u32 %0, -1, %1, %0" : "+v"(h) : "v"(c));
+    else asm("v_lshl_add_u32 %0, 1, %1, %0" : "+v"(h) : "v"(c));
 }
 
 // Counts of the second and third shells of the site at LDS byte a (its own
