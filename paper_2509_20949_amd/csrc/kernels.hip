@@ -150,11 +150,11 @@ __device__ __forceinline__ uint32_t weigh(const uint32_t (&hi)[kMaxS], const uin
 // beyond (loaded).  With T0, T1 the site's first-shell counts over indices
 // of even and odd popcount, those two sets are T[par E ^ 1] less cell
 // E ^ 7 and T[par E] less cell E (the partner).  Sets cj (the partner's
-// code) and j's counts hj (+1 per neighbour, or -1 with NEG).
+// code) and adds j's counts to h (+1 per neighbour, or -1 with NEG).
 template <int SUB, int E, bool NEG>
 __device__ __forceinline__ void partner3(const uint8_t* lat, int ai, const uint32_t (&s1)[8], uint32_t ci,
                                          const uint32_t (&r2)[6], const uint32_t (&r3)[12], uint32_t T0,
-                                         uint32_t T1, uint32_t& cj, uint32_t (&hj)[kMaxS])
+                                         uint32_t T1, uint32_t& cj, uint32_t (&h)[kMaxS])
 {
     constexpr int ex = E & 1, ey = (E >> 1) & 1, ez = (E >> 2) & 1;
     constexpr int dx = ex ? 1 : -1, dy = ey ? kP : -kP, dz = ez ? kPP : -kPP;
@@ -165,29 +165,29 @@ __device__ __forceinline__ void partner3(const uint8_t* lat, int ai, const uint3
     count1<true>(t_same, s1[E]);        // j's third-shell cells among the site's first shell
     count1<true>(t_other, s1[E ^ 7]);   // j's second-shell cells among them
     // j's first shell
-    count1<NEG>(hj[0], ci);
-    count1<NEG>(hj[0], r2[ex ? 0 : 1]);
-    count1<NEG>(hj[0], r2[ey ? 2 : 3]);
-    count1<NEG>(hj[0], r2[ez ? 4 : 5]);
-    count1<NEG>(hj[0], r3[(ex ? 0 : 2) + (ey ? 0 : 1)]);
-    count1<NEG>(hj[0], r3[4 + (ex ? 0 : 2) + (ez ? 0 : 1)]);
-    count1<NEG>(hj[0], r3[8 + (ey ? 0 : 2) + (ez ? 0 : 1)]);
-    count1<NEG>(hj[0], lat[ai + dx + dy + dz]);
+    count1<NEG>(h[0], ci);
+    count1<NEG>(h[0], r2[ex ? 0 : 1]);
+    count1<NEG>(h[0], r2[ey ? 2 : 3]);
+    count1<NEG>(h[0], r2[ez ? 4 : 5]);
+    count1<NEG>(h[0], r3[(ex ? 0 : 2) + (ey ? 0 : 1)]);
+    count1<NEG>(h[0], r3[4 + (ex ? 0 : 2) + (ez ? 0 : 1)]);
+    count1<NEG>(h[0], r3[8 + (ey ? 0 : 2) + (ez ? 0 : 1)]);
+    count1<NEG>(h[0], lat[ai + dx + dy + dz]);
     // j's second and third shells
-    hj[1] = NEG ? 0u - t_other : t_other;
-    hj[2] = NEG ? 0u - t_same : t_same;
-    count1<NEG>(hj[1], lat[aj + dx]);
-    count1<NEG>(hj[1], lat[aj + dy]);
-    count1<NEG>(hj[1], lat[aj + dz]);
-    count1<NEG>(hj[2], lat[aj + dx + dy]);
-    count1<NEG>(hj[2], lat[aj + dx - dy]);
-    count1<NEG>(hj[2], lat[aj - dx + dy]);
-    count1<NEG>(hj[2], lat[aj + dx + dz]);
-    count1<NEG>(hj[2], lat[aj + dx - dz]);
-    count1<NEG>(hj[2], lat[aj - dx + dz]);
-    count1<NEG>(hj[2], lat[aj + dy + dz]);
-    count1<NEG>(hj[2], lat[aj + dy - dz]);
-    count1<NEG>(hj[2], lat[aj - dy + dz]);
+    h[1] = NEG ? h[1] - t_other : h[1] + t_other;
+    h[2] = NEG ? h[2] - t_same : h[2] + t_same;
+    count1<NEG>(h[1], lat[aj + dx]);
+    count1<NEG>(h[1], lat[aj + dy]);
+    count1<NEG>(h[1], lat[aj + dz]);
+    count1<NEG>(h[2], lat[aj + dx + dy]);
+    count1<NEG>(h[2], lat[aj + dx - dy]);
+    count1<NEG>(h[2], lat[aj - dx + dy]);
+    count1<NEG>(h[2], lat[aj + dx + dz]);
+    count1<NEG>(h[2], lat[aj + dx - dz]);
+    count1<NEG>(h[2], lat[aj - dx + dz]);
+    count1<NEG>(h[2], lat[aj + dy + dz]);
+    count1<NEG>(h[2], lat[aj + dy - dz]);
+    count1<NEG>(h[2], lat[aj - dy + dz]);
 }
 
 // Codes a trial hands to the next one (registers), so that the next trial
@@ -285,15 +285,17 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int e, b
         }
         hi[0] += T0 + T1;
         count_outer<3, false>(lat, ai, hi, r2, r3);
+        // j's counts: subtracted from i's chains in the difference form
+        auto& hp = *(DIFF ? &hi : &hj);
         switch (e) {   // wave-uniform
-        case 0: partner3<SUB, 0, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hj); break;
-        case 1: partner3<SUB, 1, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hj); break;
-        case 2: partner3<SUB, 2, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hj); break;
-        case 3: partner3<SUB, 3, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hj); break;
-        case 4: partner3<SUB, 4, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hj); break;
-        case 5: partner3<SUB, 5, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hj); break;
-        case 6: partner3<SUB, 6, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hj); break;
-        default: partner3<SUB, 7, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hj); break;
+        case 0: partner3<SUB, 0, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hp); break;
+        case 1: partner3<SUB, 1, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hp); break;
+        case 2: partner3<SUB, 2, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hp); break;
+        case 3: partner3<SUB, 3, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hp); break;
+        case 4: partner3<SUB, 4, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hp); break;
+        case 5: partner3<SUB, 5, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hp); break;
+        case 6: partner3<SUB, 6, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hp); break;
+        default: partner3<SUB, 7, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hp); break;
         }
     }
     // Row (a, b) of the weight planes, a = ci >> 5 and b = cj >> 5, at byte
@@ -347,7 +349,7 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int e, b
     const bool sure = fdE <= elo;
     const bool near = up & ((!sure & (fdE <= ehi)) | (u_acc == 0u));
     bool up_ok = up & sure;
-    if (__ballot(near)) {
+    if (__builtin_amdgcn_ballot_w64(near)) {
         const int e = dE < 1 ? 1 : (dE > (1 << 24) - 1 ? (1 << 24) - 1 : dE);
         const uint8_t* tb = (const uint8_t*)tab;   // global memory (L2-resident)
         const double thr = (gload<double>(tb + 8 * (512 + (e >> 16))) * gload<double>(tb + 8 * (256 + ((e >> 8) & 255)))) *
@@ -362,7 +364,7 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int e, b
     lat[ai] = (uint8_t)ci_new;
     lat[aj] = (uint8_t)(accept ? ci : cj);
     dEsum += (int64_t)(accept ? dE : 0);
-    nacc += (uint32_t)__popcll(__ballot(accept));   // wave-uniform: counted on the scalar unit
+    nacc += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(accept));   // wave-uniform: counted on the scalar unit
 
     if constexpr (COUT) {
         // the next site is first-shell cell kNext of this site; it changed
@@ -404,8 +406,13 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
                         int t, int colour)
 {
     constexpr int F = Field<KMAX>::F;
-    __shared__ int32_t s_w[wplanes(KMAX, SMAX) * kPlane];
-    __shared__ __attribute__((aligned(16))) uint8_t s_lat[WPG * kWaveLds];
+    // One LDS buffer: the weight planes at offset 0 (so a plane's LDS offset
+    // fits the st64 immediates of ds_read2st64_b32 and row addresses need no
+    // base added), then the block images.
+    constexpr int kWBytes = wplanes(KMAX, SMAX) * kPlane * 4;
+    __shared__ __attribute__((aligned(16))) uint8_t s_mem[kWBytes + WPG * kWaveLds];
+    int32_t* s_w = (int32_t*)s_mem;
+    uint8_t* s_lat = s_mem + kWBytes;
 
     const int wave = wave_id();
     const int lane = threadIdx.x % kWave;
