@@ -56,8 +56,8 @@ BYTES_PER_TRIAL = 2
 # (profiles/sweep_phase_bcc512_k5s3_hbm_counters.md).  It describes the
 # kernel built from the sources with this SHA-256 only; for other sources
 # the bench reports traffic as null.
-MEASURED_TRAFFIC = {"sources_sha256": "14554ef2004727f6bb036b145c1804b4f3a140b60b19e5395fbe3d3b5f0bed7c",
-                    "bytes_per_launch": 225395997}
+MEASURED_TRAFFIC = {"sources_sha256": "388e9331044059535aa479908c9f2e612ef18944ab8496a452cc80b8a26c4227",
+                    "bytes_per_launch": 225577565}
 KERNEL_SOURCES = ("paper_2509_20949_amd/csrc/kernels.hip", "paper_2509_20949_amd/csrc/device_common.h",
                   "paper_2509_20949_amd/csrc/smcx_internal.h")
 

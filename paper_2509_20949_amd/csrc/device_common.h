@@ -41,18 +41,15 @@ __device__ __forceinline__ void keep(uint32_t& h) { asm("" : "+v"(h)); }
 constexpr int wplane(int kmax) { return ((kmax * kmax + 31) / 32) * 32; }
 constexpr int wplanes(int kmax, int smax) { return wrow_entries(kmax, smax); }
 
-// Fill the LDS planes (PS dwords apart) from the row-major table of
-// wrow(KMAX, SMAX) ints per row.  Row (a, b) goes to plane position
-// a*KMAX + b (PS >= KMAX*KMAX), or with ROW8 to a*8 + b (PS >= 64), which
-// spares the sweep a multiply when it forms the position from two codes.
-template <int KMAX, int SMAX, int PS = wplane(KMAX), bool ROW8 = false>
+// Fill the LDS planes (PS dwords apart, PS >= KMAX*KMAX) from the
+// row-major table of wrow(KMAX, SMAX) ints per row.
+template <int KMAX, int SMAX, int PS = wplane(KMAX)>
 __device__ __forceinline__ void load_wplanes(int32_t* s_w, const int32_t* wtab)
 {
     constexpr int WR = wrow(KMAX, SMAX);
     for (int k = threadIdx.x; k < wplanes(KMAX, SMAX) * PS; k += blockDim.x) {
-        const int f = k / PS, pos = k - f * PS;
-        const int a = ROW8 ? pos >> 3 : pos / KMAX, b = ROW8 ? pos & 7 : pos - a * KMAX;
-        s_w[k] = a < KMAX && b < KMAX ? wtab[(a * KMAX + b) * WR + f] : 0;
+        const int f = k / PS, row = k - f * PS;
+        s_w[k] = row < KMAX * KMAX ? wtab[row * WR + f] : 0;
     }
 }
 

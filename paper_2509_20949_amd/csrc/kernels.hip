@@ -49,12 +49,14 @@ constexpr int kSweepWavesPerSimd = 5;
 // bound it: one aligned word per row once the two loads are joined).
 constexpr int kStageBatch = 16;
 
-// Weight planes of the BCC kernel: row (a, b) at position 8a + b of a
+// Weight planes of the BCC kernel: row (a, b) at position a*KMAX + b of a
 // 64-entry plane, so that the position of any two 3-bit codes (a lane
-// without a site may decode a stale halo byte) stays inside its plane and
-// is formed from the codes by a mask, a shift and a shift-add.
+// without a site may decode a stale halo byte) stays inside its plane.  The
+// KMAX^2 rows of real species then lie in distinct LDS banks (positions
+// 8a + b, one multiply fewer, put species 4 and 0 of K = 5 on the same
+// banks: 16 % of the LDS cycles went to those conflicts).
 constexpr int kPlane = 64;
-static_assert(8 * 7 + 7 < kPlane && kMaxK <= 8, "weight plane too narrow");
+static_assert(7 * kMaxK + 7 < kPlane, "weight plane too narrow");
 
 // Shell offsets inside one sublattice array.
 __device__ __forceinline__ constexpr int s2off(int k)
@@ -299,10 +301,10 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int e, b
         }
     }
     // Row (a, b) of the weight planes, a = ci >> 5 and b = cj >> 5, at byte
-    // 4 (8a + b) of a plane.  (Lanes without a site in this round may decode
-    // stale halo bytes: their row still lies inside the planes, and their
-    // result is discarded.)
-    const uint32_t row4 = (ci & 0xe0u) + ((cj >> 5) << 2);
+    // 4 (a*KMAX + b) of a plane.  (Lanes without a site in this round may
+    // decode stale halo bytes: their row still lies inside the planes, and
+    // their result is discarded.)
+    const uint32_t row4 = __umul24(ci >> 5, 4u * KMAX) + ((cj >> 5) << 2);
     const int32_t* w = (const int32_t*)((const uint8_t*)wtab + row4);
     // the cell of this sublattice the next trial's first shell needs besides
     // these: corner(x + 1, y + 1, z + 1) or body(x + 1, y - 1, z - 1)
@@ -431,7 +433,7 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
     // Weight planes in LDS; the threshold tables of sweep s stay in global
     // memory (read only for the few draws whose decision needs them), which
     // leaves LDS for five workgroups per CU.
-    load_wplanes<KMAX, SMAX, kPlane, true>(s_w, D.wtab);
+    load_wplanes<KMAX, SMAX, kPlane>(s_w, D.wtab);
     __syncthreads();
     int ti = (int)(s - D.tab_s0);
     ti = ti < 0 ? 0 : (ti >= D.n_tabs ? D.n_tabs - 1 : ti);
