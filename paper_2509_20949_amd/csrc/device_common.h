@@ -32,6 +32,18 @@ __device__ __forceinline__ void lane_cell(int lane, int& ix, int& iy, int& iz)
 // its own mask and instruction instead of one shift-add.
 __device__ __forceinline__ void keep(uint32_t& h) { asm("" : "+v"(h)); }
 
+// Add +1 (NEG: -1) in the field of code c to h: one v_lshl_add_u32, whose
+// shift takes the low 5 bits of c.  Written out, so that no mask of c is
+// materialised: the compiler folds c & 31 into the shift only when both sit
+// in one basic block, and the sweep kernels count codes in partner-specific
+// blocks that were loaded before the branch to them.  (The instruction also
+// keeps each count a chain of shift-adds, as keep() does.)
+template <bool NEG> __device__ __forceinline__ void count1(uint32_t& h, uint32_t c)
+{
+    if constexpr (NEG) asm("v_lshl_add_u32 %0, -1, %1, %0" : "+v"(h) : "v"(c));
+    else asm("v_lshl_add_u32 %0, 1, %1, %0" : "+v"(h) : "v"(c));
+}
+
 // LDS form of the pair-weight table: entry f of row (a, b) (f = s*KMAX + p
 // for a weight, SMAX*KMAX for the constant) sits in plane f at position
 // a*KMAX + b, planes wplane(KMAX) dwords apart.  The lanes of a wave read one

@@ -71,17 +71,6 @@ __device__ __forceinline__ constexpr int s3off(int k)
          : k == 8 ? kP + kPP : k == 9 ? kP - kPP : k == 10 ? -kP + kPP : -kP - kPP;
 }
 
-// Add +1 (NEG: -1) in the field of code c to h: one v_lshl_add_u32, whose
-// shift takes the low 5 bits of c.  Written out, so that no mask of c is
-// materialised: the compiler folds c & 31 into the shift only when both sit
-// in one basic block, and codes the direction-specialised partner parts
-// count are loaded before the switch on the direction.  (The instruction
-// also keeps each count a chain of shift-adds, as keep() does.)
-template <bool NEG> __device__ __forceinline__ void count1(uint32_t& h, uint32_t c)
-{
-    if constexpr (NEG) asm("v_lshl_add_u32 %0, -1, %1, %0" : "+v"(h) : "v"(c));
-    else asm("v_lshl_add_u32 %0, 1, %1, %0" : "+v"(h) : "v"(c));
-}
 
 // Counts of the second and third shells of the site at LDS byte a (its own
 // sublattice), added to h[1] and h[2]; the codes of the 6 second and 12

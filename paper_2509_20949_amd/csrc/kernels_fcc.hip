@@ -76,6 +76,71 @@ template <int B> struct Off { static constexpr Offsets v = make_offsets(B); };
 constexpr int axis1(int B, int BP) { return SUB[B][0] != SUB[BP][0] ? 0 : 1; }
 constexpr int axis2(int B, int BP) { return SUB[B][2] != SUB[BP][2] ? 2 : 1; }
 
+// The cells a trial must load, for the site in sublattice B and its partner
+// in sublattice BP with signs SG (bit 0: first differing axis, bit 1:
+// second; set = +1), counting shells s < S.  In doubled coordinates the
+// partner is at dj, and what the energy change needs per shell s is
+// sum over N_s of e(i + v) - sum over N_s of e(i + dj + v): cells in both
+// N_s(i) and N_s(j) cancel.  The rest, the symmetric differences, are 50
+// distinct cells for S = 3 (against 2 x 42 neighbours), some counted in two
+// shells.  plus/minus: bit s set = +1 / -1 in shell s.  The partner (dj, in
+// i's first shell) and the site itself (in j's first shell) are among them.
+struct DiffCells {
+    int n;
+    int off[64];
+    int plus[64], minus[64];
+    int i_site, i_partner;   // indices of the site and of the partner
+    int off_partner;         // LDS offset of the partner
+};
+
+constexpr int find_cell(const int (&d)[64][3], int n, int x, int y, int z)
+{
+    for (int k = 0; k < n; ++k)
+        if (d[k][0] == x && d[k][1] == y && d[k][2] == z) return k;
+    return -1;
+}
+
+constexpr bool in_shell(int s, int x, int y, int z)
+{
+    const int r = x * x + y * y + z * z;
+    return ((x + y + z) & 1) == 0 && r == (s == 0 ? 2 : s == 1 ? 4 : 6);
+}
+
+constexpr DiffCells make_diff(int B, int BP, int SG, int S)
+{
+    DiffCells c{};
+    int d[64][3] = {};
+    int dj[3] = {0, 0, 0};
+    dj[axis1(B, BP)] = (SG & 1) ? 1 : -1;
+    dj[axis2(B, BP)] = (SG & 2) ? 1 : -1;
+    for (int s = 0; s < S; ++s) {
+        const int n = s == 0 ? 12 : s == 1 ? 6 : 24;
+        for (int k = 0; k < n; ++k) {
+            const int* v = s == 0 ? SH1[k] : s == 1 ? SH2[k] : SH3[k];
+            // i's neighbour v, unless it is also j's neighbour in shell s
+            if (!in_shell(s, v[0] - dj[0], v[1] - dj[1], v[2] - dj[2])) {
+                int t = find_cell(d, c.n, v[0], v[1], v[2]);
+                if (t < 0) { t = c.n++; d[t][0] = v[0]; d[t][1] = v[1]; d[t][2] = v[2]; }
+                c.plus[t] |= 1 << s;
+            }
+            // j's neighbour dj + v, unless it is also i's neighbour in shell s
+            const int w0 = dj[0] + v[0], w1 = dj[1] + v[1], w2 = dj[2] + v[2];
+            if (!in_shell(s, w0, w1, w2)) {
+                int t = find_cell(d, c.n, w0, w1, w2);
+                if (t < 0) { t = c.n++; d[t][0] = w0; d[t][1] = w1; d[t][2] = w2; }
+                c.minus[t] |= 1 << s;
+            }
+        }
+    }
+    for (int k = 0; k < c.n; ++k) c.off[k] = offset(B, d[k][0], d[k][1], d[k][2]);
+    c.i_site = find_cell(d, c.n, 0, 0, 0);
+    c.i_partner = find_cell(d, c.n, dj[0], dj[1], dj[2]);
+    c.off_partner = offset(B, dj[0], dj[1], dj[2]);
+    return c;
+}
+
+template <int B, int BP, int SG, int S> struct Diff { static constexpr DiffCells v = make_diff(B, BP, SG, S); };
+
 // Packed species counts of the neighbours of the site at LDS byte a, one
 // word per shell, added to h.  Each shell is summed in NC short chains of
 // shift-adds (kept apart by keep(), so each step stays one v_lshl_add),
@@ -113,27 +178,38 @@ constexpr int KMAXF = 5;
 constexpr uint32_t kBias = 32u * (1u | 1u << 6 | 1u << 12 | 1u << 18 | 1u << 24);
 
 // One trial: site at LDS byte ai (sublattice B), partner in sublattice BP
-// with the wave-uniform signs (bit 0: first differing axis, bit 1: second;
-// set = +1), acceptance draw u_acc.
+// with the signs SG (bit 0: first differing axis, bit 1: second; set = +1),
+// all three wave-uniform, acceptance draw u_acc.
 // mode: the form of the weight rows (wave-uniform): kWtabDot or kWtabFull.
-template <int SMAX, int B, int BP>
-__device__ __forceinline__ void trial(uint8_t* lat, int ai, int signs, uint32_t u_acc, bool valid, int mode,
+template <int SMAX, int B, int BP, int SG>
+__device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u_acc, bool valid, int mode,
                                       const int32_t* wtab, const double* tab, float ln2kT, int64_t& dEsum,
                                       uint32_t& nacc)
 {
     int e_lo, e_hi;
     accept_bounds(u_acc, ln2kT, e_lo, e_hi);   // depends on the draw only
     constexpr int PS = wplane(KMAXF);
-    constexpr int a1 = axis1(B, BP), a2 = axis2(B, BP);
-    const int bit1 = signs & 1, bit2 = (signs >> 1) & 1;
-    const int aj = ai + (BP - B) * kArr + (SUB[BP][a1] - 1 + bit1) * stride(a1) + (SUB[BP][a2] - 1 + bit2) * stride(a2);
-    const uint32_t ci = lat[ai];
-    const uint32_t cj = lat[aj];
-    uint32_t hi[kMaxS], hj[kMaxS];
+    constexpr DiffCells C = Diff<B, BP, SG, SMAX>::v;
+    static_assert(C.n <= 64 && C.i_site >= 0 && C.i_partner >= 0, "cell table");
+    // packed per-shell fields bias + n_i - n_j over the symmetric
+    // differences (6-bit fields, or bytes in the byte-dot form), with the
+    // codes of the site and of the partner
+    uint32_t h[kMaxS];
 #pragma unroll
-    for (int s = 0; s < kMaxS; ++s) { hi[s] = mode == kWtabDot ? 0x20202020u : kBias; hj[s] = 0u; }
-    histogram<SMAX, B>(lat, ai, hi);
-    histogram<SMAX, BP>(lat, aj, hj);
+    for (int s = 0; s < kMaxS; ++s) h[s] = mode == kWtabDot ? 0x20202020u : kBias;
+    uint32_t ci = 0u, cj = 0u;
+#pragma unroll
+    for (int k = 0; k < C.n; ++k) {
+        const uint32_t c = lat[ai + C.off[k]];
+        if (k == C.i_site) ci = c;
+        if (k == C.i_partner) cj = c;
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) {
+            if (C.plus[k] >> s & 1) count1<false>(h[s], c);
+            if (C.minus[k] >> s & 1) count1<true>(h[s], c);
+        }
+    }
+    const int aj = ai + C.off_partner;
     const uint32_t a = min(decode(ci), (uint32_t)(KMAXF - 1)), b = min(decode(cj), (uint32_t)(KMAXF - 1));
     const int32_t* w = wtab + (a * KMAXF + b);   // row (a, b) of the weight planes
     // (kmax = 5: the table builder gives the byte-dot rows or, when the
@@ -141,23 +217,27 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, int signs, uint32_t 
     uint32_t acc;
     if (mode == kWtabDot) {
         // bytes 32 + n_i - n_j (bit 31, the last species, masked off) dotted
-        // with the three base-256 digits of the folded weights
-        int32_t A0 = w[3 * SMAX * PS], A1 = 0, A2 = 0;
+        // with the three base-256 digits of the folded weights, in one
+        // chain: ((A2 * 256 + A1) * 256 + constant) + A0
+        int32_t dd[kMaxS];
 #pragma unroll
-        for (int s = 0; s < SMAX; ++s) {
-            const int32_t d = (int32_t)((hi[s] - hj[s]) & 0x7fffffffu);
-            A0 = __builtin_amdgcn_sdot4(d, w[(3 * s + 0) * PS], A0, false);
-            A1 = __builtin_amdgcn_sdot4(d, w[(3 * s + 1) * PS], A1, false);
-            A2 = __builtin_amdgcn_sdot4(d, w[(3 * s + 2) * PS], A2, false);
-        }
-        acc = (uint32_t)A0 + ((uint32_t)A1 << 8) + ((uint32_t)A2 << 16);
+        for (int s = 0; s < SMAX; ++s) dd[s] = (int32_t)(h[s] & 0x7fffffffu);
+        int32_t X = 0;
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) X = __builtin_amdgcn_sdot4(dd[s], w[(3 * s + 2) * PS], X, false);
+        X = (int32_t)((uint32_t)X << 8);
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) X = __builtin_amdgcn_sdot4(dd[s], w[(3 * s + 1) * PS], X, false);
+        X = (int32_t)(((uint32_t)X << 8) + (uint32_t)w[3 * SMAX * PS]);
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) X = __builtin_amdgcn_sdot4(dd[s], w[(3 * s + 0) * PS], X, false);
+        acc = (uint32_t)X;
     } else {
         acc = (uint32_t)w[SMAX * KMAXF * PS];
 #pragma unroll
         for (int s = 0; s < SMAX; ++s) {
-            const uint32_t d = hi[s] - hj[s];
 #pragma unroll
-            for (int p = 0; p < KMAXF; ++p) acc = mad24((d >> (F * p)) & 63u, w[(s * KMAXF + p) * PS], acc);
+            for (int p = 0; p < KMAXF; ++p) acc = mad24((h[s] >> (F * p)) & 63u, w[(s * KMAXF + p) * PS], acc);
         }
     }
     const int32_t dE = (int32_t)acc;
@@ -166,7 +246,7 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, int signs, uint32_t 
     const bool up = (dE > 0) & (dE < (1 << 24));
     const bool near = up & (((dE > e_lo) & (dE <= e_hi)) | (u_acc == 0u));
     bool up_ok = up & (dE <= e_lo);
-    if (__ballot(near)) {
+    if (__builtin_amdgcn_ballot_w64(near)) {
         const int e = dE < 1 ? 1 : (dE > (1 << 24) - 1 ? (1 << 24) - 1 : dE);
         const uint8_t* tb = (const uint8_t*)tab;
         const double thr = (gload<double>(tb + 8 * (512 + (e >> 16))) * gload<double>(tb + 8 * (256 + ((e >> 8) & 255)))) *
@@ -179,19 +259,33 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, int signs, uint32_t 
     lat[ai] = (uint8_t)(accept ? cj : ci);
     lat[aj] = (uint8_t)(accept ? ci : cj);
     dEsum += (int64_t)(accept ? dE : 0);
-    nacc += (uint32_t)__popcll(__ballot(accept));   // wave-uniform
+    nacc += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(accept));   // wave-uniform
 }
 
-// Partner sublattice BP (a wave-uniform value) selects one instantiation.
+// The partner sublattice BP and signs (wave-uniform values) select one
+// instantiation.
+template <int SMAX, int B, int BP>
+__device__ __forceinline__ void trial_signs(int signs, uint8_t* lat, int ai, uint32_t u_acc, bool valid, int drop,
+                                            const int32_t* wtab, const double* tab, float ln2kT, int64_t& dEsum,
+                                            uint32_t& nacc)
+{
+    switch (signs) {
+    case 0: trial<SMAX, B, BP, 0>(lat, ai, u_acc, valid, drop, wtab, tab, ln2kT, dEsum, nacc); break;
+    case 1: trial<SMAX, B, BP, 1>(lat, ai, u_acc, valid, drop, wtab, tab, ln2kT, dEsum, nacc); break;
+    case 2: trial<SMAX, B, BP, 2>(lat, ai, u_acc, valid, drop, wtab, tab, ln2kT, dEsum, nacc); break;
+    default: trial<SMAX, B, BP, 3>(lat, ai, u_acc, valid, drop, wtab, tab, ln2kT, dEsum, nacc); break;
+    }
+}
+
 template <int SMAX, int B>
 __device__ __forceinline__ void trial_any(int bp, uint8_t* lat, int ai, int signs, uint32_t u_acc, bool valid, int drop,
                                           const int32_t* wtab, const double* tab, float ln2kT, int64_t& dEsum,
                                           uint32_t& nacc)
 {
-    if constexpr (B != 0) { if (bp == 0) { trial<SMAX, B, 0>(lat, ai, signs, u_acc, valid, drop, wtab, tab, ln2kT, dEsum, nacc); return; } }
-    if constexpr (B != 1) { if (bp == 1) { trial<SMAX, B, 1>(lat, ai, signs, u_acc, valid, drop, wtab, tab, ln2kT, dEsum, nacc); return; } }
-    if constexpr (B != 2) { if (bp == 2) { trial<SMAX, B, 2>(lat, ai, signs, u_acc, valid, drop, wtab, tab, ln2kT, dEsum, nacc); return; } }
-    if constexpr (B != 3) { if (bp == 3) { trial<SMAX, B, 3>(lat, ai, signs, u_acc, valid, drop, wtab, tab, ln2kT, dEsum, nacc); return; } }
+    if constexpr (B != 0) { if (bp == 0) { trial_signs<SMAX, B, 0>(signs, lat, ai, u_acc, valid, drop, wtab, tab, ln2kT, dEsum, nacc); return; } }
+    if constexpr (B != 1) { if (bp == 1) { trial_signs<SMAX, B, 1>(signs, lat, ai, u_acc, valid, drop, wtab, tab, ln2kT, dEsum, nacc); return; } }
+    if constexpr (B != 2) { if (bp == 2) { trial_signs<SMAX, B, 2>(signs, lat, ai, u_acc, valid, drop, wtab, tab, ln2kT, dEsum, nacc); return; } }
+    if constexpr (B != 3) { if (bp == 3) { trial_signs<SMAX, B, 3>(signs, lat, ai, u_acc, valid, drop, wtab, tab, ln2kT, dEsum, nacc); return; } }
 }
 
 template <int B>
