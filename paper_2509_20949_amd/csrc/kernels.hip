@@ -210,11 +210,14 @@ struct Carry {
 // Adds the accepted energy change to the lane's dEsum and the wave's
 // accepted count to nacc (the same in every lane); updates the LDS image in
 // place.
-template <int KMAX, int SMAX, int SUB, int MODE, bool CIN, bool COUT>
-__device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int e, bool valid,
-                                      const int32_t* wtab, const double* tab, float ln2kT, int64_t& dEsum,
-                                      uint32_t& nacc, Carry& cy)
+// E >= 0: the direction as a compile-time value (three shells), else e_rt.
+template <int KMAX, int SMAX, int SUB, int MODE, bool CIN, bool COUT, int E>
+__device__ __forceinline__ void trial_dir(uint8_t* lat, int ai, uint32_t u, int e_rt, bool valid,
+                                          const int32_t* wtab, const double* tab, float ln2kT, int64_t& dEsum,
+                                          uint32_t& nacc, Carry& cy)
 {
+    static_assert(SMAX < 3 || E >= 0, "three-shell trials take a compile-time direction");
+    const int e = E >= 0 ? E : e_rt;
     constexpr int F = Field<KMAX>::F;
     constexpr bool DOT = MODE == kWtabDot;
     // 5-bit fields (and the byte-dot form) hold bias + n_i - n_j without
@@ -278,16 +281,7 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int e, b
         count_outer<3, false>(lat, ai, hi, r2, r3);
         // j's counts: subtracted from i's chains in the difference form
         auto& hp = *(DIFF ? &hi : &hj);
-        switch (e) {   // wave-uniform
-        case 0: partner3<SUB, 0, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hp); break;
-        case 1: partner3<SUB, 1, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hp); break;
-        case 2: partner3<SUB, 2, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hp); break;
-        case 3: partner3<SUB, 3, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hp); break;
-        case 4: partner3<SUB, 4, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hp); break;
-        case 5: partner3<SUB, 5, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hp); break;
-        case 6: partner3<SUB, 6, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hp); break;
-        default: partner3<SUB, 7, DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hp); break;
-        }
+        partner3<SUB, (E >= 0 ? E : 0), DIFF>(lat, ai, s1, ci, r2, r3, T0, T1, cj, hp);
     }
     // Row (a, b) of the weight planes, a = ci >> 5 and b = cj >> 5, at byte
     // 4 (a*KMAX + b) of a plane.  (Lanes without a site in this round may
@@ -381,6 +375,30 @@ __device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int e, b
             cy.s1[6] = ci_new;  // the site itself
             cy.s1[7] = r2[0];   // +x
         }
+    }
+}
+
+// One trial with the round's direction e (wave-uniform).  Three-shell trials
+// switch on it before anything else: each case is then one straight-line
+// trial whose loads (the site's and the partner's cells) the compiler can
+// issue together.
+template <int KMAX, int SMAX, int SUB, int MODE, bool CIN, bool COUT>
+__device__ __forceinline__ void trial(uint8_t* lat, int ai, uint32_t u, int e, bool valid, const int32_t* wtab,
+                                      const double* tab, float ln2kT, int64_t& dEsum, uint32_t& nacc, Carry& cy)
+{
+    if constexpr (SMAX == 3) {
+        switch (e) {
+        case 0: trial_dir<KMAX, SMAX, SUB, MODE, CIN, COUT, 0>(lat, ai, u, e, valid, wtab, tab, ln2kT, dEsum, nacc, cy); break;
+        case 1: trial_dir<KMAX, SMAX, SUB, MODE, CIN, COUT, 1>(lat, ai, u, e, valid, wtab, tab, ln2kT, dEsum, nacc, cy); break;
+        case 2: trial_dir<KMAX, SMAX, SUB, MODE, CIN, COUT, 2>(lat, ai, u, e, valid, wtab, tab, ln2kT, dEsum, nacc, cy); break;
+        case 3: trial_dir<KMAX, SMAX, SUB, MODE, CIN, COUT, 3>(lat, ai, u, e, valid, wtab, tab, ln2kT, dEsum, nacc, cy); break;
+        case 4: trial_dir<KMAX, SMAX, SUB, MODE, CIN, COUT, 4>(lat, ai, u, e, valid, wtab, tab, ln2kT, dEsum, nacc, cy); break;
+        case 5: trial_dir<KMAX, SMAX, SUB, MODE, CIN, COUT, 5>(lat, ai, u, e, valid, wtab, tab, ln2kT, dEsum, nacc, cy); break;
+        case 6: trial_dir<KMAX, SMAX, SUB, MODE, CIN, COUT, 6>(lat, ai, u, e, valid, wtab, tab, ln2kT, dEsum, nacc, cy); break;
+        default: trial_dir<KMAX, SMAX, SUB, MODE, CIN, COUT, 7>(lat, ai, u, e, valid, wtab, tab, ln2kT, dEsum, nacc, cy); break;
+        }
+    } else {
+        trial_dir<KMAX, SMAX, SUB, MODE, CIN, COUT, -1>(lat, ai, u, e, valid, wtab, tab, ln2kT, dEsum, nacc, cy);
     }
 }
 
@@ -653,29 +671,40 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
             const uint32_t xb = (uint32_t)(x_bits >> (2 * m));
             const int e0 = (int)(xb & 1u) | (int)(b4 & 3u) << 1;
             const int e1 = (int)((xb >> 1) & 1u) | (int)((b4 >> 2) & 3u) << 1;
-            if (CARRY && rx != 0)   // wave-uniform
-                trial<KMAX, SMAX, 0, MODE, CARRY, CARRY>(lat, ac, uc, e0, valid, s_w, g_tab, ln2kT, dEsum, nacc, cy);
-            else
-                trial<KMAX, SMAX, 0, MODE, false, CARRY>(lat, ac, uc, e0, valid, s_w, g_tab, ln2kT, dEsum, nacc, cy);
+            if (CARRY && rx == 0) {   // wave-uniform: no carry into the first class of an x row
+#pragma unroll
+                for (int e = 0; e < 8; ++e) cy.s1[e] = lat[ac + s1off<0>(e)];
+                cy.own = lat[ac];
+            }
+            trial<KMAX, SMAX, 0, MODE, CARRY, CARRY>(lat, ac, uc, e0, valid, s_w, g_tab, ln2kT, dEsum, nacc, cy);
             __builtin_amdgcn_wave_barrier();
             trial<KMAX, SMAX, 1, MODE, CARRY, CARRY>(lat, ac + kBodyFromCorner, ub, e1, valid, s_w, g_tab, ln2kT,
                                                      dEsum, nacc, cy);
             __builtin_amdgcn_wave_barrier();
         };
+        // One copy of the round code serves all 27 classes (loops that are
+        // not unrolled): the code a wave runs per round then stays small
+        // enough for the instruction cache, which the CU's waves, each at
+        // its own round, share.  The call for the next pair is made ahead
+        // of the pair's rounds (for class 26 it is made and not used).
         uint32_t w[4] = {base_lo, base_hi, s, (uint32_t)colour};
         philox4x32_10(w, k0, k1);
-        for (int k = 0; k < 13; ++k) {
-            const uint32_t u0 = w[0], u1 = w[1], u2 = w[2], u3 = w[3];
-            // the next pair's call, issued ahead of this pair's LDS traffic
-            // (same basic block, so the scheduler can interleave the two)
+#pragma nounroll
+        for (int k = 0; k < 14; ++k) {
+            uint32_t u0 = w[0], u1 = w[1], u2 = w[2], u3 = w[3];
             w[0] = base_lo; w[1] = base_hi; w[2] = s; w[3] = (uint32_t)colour + 256u * (uint32_t)(k + 1);
             philox4x32_10(w, k0, k1);
             // partner bits of sub-colours 4k .. 4k+3: bits 8k .. 8k+7
-            const uint32_t bits = (uint32_t)(8 * k < 64 ? yz_lo >> (8 * k) : yz_hi >> (8 * k - 64));
-            rounds(2 * k, u0, u1, bits);
-            rounds(2 * k + 1, u2, u3, bits >> 4);
+            uint32_t bits = (uint32_t)(8 * k < 64 ? yz_lo >> (8 * k) : yz_hi >> (8 * k - 64));
+            const int nj = k < 13 ? 2 : 1;
+#pragma nounroll
+            for (int j = 0; j < nj; ++j) {
+                rounds(2 * k + j, u0, u1, bits);
+                u0 = u2;
+                u1 = u3;
+                bits >>= 4;
+            }
         }
-        rounds(26, w[0], w[1], (uint32_t)(yz_hi >> 40));   // bits 104 .. 107
     };
     if constexpr (KMAX <= 5) {
         if (D.drop_last == kWtabDot)
