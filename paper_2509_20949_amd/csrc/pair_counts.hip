@@ -315,6 +315,251 @@ void pair_counts_kernel(const uint8_t* __restrict__ g, int Lx, int Ly, int Lz, i
     }
 }
 
+// ---------------------------------------------------------------------------
+// BCC with K <= 5 species: bit planes.  A wavefront takes a tile of 64 x 64
+// cells of a z range: lane l holds x = x0 - 1 + l, bit b of a word pair holds
+// y = y0 - 1 + b (both wrapped; lanes 0 and 63 and bits 0 and 63 are the
+// halo, the 62 x 62 cells inside are the tile's own).  Per z plane and
+// sublattice the wave builds one 64-bit plane per species b < K - 1 (bit y
+// set iff the site at (x, y) holds b): the species' three bits are gathered
+// row by row, and each species plane is one three-input logic operation of
+// them.  A half-shell bond (cell offset d, neighbour sublattice q) then
+// counts the pairs (a, b) of 64 sites with two ANDs and two bit counts:
+// popcount(P_a(z) & shift(P_b(z + dz))), the y step a shift of the word pair,
+// the x step a lane shift (DPP), the z step one of three planes held in
+// registers.  Pairs with the last species follow from the row sums
+// sum_b N_m[a][b] = Z_m n_a (every site has Z_m neighbours in shell m).
+namespace pc {
+template <class Fn, int... Ks>
+__device__ __forceinline__ void for_each_index(Fn&& fn, std::integer_sequence<int, Ks...>)
+{
+    (fn(std::integral_constant<int, Ks>{}), ...);
+}
+constexpr int kTile = 62;                    // cells a tile owns along x and y
+constexpr int kZmBcc[3] = {8, 6, 12};        // shell sizes
+}
+
+template <int KM1>
+struct Planes {
+    uint32_t p[2][KM1 > 0 ? KM1 : 1][2];    // [sublattice][species][half]
+};
+
+// Species planes of one z plane, the plane addressed by a buffer resource:
+// row b (bit b) is row y = ystart + b (wrapped) at byte offset 2 y Lx + xo,
+// stepped row by row on the scalar unit; one row per instruction, 8 rows
+// ahead of their use.
+template <int KM1>
+__device__ __forceinline__ void build_planes(__amdgpu_buffer_rsrc_t rs, int ystart, int Ly, uint32_t row_bytes,
+                                             uint32_t xo, Planes<KM1>& P)
+{
+    int y = ystart;
+    uint32_t so = (uint32_t)ystart * row_bytes;
+    auto load = [&](int) -> uint32_t {
+        const uint32_t v = (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rs, (int)xo, (int)so, 0);
+        if (++y == Ly) {
+            y = 0;
+            so = 0;
+        } else {
+            so += row_bytes;
+        }
+        return v;
+    };
+    uint32_t S[2][3][2] = {};          // [sublattice][species bit][half]
+    constexpr int R = 8;               // rows per group
+    uint32_t c[R], cn[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) c[r] = load(r);
+#pragma unroll
+    for (int grp = 0; grp < 64 / R; ++grp) {
+        if (grp < 64 / R - 1) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) cn[r] = load(R * (grp + 1) + r);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int b = R * grp + r;
+#pragma unroll
+            for (int sub = 0; sub < 2; ++sub)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    // one v_bfe and one v_lshl_or per bit, in a chain per
+                    // word (not an OR tree, which holds every term at once)
+                    S[sub][i][b >> 5] |= ((c[r] >> (8 * sub + i)) & 1u) << (b & 31);
+                    keep(S[sub][i][b >> 5]);
+                }
+        }
+        if (grp < 64 / R - 1) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) c[r] = cn[r];
+        }
+        // keep the scheduler from hoisting later groups' loads (each would
+        // hold a register until its row is used)
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int sub = 0; sub < 2; ++sub)
+#pragma unroll
+        for (int sp = 0; sp < KM1; ++sp)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const uint32_t m0 = sp & 1 ? 0u : ~0u, m1 = sp & 2 ? 0u : ~0u, m2 = sp & 4 ? 0u : ~0u;
+                P.p[sub][sp][h] = (S[sub][0][h] ^ m0) & (S[sub][1][h] ^ m1) & (S[sub][2][h] ^ m2);
+            }
+}
+
+// The word pair w shifted so that bit y holds bit y + DY (DY = -1, 0, 1).
+template <int DY> __device__ __forceinline__ void yshift(uint32_t& lo, uint32_t& hi)
+{
+    if constexpr (DY == 1) {
+        lo = __builtin_amdgcn_alignbit(hi, lo, 1);
+        hi = hi >> 1;
+    } else if constexpr (DY == -1) {
+        hi = __builtin_amdgcn_alignbit(hi, lo, 31);
+        lo = lo << 1;
+    }
+}
+// The value of lane l + DX in lane l (DX = -1, 0, 1; wavefront shifts).
+template <int DX> __device__ __forceinline__ uint32_t xshift(uint32_t v)
+{
+    if constexpr (DX == 1) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xf, 0xf, true);
+    else if constexpr (DX == -1) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xf, 0xf, true);
+    else return v;
+}
+
+template <int KM1, int SMAX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+void pair_counts_bcc_planes_kernel(const uint8_t* __restrict__ g, int Lx, int Ly, int Lz, int ntx, int nty, int zc,
+                                   uint32_t n_items, unsigned long long* __restrict__ counts)
+{
+    using T = pc::Tables<0>;
+    const int lane = threadIdx.x % kWave;
+    const int grp = xcd_group((int)gridDim.x);
+    if (grp < 0) return;   // no barriers in this kernel
+    const uint32_t item = (uint32_t)grp * (blockDim.x / kWave) + (uint32_t)wave_id();
+    if (item >= n_items) return;
+    const int tx = (int)(item % (uint32_t)ntx), ty = (int)((item / (uint32_t)ntx) % (uint32_t)nty);
+    const int zi = (int)(item / ((uint32_t)ntx * (uint32_t)nty));
+    const int x0 = tx * pc::kTile, y0 = ty * pc::kTile;
+    const int zb = zi * zc, ze = min(Lz, zb + zc);
+    const int wx = min(pc::kTile, Lx - x0), wy = min(pc::kTile, Ly - y0);
+    const int xl = (x0 - 1 + lane + Lx) % Lx;
+    const int ystart = (y0 - 1 + Ly) % Ly;
+    const uint32_t row_bytes = 2u * (uint32_t)Lx;
+    const uint32_t xo = 2u * (uint32_t)xl;
+    // the tile's own sites: lanes 1..wx, bits 1..wy
+    const uint32_t xmask = (lane >= 1 && lane <= wx) ? ~0u : 0u;
+    const uint64_t ym = (wy >= 63 ? ~0ull : ((1ull << (wy + 1)) - 1)) & ~1ull;
+    const uint32_t ymask[2] = {(uint32_t)ym & xmask, (uint32_t)(ym >> 32) & xmask};
+    const uint64_t plane = 2ull * (uint32_t)Lx * (uint32_t)Ly;   // bytes per z plane (< 2^32: checked on launch)
+    auto zrsrc = [&](int z) {
+        z = z < 0 ? z + Lz : (z >= Lz ? z - Lz : z);
+        return byte_rsrc((uint8_t*)g + (uint64_t)z * plane, plane);
+    };
+
+    Planes<KM1> W0, W1, W2;   // planes z - 1, z, z + 1
+    build_planes<KM1>(zrsrc(zb - 1), ystart, Ly, row_bytes, xo, W0);
+    build_planes<KM1>(zrsrc(zb), ystart, Ly, row_bytes, xo, W1);
+    uint32_t acc[SMAX][KM1 > 0 ? KM1 : 1][KM1 > 0 ? KM1 : 1] = {};
+    uint32_t nsp[KM1 > 0 ? KM1 : 1] = {};
+#pragma nounroll
+    for (int z = zb; z < ze; ++z) {
+        build_planes<KM1>(zrsrc(z + 1), ystart, Ly, row_bytes, xo, W2);
+        const Planes<KM1>* Wz[3] = {&W0, &W1, &W2};
+        auto centre = [&](auto sc) {
+            constexpr int s = decltype(sc)::value;
+            uint32_t C[KM1 > 0 ? KM1 : 1][2];
+#pragma unroll
+            for (int a = 0; a < KM1; ++a) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    C[a][h] = W1.p[s][a][h] & ymask[h];
+                    nsp[a] += (uint32_t)__popc(C[a][h]);
+                }
+            }
+            auto shell = [&](auto mc) {
+                constexpr int m = decltype(mc)::value;
+                if constexpr (m < SMAX) {
+                    auto bond = [&](auto kc) {
+                        constexpr int k = decltype(kc)::value;
+                        constexpr int o = T::bonds.b[s][m][k].cell, q = T::bonds.b[s][m][k].sub;
+                        constexpr int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+                        const Planes<KM1>& N = *Wz[dz + 1];
+#pragma unroll
+                        for (int b = 0; b < KM1; ++b) {
+                            uint32_t lo = N.p[q][b][0], hi = N.p[q][b][1];
+                            yshift<dy>(lo, hi);
+                            lo = xshift<dx>(lo);
+                            hi = xshift<dx>(hi);
+#pragma unroll
+                            for (int a = 0; a < KM1; ++a)
+                                acc[m][a][b] += (uint32_t)__popc(C[a][0] & lo) + (uint32_t)__popc(C[a][1] & hi);
+                        }
+                    };
+                    pc::for_each_index(bond, std::make_integer_sequence<int, T::bonds.n[s][m]>{});
+                }
+            };
+            shell(std::integral_constant<int, 0>{});
+            shell(std::integral_constant<int, 1>{});
+            shell(std::integral_constant<int, 2>{});
+        };
+        centre(std::integral_constant<int, 0>{});
+        centre(std::integral_constant<int, 1>{});
+        W0 = W1;
+        W1 = W2;
+    }
+
+    // wave sums, then this wave's share of every N_m[a][b] into copy
+    // item % kCountSlots (two's-complement adds: a share may be negative,
+    // the totals are exact)
+    auto wsum = [&](uint32_t v) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o, kWave);
+        return v;
+    };
+    int64_t n[KM1 > 0 ? KM1 : 1];
+    int64_t nlast = 2ll * wx * wy * (ze - zb);   // sites of the tile and z range
+#pragma unroll
+    for (int a = 0; a < KM1; ++a) {
+        n[a] = (int64_t)wsum(nsp[a]);
+        nlast -= n[a];
+    }
+    constexpr int L = KM1;   // the last species
+    unsigned long long* out = counts + (item % kCountSlots) * kCountWords;
+    auto add = [&](int m, int a, int b, int64_t v) {
+        if (v != 0) atomicAdd(&out[(m * kMaxK + a) * kMaxK + b], (unsigned long long)v);
+    };
+#pragma unroll
+    for (int m = 0; m < SMAX; ++m) {
+        int64_t B[KM1 > 0 ? KM1 : 1][KM1 > 0 ? KM1 : 1];
+#pragma unroll
+        for (int a = 0; a < KM1; ++a)
+#pragma unroll
+            for (int b = 0; b < KM1; ++b) B[a][b] = (int64_t)wsum(acc[m][a][b]);
+        if (lane == 0) {
+            const int64_t Z = pc::kZmBcc[m];
+            int64_t lastrow = Z * nlast;
+#pragma unroll
+            for (int a = 0; a < KM1; ++a) {
+                int64_t row = 0;
+#pragma unroll
+                for (int b = 0; b < KM1; ++b) {
+                    const int64_t v = B[a][b] + B[b][a];
+                    row += v;
+                    if (b >= a) {
+                        add(m, a, b, v);
+                        if (b > a) add(m, b, a, v);
+                    }
+                }
+                const int64_t vl = Z * n[a] - row;   // N_m[a][last]
+                add(m, a, L, vl);
+                add(m, L, a, vl);
+                lastrow -= vl;
+            }
+            add(m, L, L, lastrow);
+        }
+    }
+}
+
 template <int LAT, int F>
 static hipError_t launch_pc(const uint8_t* species, const int32_t L[3], int K, int S, unsigned long long* d_counts,
                             hipStream_t stream)
@@ -345,6 +590,46 @@ static hipError_t launch_pc(const uint8_t* species, const int32_t L[3], int K, i
     return hipGetLastError();
 }
 
+// BCC, 2 <= K <= 5: the bit-plane kernel.  Work items are (x tile, y tile,
+// z range); the z ranges are sized so that the launch has about 3,000
+// wavefronts (three per SIMD), each with at least 4 planes.
+static hipError_t launch_planes(const uint8_t* species, const int32_t L[3], int K, int S,
+                                unsigned long long* d_counts, hipStream_t stream)
+{
+    const int ntx = (L[0] + pc::kTile - 1) / pc::kTile, nty = (L[1] + pc::kTile - 1) / pc::kTile;
+    const uint64_t tiles = (uint64_t)ntx * (uint64_t)nty;
+    const uint64_t target = 3072;
+    uint64_t zc = (tiles * (uint64_t)L[2] + target - 1) / target;
+    zc = std::max<uint64_t>(zc, 4);
+    zc = std::min<uint64_t>(zc, (uint64_t)L[2]);
+    const uint64_t nz = ((uint64_t)L[2] + zc - 1) / zc;
+    const uint64_t items = tiles * nz;
+    if (items > 0x7fffffffull) return hipErrorInvalidValue;
+    const int waves_per_group = 4;
+    const uint64_t groups = (items + waves_per_group - 1) / waves_per_group;
+    const dim3 grid((unsigned)xcd_grid((int)groups)), block((unsigned)(waves_per_group * kWave));
+#define SMCX_PC_PLANES(KM1, SM)                                                                                    \
+    hipLaunchKernelGGL((pair_counts_bcc_planes_kernel<KM1, SM>), grid, block, 0, stream, species, L[0], L[1], L[2], \
+                       ntx, nty, (int)zc, (uint32_t)items, d_counts)
+    switch ((K - 1) * 4 + S) {
+    case 1 * 4 + 1: SMCX_PC_PLANES(1, 1); break;
+    case 1 * 4 + 2: SMCX_PC_PLANES(1, 2); break;
+    case 1 * 4 + 3: SMCX_PC_PLANES(1, 3); break;
+    case 2 * 4 + 1: SMCX_PC_PLANES(2, 1); break;
+    case 2 * 4 + 2: SMCX_PC_PLANES(2, 2); break;
+    case 2 * 4 + 3: SMCX_PC_PLANES(2, 3); break;
+    case 3 * 4 + 1: SMCX_PC_PLANES(3, 1); break;
+    case 3 * 4 + 2: SMCX_PC_PLANES(3, 2); break;
+    case 3 * 4 + 3: SMCX_PC_PLANES(3, 3); break;
+    case 4 * 4 + 1: SMCX_PC_PLANES(4, 1); break;
+    case 4 * 4 + 2: SMCX_PC_PLANES(4, 2); break;
+    case 4 * 4 + 3: SMCX_PC_PLANES(4, 3); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef SMCX_PC_PLANES
+    return hipGetLastError();
+}
+
 // d_counts (kCountSlots copies of [kMaxS][kMaxK][kMaxK] uint64) receives
 // N_m[p'][p] added to what it holds, split over the copies; the caller
 // clears it first and sums the copies (count_sum).
@@ -354,6 +639,8 @@ hipError_t launch_pair_counts(int lattice, const uint8_t* species, const int32_t
     if (K < 1 || K > kMaxK || S < 1 || S > kMaxS) return hipErrorInvalidValue;
     if (lattice == 1) return K <= 4 ? launch_pc<1, 8>(species, L, K, S, d_counts, stream)
                                     : launch_pc<1, 4>(species, L, K, S, d_counts, stream);
+    if (K >= 2 && K <= 5 && 2ull * (uint32_t)L[0] * (uint32_t)L[1] < (1ull << 32))
+        return launch_planes(species, L, K, S, d_counts, stream);
     return K <= 4 ? launch_pc<0, 8>(species, L, K, S, d_counts, stream)
                   : launch_pc<0, 4>(species, L, K, S, d_counts, stream);
 }
