@@ -316,46 +316,103 @@ void pair_counts_kernel(const uint8_t* __restrict__ g, int Lx, int Ly, int Lz, i
 }
 
 // ---------------------------------------------------------------------------
-// BCC with K <= 5 species: bit planes.  A wavefront takes a tile of 64 x 64
-// cells of a z range: lane l holds x = x0 - 1 + l, bit b of a word pair holds
-// y = y0 - 1 + b (both wrapped; lanes 0 and 63 and bits 0 and 63 are the
-// halo, the 62 x 62 cells inside are the tile's own).  Per z plane and
-// sublattice the wave builds one 64-bit plane per species b < K - 1 (bit y
-// set iff the site at (x, y) holds b): the species' three bits are gathered
-// row by row, and each species plane is one three-input logic operation of
-// them.  A half-shell bond (cell offset d, neighbour sublattice q) then
-// counts the pairs (a, b) of 64 sites with two ANDs and two bit counts:
-// popcount(P_a(z) & shift(P_b(z + dz))), the y step a shift of the word pair,
-// the x step a lane shift (DPP), the z step one of three planes held in
-// registers.  Pairs with the last species follow from the row sums
-// sum_b N_m[a][b] = Z_m n_a (every site has Z_m neighbours in shell m).
+// K <= 5 species (BCC and FCC): bit planes.  A wavefront takes a tile of
+// 64 x 64 cells of a z range: lane l holds x = x0 - 1 + l, bit b of a word
+// pair holds y = y0 - 1 + b (both wrapped; lanes 0 and 63 and bits 0 and 63
+// are the halo, the 62 x 62 cells inside are the tile's own).  Per z plane
+// and sublattice the wave builds one 64-bit plane per species b < K - 1
+// (bit y set iff the site at (x, y) holds b): the species' three bits are
+// gathered row by row, and each species plane is one three-input logic
+// operation of them.  A half-shell bond (cell offset d, neighbour sublattice
+// q) then counts the pairs (a, b) of 64 sites with two ANDs and two bit
+// counts, popcount(P_a(z) & shift(P_b(z + dz))): the y step a shift of the
+// word pair, the x step a lane shift (DPP), the z step one of two planes
+// held in registers.  The half shells here are the vectors whose first
+// nonzero component in the order z, y, x is positive, so every bond reaches
+// the same z plane or the next (dz = 0 or 1).  Pairs with the last species
+// follow from the row sums sum_b N_m[a][b] = Z_m n_a (every site has Z_m
+// neighbours in shell m).
 namespace pc {
 template <class Fn, int... Ks>
 __device__ __forceinline__ void for_each_index(Fn&& fn, std::integer_sequence<int, Ks...>)
 {
     (fn(std::integral_constant<int, Ks>{}), ...);
 }
-constexpr int kTile = 62;                    // cells a tile owns along x and y
-constexpr int kZmBcc[3] = {8, 6, 12};        // shell sizes
-}
+constexpr int kTile = 62;   // cells a tile owns along x and y
+constexpr int kZm[2][3] = {{8, 6, 12}, {12, 6, 24}};   // shell sizes, BCC and FCC
 
-template <int KM1>
+// Half-shell bonds with the z-first rule: neighbour cell offset (dx, dy in
+// -1..1, dz in 0..1) and sublattice.
+struct ZBond {
+    int dx, dy, dz, sub;
+};
+struct ZBonds {
+    int n[4][3];
+    ZBond b[4][3][12];
+};
+constexpr ZBonds make_zbonds(const Geo g)
+{
+    ZBonds r{};
+    for (int b = 0; b < g.nsub; ++b)
+        for (int m = 0; m < 3; ++m) {
+            int n = 0;
+            for (int k = 0; k < g.nvec[m]; ++k) {
+                const int* v = g.vec[m][k];
+                const int first = v[2] != 0 ? v[2] : (v[1] != 0 ? v[1] : v[0]);
+                if (first < 0) continue;   // the other half: B^T
+                int cd[3] = {0, 0, 0}, par[3] = {0, 0, 0};
+                for (int a = 0; a < 3; ++a) {
+                    const int t = g.sub[b][a] + v[a];
+                    cd[a] = fdiv2(t);
+                    par[a] = t - 2 * cd[a];
+                }
+                int bp = -1;
+                for (int q = 0; q < g.nsub; ++q)
+                    if (g.sub[q][0] == par[0] && g.sub[q][1] == par[1] && g.sub[q][2] == par[2]) bp = q;
+                r.b[b][m][n] = ZBond{cd[0], cd[1], cd[2], bp};
+                ++n;
+            }
+            r.n[b][m] = n;
+        }
+    return r;
+}
+template <int LAT> struct ZTables {
+    static constexpr Geo geo = LAT == 1 ? fcc_geo() : bcc_geo();
+    static constexpr ZBonds bonds = make_zbonds(geo);
+};
+constexpr bool zbonds_ok(const ZBonds& r, int nsub)
+{
+    for (int b = 0; b < nsub; ++b)
+        for (int m = 0; m < 3; ++m)
+            for (int k = 0; k < r.n[b][m]; ++k) {
+                const ZBond& d = r.b[b][m][k];
+                if (d.dx < -1 || d.dx > 1 || d.dy < -1 || d.dy > 1 || d.dz < 0 || d.dz > 1 || d.sub < 0) return false;
+            }
+    return true;
+}
+static_assert(zbonds_ok(ZTables<0>::bonds, 2) && zbonds_ok(ZTables<1>::bonds, 4), "z-first half shells");
+static_assert(ZTables<0>::bonds.n[0][0] + ZTables<0>::bonds.n[1][0] == 8, "BCC: 8 first-shell bonds per cell");
+static_assert(ZTables<1>::bonds.n[0][2] + ZTables<1>::bonds.n[3][2] == 24, "FCC: 12 third-shell bonds per site");
+}  // namespace pc
+
+template <int NSUB, int KM1>
 struct Planes {
-    uint32_t p[2][KM1 > 0 ? KM1 : 1][2];    // [sublattice][species][half]
+    uint32_t p[NSUB][KM1 > 0 ? KM1 : 1][2];   // [sublattice][species][half]
 };
 
 // Species planes of one z plane, the plane addressed by a buffer resource:
-// row b (bit b) is row y = ystart + b (wrapped) at byte offset 2 y Lx + xo,
-// stepped row by row on the scalar unit; one row per instruction, 8 rows
+// row b (bit b) is row y = ystart + b (wrapped) at byte offset NSUB y Lx +
+// xo, stepped row by row on the scalar unit; one row per instruction, 8 rows
 // ahead of their use.
-template <int KM1>
+template <int NSUB, int KM1>
 __device__ __forceinline__ void build_planes(__amdgpu_buffer_rsrc_t rs, int ystart, int Ly, uint32_t row_bytes,
-                                             uint32_t xo, Planes<KM1>& P)
+                                             uint32_t xo, Planes<NSUB, KM1>& P)
 {
     int y = ystart;
     uint32_t so = (uint32_t)ystart * row_bytes;
     auto load = [&](int) -> uint32_t {
-        const uint32_t v = (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rs, (int)xo, (int)so, 0);
+        const uint32_t v = NSUB == 4 ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)xo, (int)so, 0)
+                                     : (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rs, (int)xo, (int)so, 0);
         if (++y == Ly) {
             y = 0;
             so = 0;
@@ -364,8 +421,8 @@ __device__ __forceinline__ void build_planes(__amdgpu_buffer_rsrc_t rs, int ysta
         }
         return v;
     };
-    uint32_t S[2][3][2] = {};          // [sublattice][species bit][half]
-    constexpr int R = 8;               // rows per group
+    uint32_t S[NSUB][3][2] = {};   // [sublattice][species bit][half]
+    constexpr int R = 8;           // rows per group
     uint32_t c[R], cn[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) c[r] = load(r);
@@ -379,7 +436,7 @@ __device__ __forceinline__ void build_planes(__amdgpu_buffer_rsrc_t rs, int ysta
         for (int r = 0; r < R; ++r) {
             const int b = R * grp + r;
 #pragma unroll
-            for (int sub = 0; sub < 2; ++sub)
+            for (int sub = 0; sub < NSUB; ++sub)
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
                     // one v_bfe and one v_lshl_or per bit, in a chain per
@@ -397,7 +454,7 @@ __device__ __forceinline__ void build_planes(__amdgpu_buffer_rsrc_t rs, int ysta
         __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
-    for (int sub = 0; sub < 2; ++sub)
+    for (int sub = 0; sub < NSUB; ++sub)
 #pragma unroll
         for (int sp = 0; sp < KM1; ++sp)
 #pragma unroll
@@ -407,7 +464,7 @@ __device__ __forceinline__ void build_planes(__amdgpu_buffer_rsrc_t rs, int ysta
             }
 }
 
-// The word pair w shifted so that bit y holds bit y + DY (DY = -1, 0, 1).
+// The word pair shifted so that bit y holds bit y + DY (DY = -1, 0, 1).
 template <int DY> __device__ __forceinline__ void yshift(uint32_t& lo, uint32_t& hi)
 {
     if constexpr (DY == 1) {
@@ -426,12 +483,17 @@ template <int DX> __device__ __forceinline__ uint32_t xshift(uint32_t v)
     else return v;
 }
 
-template <int KM1, int SMAX>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
-void pair_counts_bcc_planes_kernel(const uint8_t* __restrict__ g, int Lx, int Ly, int Lz, int ntx, int nty, int zc,
-                                   uint32_t n_items, unsigned long long* __restrict__ counts)
+// Waves per SIMD: 3 (BCC), 2 (FCC: four sublattices' planes in registers).
+template <int LAT> constexpr int kPlanesWaves = LAT == 1 ? 2 : 3;
+
+template <int LAT, int KM1, int SMAX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPlanesWaves<LAT>)))
+void pair_counts_planes_kernel(const uint8_t* __restrict__ g, int Lx, int Ly, int Lz, int ntx, int nty, int zc,
+                               uint32_t n_items, unsigned long long* __restrict__ counts)
 {
-    using T = pc::Tables<0>;
+    using T = pc::ZTables<LAT>;
+    constexpr int NSUB = T::geo.nsub;
+    constexpr int KA = KM1 > 0 ? KM1 : 1;
     const int lane = threadIdx.x % kWave;
     const int grp = xcd_group((int)gridDim.x);
     if (grp < 0) return;   // no barriers in this kernel
@@ -444,35 +506,33 @@ void pair_counts_bcc_planes_kernel(const uint8_t* __restrict__ g, int Lx, int Ly
     const int wx = min(pc::kTile, Lx - x0), wy = min(pc::kTile, Ly - y0);
     const int xl = (x0 - 1 + lane + Lx) % Lx;
     const int ystart = (y0 - 1 + Ly) % Ly;
-    const uint32_t row_bytes = 2u * (uint32_t)Lx;
-    const uint32_t xo = 2u * (uint32_t)xl;
+    const uint32_t row_bytes = (uint32_t)NSUB * (uint32_t)Lx;
+    const uint32_t xo = (uint32_t)NSUB * (uint32_t)xl;
     // the tile's own sites: lanes 1..wx, bits 1..wy
     const uint32_t xmask = (lane >= 1 && lane <= wx) ? ~0u : 0u;
-    const uint64_t ym = (wy >= 63 ? ~0ull : ((1ull << (wy + 1)) - 1)) & ~1ull;
+    const uint64_t ym = ((1ull << (wy + 1)) - 1) & ~1ull;
     const uint32_t ymask[2] = {(uint32_t)ym & xmask, (uint32_t)(ym >> 32) & xmask};
-    const uint64_t plane = 2ull * (uint32_t)Lx * (uint32_t)Ly;   // bytes per z plane (< 2^32: checked on launch)
+    const uint64_t plane = (uint64_t)NSUB * (uint32_t)Lx * (uint32_t)Ly;   // bytes per z plane (< 2^32: checked on launch)
     auto zrsrc = [&](int z) {
-        z = z < 0 ? z + Lz : (z >= Lz ? z - Lz : z);
+        z = z >= Lz ? z - Lz : z;
         return byte_rsrc((uint8_t*)g + (uint64_t)z * plane, plane);
     };
 
-    Planes<KM1> W0, W1, W2;   // planes z - 1, z, z + 1
-    build_planes<KM1>(zrsrc(zb - 1), ystart, Ly, row_bytes, xo, W0);
-    build_planes<KM1>(zrsrc(zb), ystart, Ly, row_bytes, xo, W1);
-    uint32_t acc[SMAX][KM1 > 0 ? KM1 : 1][KM1 > 0 ? KM1 : 1] = {};
-    uint32_t nsp[KM1 > 0 ? KM1 : 1] = {};
+    Planes<NSUB, KM1> W0, W1;   // planes z and z + 1
+    build_planes<NSUB, KM1>(zrsrc(zb), ystart, Ly, row_bytes, xo, W0);
+    uint32_t acc[SMAX][KA][KA] = {};
+    uint32_t nsp[KA] = {};
 #pragma nounroll
     for (int z = zb; z < ze; ++z) {
-        build_planes<KM1>(zrsrc(z + 1), ystart, Ly, row_bytes, xo, W2);
-        const Planes<KM1>* Wz[3] = {&W0, &W1, &W2};
+        build_planes<NSUB, KM1>(zrsrc(z + 1), ystart, Ly, row_bytes, xo, W1);
         auto centre = [&](auto sc) {
             constexpr int s = decltype(sc)::value;
-            uint32_t C[KM1 > 0 ? KM1 : 1][2];
+            uint32_t C[KA][2];
 #pragma unroll
             for (int a = 0; a < KM1; ++a) {
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    C[a][h] = W1.p[s][a][h] & ymask[h];
+                    C[a][h] = W0.p[s][a][h] & ymask[h];
                     nsp[a] += (uint32_t)__popc(C[a][h]);
                 }
             }
@@ -481,19 +541,22 @@ void pair_counts_bcc_planes_kernel(const uint8_t* __restrict__ g, int Lx, int Ly
                 if constexpr (m < SMAX) {
                     auto bond = [&](auto kc) {
                         constexpr int k = decltype(kc)::value;
-                        constexpr int o = T::bonds.b[s][m][k].cell, q = T::bonds.b[s][m][k].sub;
-                        constexpr int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
-                        const Planes<KM1>& N = *Wz[dz + 1];
+                        constexpr pc::ZBond d = T::bonds.b[s][m][k];
+                        const Planes<NSUB, KM1>& N = d.dz ? W1 : W0;
 #pragma unroll
                         for (int b = 0; b < KM1; ++b) {
-                            uint32_t lo = N.p[q][b][0], hi = N.p[q][b][1];
-                            yshift<dy>(lo, hi);
-                            lo = xshift<dx>(lo);
-                            hi = xshift<dx>(hi);
+                            uint32_t lo = N.p[d.sub][b][0], hi = N.p[d.sub][b][1];
+                            yshift<d.dy>(lo, hi);
+                            lo = xshift<d.dx>(lo);
+                            hi = xshift<d.dx>(hi);
 #pragma unroll
                             for (int a = 0; a < KM1; ++a)
                                 acc[m][a][b] += (uint32_t)__popc(C[a][0] & lo) + (uint32_t)__popc(C[a][1] & hi);
                         }
+                        // one bond at a time (its 2 (K - 1)^2 ANDs and bit
+                        // counts are independent work enough): shifted planes
+                        // of later bonds are not computed ahead
+                        __builtin_amdgcn_sched_barrier(0);
                     };
                     pc::for_each_index(bond, std::make_integer_sequence<int, T::bonds.n[s][m]>{});
                 }
@@ -502,10 +565,8 @@ void pair_counts_bcc_planes_kernel(const uint8_t* __restrict__ g, int Lx, int Ly
             shell(std::integral_constant<int, 1>{});
             shell(std::integral_constant<int, 2>{});
         };
-        centre(std::integral_constant<int, 0>{});
-        centre(std::integral_constant<int, 1>{});
+        pc::for_each_index(centre, std::make_integer_sequence<int, NSUB>{});
         W0 = W1;
-        W1 = W2;
     }
 
     // wave sums, then this wave's share of every N_m[a][b] into copy
@@ -516,8 +577,8 @@ void pair_counts_bcc_planes_kernel(const uint8_t* __restrict__ g, int Lx, int Ly
         for (int o = 32; o >= 1; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o, kWave);
         return v;
     };
-    int64_t n[KM1 > 0 ? KM1 : 1];
-    int64_t nlast = 2ll * wx * wy * (ze - zb);   // sites of the tile and z range
+    int64_t n[KA];
+    int64_t nlast = (int64_t)NSUB * wx * wy * (ze - zb);   // sites of the tile and z range
 #pragma unroll
     for (int a = 0; a < KM1; ++a) {
         n[a] = (int64_t)wsum(nsp[a]);
@@ -530,13 +591,13 @@ void pair_counts_bcc_planes_kernel(const uint8_t* __restrict__ g, int Lx, int Ly
     };
 #pragma unroll
     for (int m = 0; m < SMAX; ++m) {
-        int64_t B[KM1 > 0 ? KM1 : 1][KM1 > 0 ? KM1 : 1];
+        int64_t B[KA][KA];
 #pragma unroll
         for (int a = 0; a < KM1; ++a)
 #pragma unroll
             for (int b = 0; b < KM1; ++b) B[a][b] = (int64_t)wsum(acc[m][a][b]);
         if (lane == 0) {
-            const int64_t Z = pc::kZmBcc[m];
+            const int64_t Z = pc::kZm[LAT][m];
             int64_t lastrow = Z * nlast;
 #pragma unroll
             for (int a = 0; a < KM1; ++a) {
@@ -590,15 +651,17 @@ static hipError_t launch_pc(const uint8_t* species, const int32_t L[3], int K, i
     return hipGetLastError();
 }
 
-// BCC, 2 <= K <= 5: the bit-plane kernel.  Work items are (x tile, y tile,
-// z range); the z ranges are sized so that the launch has about 3,000
-// wavefronts (three per SIMD), each with at least 4 planes.
+// 2 <= K <= 5: the bit-plane kernel.  Work items are (x tile, y tile,
+// z range); the z ranges are sized so that the launch has about one
+// wavefront per wave slot of the chip (1,024 SIMDs x kPlanesWaves), each
+// with at least 4 planes.
+template <int LAT>
 static hipError_t launch_planes(const uint8_t* species, const int32_t L[3], int K, int S,
                                 unsigned long long* d_counts, hipStream_t stream)
 {
     const int ntx = (L[0] + pc::kTile - 1) / pc::kTile, nty = (L[1] + pc::kTile - 1) / pc::kTile;
     const uint64_t tiles = (uint64_t)ntx * (uint64_t)nty;
-    const uint64_t target = 3072;
+    const uint64_t target = 1024 * kPlanesWaves<LAT>;
     uint64_t zc = (tiles * (uint64_t)L[2] + target - 1) / target;
     zc = std::max<uint64_t>(zc, 4);
     zc = std::min<uint64_t>(zc, (uint64_t)L[2]);
@@ -609,7 +672,7 @@ static hipError_t launch_planes(const uint8_t* species, const int32_t L[3], int 
     const uint64_t groups = (items + waves_per_group - 1) / waves_per_group;
     const dim3 grid((unsigned)xcd_grid((int)groups)), block((unsigned)(waves_per_group * kWave));
 #define SMCX_PC_PLANES(KM1, SM)                                                                                    \
-    hipLaunchKernelGGL((pair_counts_bcc_planes_kernel<KM1, SM>), grid, block, 0, stream, species, L[0], L[1], L[2], \
+    hipLaunchKernelGGL((pair_counts_planes_kernel<LAT, KM1, SM>), grid, block, 0, stream, species, L[0], L[1], L[2], \
                        ntx, nty, (int)zc, (uint32_t)items, d_counts)
     switch ((K - 1) * 4 + S) {
     case 1 * 4 + 1: SMCX_PC_PLANES(1, 1); break;
@@ -637,10 +700,12 @@ hipError_t launch_pair_counts(int lattice, const uint8_t* species, const int32_t
                               unsigned long long* d_counts, hipStream_t stream)
 {
     if (K < 1 || K > kMaxK || S < 1 || S > kMaxS) return hipErrorInvalidValue;
+    const uint64_t plane_bytes = (lattice == 1 ? 4ull : 2ull) * (uint32_t)L[0] * (uint32_t)L[1];
+    if (K >= 2 && K <= 5 && plane_bytes < (1ull << 32))
+        return lattice == 1 ? launch_planes<1>(species, L, K, S, d_counts, stream)
+                            : launch_planes<0>(species, L, K, S, d_counts, stream);
     if (lattice == 1) return K <= 4 ? launch_pc<1, 8>(species, L, K, S, d_counts, stream)
                                     : launch_pc<1, 4>(species, L, K, S, d_counts, stream);
-    if (K >= 2 && K <= 5 && 2ull * (uint32_t)L[0] * (uint32_t)L[1] < (1ull << 32))
-        return launch_planes(species, L, K, S, d_counts, stream);
     return K <= 4 ? launch_pc<0, 8>(species, L, K, S, d_counts, stream)
                   : launch_pc<0, 4>(species, L, K, S, d_counts, stream);
 }
