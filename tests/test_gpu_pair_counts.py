@@ -2,7 +2,8 @@
 Warren-Cowley SRO, Eq. (SRO)) on lattices of 2^22 cells and more, where the
 library counts with bit planes: equal to the oracle's counts entry by entry,
 with ragged x/y tiles, a z extent that leaves a short last z range, both
-lattices, and a composition with an absent species."""
+lattices, a composition with an absent species, and lattices narrower than
+a tile (rows or x cells that wrap within one tile)."""
 import sys
 
 import numpy as np
@@ -37,6 +38,10 @@ CASES = [
     (BCC, (124, 186, 190), 5, 3, np.array([0.5, 0.3, 0.0, 0.15, 0.05])),
     (FCC, (130, 132, 250), 5, 3, None),
     (FCC, (200, 150, 141), 4, 2, None),
+    # fewer rows than a tile's 64 bits (rows wrap several times in a word),
+    # and fewer cells along x than a wavefront's lanes
+    (BCC, (40000, 8, 14), 5, 3, None),
+    (FCC, (6, 600, 1200), 5, 3, None),
 ]
 
 
