@@ -35,9 +35,9 @@ __device__ __forceinline__ void keep(uint32_t& h) { asm("" : "+v"(h)); }
 // Add +1 (NEG: -1) in the field of code c to h: one v_lshl_add_u32, whose
 // shift takes the low 5 bits of c.  Written out, so that no mask of c is
 // materialised: the compiler folds c & 31 into the shift only when both sit
-// in one basic block, and the sweep kernels count codes in partner-specific
-// blocks that were loaded before the branch to them.  (The instruction also
-// keeps each count a chain of shift-adds, as keep() does.)
+// in one basic block, and the sweep kernels count codes that were loaded in
+// other blocks (codes carried from the previous trial, in a loop).  (The
+// instruction also keeps each count a chain of shift-adds, as keep() does.)
 template <bool NEG> __device__ __forceinline__ void count1(uint32_t& h, uint32_t c)
 {
     if constexpr (NEG) asm("v_lshl_add_u32 %0, -1, %1, %0" : "+v"(h) : "v"(c));
