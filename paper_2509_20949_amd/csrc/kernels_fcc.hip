@@ -57,21 +57,6 @@ constexpr int offset(int b, int dx, int dy, int dz)
     return off;
 }
 
-struct Offsets {
-    int s1[12], s2[6], s3[24];
-};
-
-constexpr Offsets make_offsets(int b)
-{
-    Offsets o{};
-    for (int k = 0; k < 12; ++k) o.s1[k] = offset(b, SH1[k][0], SH1[k][1], SH1[k][2]);
-    for (int k = 0; k < 6; ++k) o.s2[k] = offset(b, SH2[k][0], SH2[k][1], SH2[k][2]);
-    for (int k = 0; k < 24; ++k) o.s3[k] = offset(b, SH3[k][0], SH3[k][1], SH3[k][2]);
-    return o;
-}
-
-template <int B> struct Off { static constexpr Offsets v = make_offsets(B); };
-
 // The two axes on which sublattices B and BP differ.
 constexpr int axis1(int B, int BP) { return SUB[B][0] != SUB[BP][0] ? 0 : 1; }
 constexpr int axis2(int B, int BP) { return SUB[B][2] != SUB[BP][2] ? 2 : 1; }
@@ -140,36 +125,6 @@ constexpr DiffCells make_diff(int B, int BP, int SG, int S)
 }
 
 template <int B, int BP, int SG, int S> struct Diff { static constexpr DiffCells v = make_diff(B, BP, SG, S); };
-
-// Packed species counts of the neighbours of the site at LDS byte a, one
-// word per shell, added to h.  Each shell is summed in NC short chains of
-// shift-adds (kept apart by keep(), so each step stays one v_lshl_add),
-// joined at the end: short dependency chains, one instruction per neighbour.
-template <int N, int NC>
-__device__ __forceinline__ uint32_t count_shell(const uint8_t* lat, int a, const int (&off)[N], uint32_t h)
-{
-    uint32_t c[NC];
-#pragma unroll
-    for (int j = 0; j < NC; ++j) c[j] = j == 0 ? h : 0u;
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        c[k % NC] += 1u << (lat[a + off[k]] & 31u);
-        keep(c[k % NC]);
-    }
-    uint32_t t = c[0];
-#pragma unroll
-    for (int j = 1; j < NC; ++j) t += c[j];
-    return t;
-}
-
-template <int SMAX, int B>
-__device__ __forceinline__ void histogram(const uint8_t* lat, int a, uint32_t (&h)[kMaxS])
-{
-    constexpr Offsets O = Off<B>::v;
-    h[0] = count_shell<12, 3>(lat, a, O.s1, h[0]);
-    if constexpr (SMAX >= 2) h[1] = count_shell<6, 2>(lat, a, O.s2, h[1]);
-    if constexpr (SMAX >= 3) h[2] = count_shell<24, 4>(lat, a, O.s3, h[2]);
-}
 
 // Species fields: 6 bits each (up to 24 neighbours per shell), 5 species,
 // biased by 32 so that 32 + n_i - n_j never borrows.
