@@ -1,4 +1,4 @@
-// kernels_fcc.hip -- the sweep and pair-count kernels on the FCC lattice
+// kernels_fcc.hip -- the sweep kernel on the FCC lattice
 // (the lattice of the paper's quinary alloy and its L1_2 precipitates).
 //
 // Four sublattices per cubic cell at doubled offsets SUB[b]; 12/6/24
@@ -11,10 +11,12 @@
 // Partner choice: the partner of all trials of one (sweep, colour,
 // sub-colour) set -- its sublattice and the signs of the step on the two
 // axes where the sublattices differ -- is drawn once (the same draw on
-// every wave), so the partner's neighbour offsets are selected by a scalar
-// branch and every partner read of a wave is at one common offset.  A
-// trial's own draw is its acceptance word: one Philox call per cell serves
-// the cell's four sites.
+// every wave), so a scalar branch selects a trial specialised on it, which
+// reads only the cells its energy change needs (the symmetric difference of
+// the site's and the partner's shells), every read of a wave at one common
+// offset.  A trial's own draw is its acceptance word: one Philox call per
+// cell serves the cell's four sites.  (The FCC pair counts are in
+// pair_counts.hip.)
 #include "device_common.h"
 
 namespace smcx {
