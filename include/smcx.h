@@ -182,6 +182,19 @@ smcx_status smcx_set_schedule(smcx_ctx* ctx, const double* T_per_sweep, int32_t 
  * site each).  Asynchronous.  RANGE if the sweep counter would pass 2^32. */
 smcx_status smcx_sweep(smcx_ctx* ctx, int32_t n);
 
+/* n sweeps as smcx_sweep(n), recording after every sweep t (0-based) the
+ * pair counts N_m[p'][p] of the configuration (Eq. (SRO): the numerators of
+ * the Warren-Cowley parameters) in counts[((t*S + m)*K + p')*K + p] and its
+ * energy, E = 1/2 sum_m sum_{p',p} N_m[p'][p] V_m(p', p) (micro-eV, equal to
+ * the running energy), in E_ueV[t].  Either output may be NULL.  The counts
+ * stay on the device between sweeps (a device buffer of 24 KiB per sweep,
+ * at most 256 sweeps at a time, allocated and freed by the call) and are
+ * read back once per 256 sweeps: no host synchronisation per sweep.
+ * Returns when all n sweeps are done.  Errors: as smcx_sweep; HIP if the
+ * buffer cannot be allocated (sweeps already enqueued by the call stay
+ * done). */
+smcx_status smcx_sweep_observed(smcx_ctx* ctx, int32_t n, int64_t* E_ueV, uint64_t* counts);
+
 /* Running energy: the initial energy plus every accepted dE (micro-eV). */
 smcx_status smcx_energy(smcx_ctx* ctx, int64_t* E_ueV);
 

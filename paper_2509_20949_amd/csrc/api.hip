@@ -582,6 +582,57 @@ smcx_status smcx_sweep(smcx_ctx* c, int32_t n)
     return enqueue_sweeps(c, n);
 }
 
+smcx_status smcx_sweep_observed(smcx_ctx* c, int32_t n, int64_t* E, uint64_t* counts)
+{
+    if (!c) return fail_global(SMCX_E_INVALID, "ctx is NULL");
+    if (c->view) return fail(c, SMCX_E_STATE, "batch views are advanced by smcx_batch_run");
+    if (n < 0) return fail(c, SMCX_E_INVALID, "n = %d < 0", n);
+    if (c->sweeps + (uint64_t)n > 0xffffffffull) return fail(c, SMCX_E_RANGE, "sweep counter would pass 2^32");
+    if (c->phase != 0) return fail(c, SMCX_E_STATE, "a sweep stepped by smcx_slab_phase is unfinished");
+    if (n == 0) return SMCX_OK;
+    // Chunks of up to kChunk sweeps: each sweep's pair counts go to their own
+    // copy-slot block of one device buffer (kCountBytes per sweep), read back
+    // once per chunk.
+    constexpr int32_t kChunk = 256;
+    const int32_t chunk = n < kChunk ? n : kChunk;
+    unsigned long long* d_buf = nullptr;
+    smcx_status st = ctx_hip(c, hipMalloc(&d_buf, kCountBytes * (size_t)chunk), "hipMalloc(observed counts)");
+    if (st) return st;
+    std::vector<unsigned long long> h((size_t)kCountSlots * kCountWords * chunk);
+    const int K = c->K, S = c->S;
+    for (int32_t t0 = 0; t0 < n && !st; t0 += chunk) {
+        const int32_t m = n - t0 < chunk ? n - t0 : chunk;
+        st = ctx_hip(c, hipMemsetAsync(d_buf, 0, kCountBytes * (size_t)m, c->stream), "hipMemsetAsync");
+        for (int32_t t = 0; t < m && !st; ++t) {
+            st = enqueue_sweeps(c, 1);
+            if (!st)
+                st = ctx_hip(c, launch_pair_counts(c->h_lat.lattice, c->d_own, c->h_lat.L, K, S,
+                                                   d_buf + (size_t)t * kCountSlots * kCountWords, c->stream),
+                             "pair_counts launch");
+        }
+        if (!st)
+            st = ctx_hip(c, hipMemcpyAsync(h.data(), d_buf, kCountBytes * (size_t)m, hipMemcpyDeviceToHost, c->stream),
+                         "hipMemcpyAsync(observed counts)");
+        if (!st) st = ctx_hip(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+        for (int32_t t = 0; t < m && !st; ++t) {
+            unsigned long long sum[kCountWords];
+            count_sum(h.data() + (size_t)t * kCountSlots * kCountWords, sum);
+            int64_t twice = 0;
+            for (int q = 0; q < S; ++q)
+                for (int a = 0; a < K; ++a)
+                    for (int b = 0; b < K; ++b) {
+                        const unsigned long long v = sum[(q * kMaxK + a) * kMaxK + b];
+                        twice += (int64_t)v * c->epi[(q * K + a) * K + b];
+                        if (counts) counts[(((size_t)(t0 + t) * S + q) * K + a) * K + b] = v;
+                    }
+            if (E) E[t0 + t] = twice / 2;
+            if (t0 + t == n - 1) std::memcpy(c->counts, sum, sizeof(sum));
+        }
+    }
+    (void)hipFree(d_buf);
+    return st;
+}
+
 smcx_status smcx_energy(smcx_ctx* c, int64_t* E)
 {
     if (!c || !E) return fail(c, SMCX_E_INVALID, "NULL argument");

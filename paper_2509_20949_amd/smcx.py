@@ -62,6 +62,7 @@ def lib():
     _sig(L, "smcx_set_temperature", st, [vp, dbl])
     _sig(L, "smcx_set_schedule", st, [vp, _P(dbl), i32])
     _sig(L, "smcx_sweep", st, [vp, i32])
+    _sig(L, "smcx_sweep_observed", st, [vp, i32, _P(i64), _P(u64)])
     _sig(L, "smcx_energy", st, [vp, _P(i64)])
     _sig(L, "smcx_energy_recompute", st, [vp, _P(i64)])
     _sig(L, "smcx_sro", st, [vp, _P(dbl), _P(u64)])
@@ -191,6 +192,13 @@ def smcx_set_schedule(ctx, T_per_sweep):
 
 def smcx_sweep(ctx, n: int):
     _check(lib().smcx_sweep(ctx, int(n)), ctx)
+
+
+def smcx_sweep_observed(ctx, n: int, S: int, K: int):
+    E = np.zeros(int(n), np.int64)
+    counts = np.zeros((int(n), S, K, K), np.uint64)
+    _check(lib().smcx_sweep_observed(ctx, int(n), _ptr(E, C.c_int64), _ptr(counts, C.c_uint64)), ctx)
+    return E, counts
 
 
 def smcx_energy(ctx) -> int:
@@ -437,6 +445,10 @@ class Lattice:
 
     def set_schedule(self, T):
         smcx_set_schedule(self.ctx, T)
+
+    def sweep_observed(self, n):
+        """n sweeps; per sweep energy (n,) and pair counts (n, S, K, K)."""
+        return smcx_sweep_observed(self.ctx, n, self.S, self.K)
 
     def energy(self):
         return smcx_energy(self.ctx)
