@@ -439,8 +439,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: the path has no multi-GPU form in this build "
-              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the sweep path runs on a single GPU, and a run "
+              "across several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
