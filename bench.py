@@ -215,7 +215,7 @@ def slab_leg(args, smcx, W, sweeps=50):
             "value": job.N * sweeps / dt, "unit": "swaps/s",
             "kernel_only_value": job.N * sweeps / (kernel_ms / 1e3),
             "avg_launch_ms": kernel_ms / max(launches, 1), "energy_check_ok": ok,
-            "halo": "2 planes each side, exchanged with itself by device copies between phases"}
+            "halo": "2 planes each side, exchanged with itself between phases by one copy kernel per phase boundary"}
 
 
 def anneal_leg(args, smcx, W):

@@ -358,22 +358,50 @@ static smcx_status enqueue_phase(smcx_ctx* c, uint32_t s, int col, int groups)
 // them) run when colour bit 2 is 0 and may write plane -1; blocks with odd
 // index (the highest) run otherwise and may write plane Lz.  The two never
 // run in one phase, so the plane written back was not changed in place.
-static smcx_status slab_self_halo(smcx_ctx* c, int col, bool after)
+// A slab that is the whole lattice exchanges its halo planes with itself
+// (plane p of the buffer at b + p P: halos -2, -1 at p = 0, 1, own planes at
+// 2 .. Lz+1, halos Lz, Lz+1 at Lz+2, Lz+3).  After a colour phase the one
+// halo plane it may have written returns to its owner plane (phase with
+// colour bit 2 clear: halo -1 -> plane Lz-1; set: halo Lz -> plane 0);
+// before a phase the halos take the current wrapped planes (Lz-2, Lz-1 ->
+// halos -2, -1; 0, 1 -> halos Lz, Lz+1).  One kernel does both steps of a
+// phase boundary, element by element in that order (the copies touch the
+// same offset q of different planes only, so a thread's order is the
+// order of the copies).
+template <class T>
+__global__ void slab_exchange_kernel(T* __restrict__ b, size_t P, size_t Lz, int after, int before)
+{
+    const size_t n = P;   // elements per plane
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
+        if (after == 0) b[(Lz + 1) * P + q] = b[P + q];
+        else if (after == 1) b[2 * P + q] = b[(Lz + 2) * P + q];
+        if (before) {
+            b[q] = b[Lz * P + q];
+            b[P + q] = b[(Lz + 1) * P + q];
+            b[(Lz + 2) * P + q] = b[2 * P + q];
+            b[(Lz + 3) * P + q] = b[3 * P + q];
+        }
+    }
+}
+
+// after: -1 (none), or the colour of the phase that just ran; before: the
+// next phase follows.
+static smcx_status slab_exchange(smcx_ctx* c, int after_col, bool before)
 {
     const size_t P = 2 * (size_t)c->h_lat.L[0] * c->h_lat.L[1];   // bytes per plane
     const size_t Lz = (size_t)c->h_lat.L[2];
-    uint8_t* b = c->d_species;                                     // plane p at b + p P
-    hipError_t e = hipSuccess;
-    if (!after) {
-        e = hipMemcpyAsync(b, b + Lz * P, 2 * P, hipMemcpyDeviceToDevice, c->stream);   // planes Lz-2, Lz-1
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(b + (Lz + 2) * P, b + 2 * P, 2 * P, hipMemcpyDeviceToDevice, c->stream);   // 0, 1
-    } else if (((col >> 2) & 1) == 0) {
-        e = hipMemcpyAsync(b + (Lz + 1) * P, b + P, P, hipMemcpyDeviceToDevice, c->stream);   // plane -1 -> Lz-1
+    uint8_t* b = c->d_species;
+    const int after = after_col < 0 ? -1 : ((after_col >> 2) & 1);
+    const dim3 block(256);
+    if (P % 16 == 0 && (uintptr_t)b % 16 == 0) {
+        const size_t n = P / 16;
+        const dim3 grid((unsigned)std::min<size_t>((n + 255) / 256, 4096));
+        hipLaunchKernelGGL(slab_exchange_kernel<uint4>, grid, block, 0, c->stream, (uint4*)b, n, Lz, after, (int)before);
     } else {
-        e = hipMemcpyAsync(b + 2 * P, b + (Lz + 2) * P, P, hipMemcpyDeviceToDevice, c->stream);   // plane Lz -> 0
+        const dim3 grid((unsigned)std::min<size_t>((P + 255) / 256, 4096));
+        hipLaunchKernelGGL(slab_exchange_kernel<uint8_t>, grid, block, 0, c->stream, b, P, Lz, after, (int)before);
     }
-    return ctx_hip(c, e, "hipMemcpyAsync(halo)");
+    return ctx_hip(c, hipGetLastError(), "slab_exchange_kernel");
 }
 
 smcx_status enqueue_sweeps(smcx_ctx* c, int32_t n)
@@ -382,9 +410,9 @@ smcx_status enqueue_sweeps(smcx_ctx* c, int32_t n)
     for (int32_t k = 0; k < n; ++k) {
         const uint32_t s = (uint32_t)(c->sweeps + (uint64_t)k);
         for (int col = 0; col < 8; ++col) {
-            smcx_status st = c->slab ? slab_self_halo(c, col, false) : SMCX_OK;
+            smcx_status st = c->slab && k == 0 && col == 0 ? slab_exchange(c, -1, true) : SMCX_OK;
             if (!st) st = enqueue_phase(c, s, col, groups);
-            if (!st && c->slab) st = slab_self_halo(c, col, true);
+            if (!st && c->slab) st = slab_exchange(c, col, !(k == n - 1 && col == 7));
             if (st) return st;
         }
     }
