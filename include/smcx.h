@@ -190,9 +190,9 @@ smcx_status smcx_sweep(smcx_ctx* ctx, int32_t n);
  * stay on the device between sweeps (a device buffer of 24 KiB per sweep,
  * at most 256 sweeps at a time, allocated and freed by the call) and are
  * read back once per 256 sweeps: no host synchronisation per sweep.
- * Returns when all n sweeps are done.  Errors: as smcx_sweep; HIP if the
- * buffer cannot be allocated (sweeps already enqueued by the call stay
- * done). */
+ * Returns when all n sweeps are done.  Errors: as smcx_sweep; NOMEM if the
+ * buffer cannot be allocated, DEVICE if a HIP call fails (sweeps already
+ * enqueued by the call stay done). */
 smcx_status smcx_sweep_observed(smcx_ctx* ctx, int32_t n, int64_t* E_ueV, uint64_t* counts);
 
 /* Running energy: the initial energy plus every accepted dE (micro-eV). */
