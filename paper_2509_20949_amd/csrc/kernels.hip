@@ -573,11 +573,67 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
                 }
             }
         }
+    } else if (plane32) {
+        // The x-range crosses the periodic boundary: the rows and LDS
+        // positions of the fast path, but each lane loads its two cells
+        // separately, one 16-bit load each at its own wrapped x, so that a
+        // pair may straddle the boundary.  The plane's byte remainder
+        // (zb & 2) goes into the scalar offset of both loads.
+        const int c8 = lane & 7, lr = lane >> 3;
+        const int lx0 = 2 * c8 - 2;
+        const int lxa = lx0 <= wx + 1 ? lx0 : -2;   // cells the lane loads
+        // gx0 + lxa + 1 <= (Lx - 1) + (wx + 2) < 2 Lx, as wx + 2 <= Lx
+        const uint32_t gxa = (uint32_t)wrap_add(gx0 + lxa, Lx), gxb = (uint32_t)wrap_add(gx0 + lxa + 1, Lx);
+        uint32_t oa[2], ob[2];
+        int cl[2];
+        bool mc0[2], mc1[2], mb0[2], mb1[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int ly = lr - 2 + 8 * h;
+            const uint32_t row = (uint32_t)wrap_add(gy0 + min(ly, wy + 1), Ly) * (uint32_t)Lx;
+            oa[h] = 2u * (row + gxa);
+            ob[h] = 2u * (row + gxb);
+            cl[h] = (ly + 1) * kP + (lx0 + 1);
+            mc0[h] = ly >= -1 && c8 >= 1;
+            mc1[h] = ly >= -1;
+            mb0[h] = ly <= 12;
+            mb1[h] = ly <= 12 && c8 <= 6;
+        }
+#pragma unroll
+        for (int it0 = 0; it0 < 32; it0 += kStageBatch) {
+            uint32_t v[kStageBatch];
+#pragma unroll
+            for (int u = 0; u < kStageBatch; ++u) {
+                const int it = it0 + u, h = it & 1, lz = (it >> 1) - 2;
+                const uint64_t zb = plane_bytes * (uint32_t)zplane(min(lz, wz + 1));
+                const uint64_t base = zb & ~(uint64_t)3;
+                const __amdgpu_buffer_rsrc_t r = byte_rsrc(g + base, buf_bytes - base);
+                const int so = (int)((uint32_t)zb & 2u);
+                const uint32_t a = __builtin_amdgcn_raw_buffer_load_b16(r, (int)oa[h], so, 0);
+                const uint32_t b = __builtin_amdgcn_raw_buffer_load_b16(r, (int)ob[h], so, 0);
+                v[u] = __builtin_amdgcn_perm(code_hi, code_lo, a | b << 16);
+            }
+#pragma unroll
+            for (int u = 0; u < kStageBatch; ++u) {
+                const int it = it0 + u, h = it & 1, lz = (it >> 1) - 2;
+                uint8_t* p = lat + cl[h] + (lz + 1) * kPP;
+                uint8_t* q = p + (kArr + kPP + kP + 1);
+                const uint32_t w8 = v[u] >> 8;
+                if (lz >= -1) {
+                    if (mc0[h]) p[0] = (uint8_t)v[u];
+                    if (mc1[h]) p[1] = (uint8_t)(v[u] >> 16);
+                }
+                if (lz <= 12) {
+                    if (mb0[h]) q[0] = (uint8_t)w8;
+                    if (mb1[h]) q[1] = (uint8_t)(w8 >> 16);
+                }
+            }
+        }
     } else {
-        // a periodic wrap along x: one cell (two bytes) per lane, rows
-        // r = (lane >> 4) + 4 it; all 64 loads of a lane are issued before
-        // any LDS write, as on the fast path (lanes and rows outside the
-        // halo load a clamped in-range cell)
+        // planes of 2 GiB or more: one cell (two bytes) per lane, rows
+        // r = (lane >> 4) + 4 it, 64-bit addresses; all 64 loads of a lane
+        // are issued before any LDS write, as on the fast path (lanes and
+        // rows outside the halo load a clamped in-range cell)
         const int lx = (lane & 15) - 2;
         const bool okx = lx <= wx + 1;
         const int gx = wrap_add(gx0 + (okx ? lx : -2), Lx);
@@ -732,8 +788,11 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
     // instruction: lane row lys = lane >> 4 takes rows ly = 4 yg + lys - 1
     // (yg = 0..3) of each plane lz = -1..w.  Per lane, the in-plane byte
     // offsets and LDS positions of its four rows are set up once; lanes past
-    // the box read a clamped in-image cell and store nothing.
-    if (plane32 && gx0 >= 1 && gx0 + wx < Lx) {
+    // the box read a clamped in-image cell and store nothing.  A lane's x is
+    // wrapped once here, so blocks whose x-range crosses the periodic
+    // boundary take this path too (same-colour blocks are as far apart
+    // across the boundary as anywhere else, nb being even).
+    if (plane32) {
         const int lx = (lane & 15) - 1, lys = lane >> 4;
         const int lxc = min(lx, wx);
         uint32_t yo[4];
@@ -744,7 +803,7 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
             const int ly = 4 * yg + lys - 1, lyc = min(ly, wy);
             ok[yg] = lx <= wx && ly <= wy;
             const uint32_t gy = (uint32_t)wrap_add(gy0 + lyc, Ly);
-            yo[yg] = 2u * (gy * (uint32_t)Lx + (uint32_t)(gx0 + lxc));
+            yo[yg] = 2u * (gy * (uint32_t)Lx + (uint32_t)wrap_add(gx0 + lxc, Lx));
             cw[yg] = (lyc + 1) * kP + (lxc + 1);   // corner(lxc, lyc, -1), less a plane
         }
 #pragma unroll
@@ -763,9 +822,9 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
                 if (ok[yg]) bstore16(r, yo[yg], (e[yg] >> 5) & 0x0707u);
         }
     } else {
-        // a periodic wrap along x: one cell (two bytes) per lane, rows
-        // r = (lane >> 4) + 4 it; the LDS reads of 8 rows are issued
-        // together (rows and cells outside the boxes read clamped in-image
+        // planes of 2 GiB or more: one cell (two bytes) per lane, rows
+        // r = (lane >> 4) + 4 it, 64-bit addresses; the LDS reads of 8 rows
+        // are issued together (rows and cells outside the boxes read clamped in-image
         // bytes and store nothing)
         const int lx = (lane & 15) - 1;
         const bool okx = lx <= wx;
