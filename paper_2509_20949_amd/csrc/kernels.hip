@@ -776,8 +776,8 @@ void sweep_phase_kernel(const DevLattice* __restrict__ lats, const WorkItem* __r
 
     // ---- write back ----
     // A trial changes only corner cells 0..w and body cells -1..w-1 of the
-    // block (its sites and their first neighbours).  Fast path (no periodic
-    // wrap along x): every cell of the box -1..w on each axis is written
+    // block (its sites and their first neighbours).  Row path (planes under
+    // 2 GiB): every cell of the box -1..w on each axis is written
     // whole (corner and body byte, one 16-bit store), the cells no trial
     // could change with the value staged from them.  That is the value they
     // still hold: no block of the same colour changes them (same-colour
