@@ -635,7 +635,7 @@ static hipError_t launch_pc(const uint8_t* species, const int32_t L[3], int K, i
     // enough waves for the chip (4096) and for the counters' range, at least
     // 4 tasks each where the lattice is small (each wave ends in a flush;
     // measured per synchronous call on 64^3 BCC: 32 us at 4 tasks per wave,
-    // 35 us at 8, 42 us at 16)
+    // 35 us at 8, 42 us at 16; 2 and 1 tasks measured the same as 4)
     uint64_t waves = (tasks + pc::kMaxTasksPerWave - 1) / pc::kMaxTasksPerWave;
     waves = std::max<uint64_t>(waves, std::min<uint64_t>((tasks + 3) / 4, 4096));
     const uint64_t groups = (waves + waves_per_group - 1) / waves_per_group;
